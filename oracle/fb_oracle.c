@@ -1,0 +1,425 @@
+/*
+ * FastBlend CPU oracle -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.
+ *
+ * A plain, slow, deliberately unoptimised C implementation of what the
+ * FastBlend hot path computes (Duan et al., "FastBlend: a Powerful Model-Free
+ * Toolkit Making Video Stylization Easier", arXiv 2311.09265).  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load
+ * it.  It shares no code, header, table or helper with the GPU library.
+ *
+ * Every function cites the passage of the paper it follows.  Where the paper
+ * is silent, the reading taken is stated at the function (and listed with all
+ * other readings in the design notes of the repository):
+ *
+ *   coordinates   F(r,c) = (row, col) of the source patch centre matched to
+ *                 target pixel (r,c); the paper's (x,y) is read as (row, col).
+ *   sampling      pixels outside an image are read clamp-to-edge.
+ *   pyramid       2x2 box filter with round-half-up, ceil(size/2) per level.
+ *   upsampling    F_l(r,c) = clamp(2 F_{l+1}(r/2, c/2) + (r&1, c&1)).
+ *   update        Jacobi: every pixel reads only the previous iteration's
+ *                 field; each pixel tries its candidates in a fixed order
+ *                 against its own running best with strict '<'.
+ *   random search symmetric integer offsets in [-rho, rho]^2 around the
+ *                 running best, rho = R >> m (R = max(h,w)) while rho >= 1,
+ *                 drawn from Philox4x32-10 (Salmon et al., SC'11) keyed by
+ *                 the seed, counter = (pixel, pair id, level<<16 | iter, m>>2);
+ *                 word m&3 gives (row 16 bits low, col 16 bits high); a
+ *                 16-bit draw u maps to [0, n) as (u * n) >> 16.
+ *   remap border  neighbours outside the image are skipped and the sum is
+ *                 divided by the number that remain (the patch-overlap
+ *                 average of Section 3.3).
+ *   window ends   the blending window is truncated to [0, N-1] and divided by
+ *                 its length; the j == i term is the style frame itself.
+ *
+ * Images are uint8 [h][w][3] row-major; NNFs are int32 [h][w][2] (row, col);
+ * energies are uint32 [h][w].  Floating-point outputs are fp64.
+ * Within one call the work over rows is spread with OpenMP; every pixel of a
+ * Jacobi iteration is independent, so this does not change any result.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#define FBO_OK 0
+#define FBO_E_INVALID -1
+#define FBO_E_ALLOC -4
+
+static int clampi(int x, int lo, int hi) { return x < lo ? lo : (x > hi ? hi : x); }
+static int maxi(int a, int b) { return a > b ? a : b; }
+
+void fbo_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+int fbo_get_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from its published definition (Salmon, Moraes, Dror, Shaw, */
+/* "Parallel Random Numbers: As Easy as 1, 2, 3", SC'11): 10 rounds of       */
+/* (x0,x1,x2,x3) -> (hi(M1 x2)^x1^k0, lo(M1 x2), hi(M0 x0)^x3^k1, lo(M0 x0)) */
+/* with the key bumped by the Weyl constants between rounds.                 */
+/* The paper draws its initial field and search offsets at random (Alg. 1,   */
+/* Section 3.2) without naming a generator; this one is counter based so a   */
+/* draw depends only on what it is for, never on evaluation order.           */
+/* ------------------------------------------------------------------------ */
+void fbo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* a 16-bit uniform draw mapped to [0, n), n <= 65536 */
+uint32_t fbo_uniform16(uint32_t u16, uint32_t n) { return (u16 * n) >> 16; }
+
+static void draw_words(uint64_t seed, uint32_t pixel, uint32_t pair_id, uint32_t level,
+                       uint32_t iter, uint32_t call, uint32_t out[4])
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t ctr[4] = { pixel, pair_id, (level << 16) | (iter & 0xFFFFu), call };
+    fbo_philox4x32_10(ctr, key, out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Image pyramid (Alg. 1, "resize images S, T" per pyramid level).           */
+/* Reading: 2x2 box filter, round half up, output ceil(h/2) x ceil(w/2),     */
+/* input reads clamped to the image.                                         */
+/* ------------------------------------------------------------------------ */
+void fbo_downsample(const uint8_t *in, int h, int w, uint8_t *out)
+{
+    int ho = (h + 1) / 2, wo = (w + 1) / 2;
+    for (int r = 0; r < ho; ++r)
+        for (int c = 0; c < wo; ++c)
+            for (int ch = 0; ch < 3; ++ch) {
+                int s = 0;
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) {
+                        int rr = clampi(2 * r + a, 0, h - 1), cc = clampi(2 * c + b, 0, w - 1);
+                        s += in[(rr * w + cc) * 3 + ch];
+                    }
+                out[(r * wo + c) * 3 + ch] = (uint8_t)((s + 2) >> 2);
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Base loss, Eq. (1): squared L2 distance between the (2p+1)x(2p+1)x3       */
+/* patches S[u] and T[v].  Integer arithmetic on uint8 pixels, so exact.     */
+/* ------------------------------------------------------------------------ */
+uint32_t fbo_patch_ssd(const uint8_t *S, const uint8_t *T, int h, int w, int p,
+                       int ur, int uc, int vr, int vc)
+{
+    uint32_t acc = 0;
+    for (int dr = -p; dr <= p; ++dr)
+        for (int dc = -p; dc <= p; ++dc) {
+            const uint8_t *s = S + 3 * (clampi(ur + dr, 0, h - 1) * w + clampi(uc + dc, 0, w - 1));
+            const uint8_t *t = T + 3 * (clampi(vr + dr, 0, h - 1) * w + clampi(vc + dc, 0, w - 1));
+            for (int ch = 0; ch < 3; ++ch) {
+                int d = (int)s[ch] - (int)t[ch];
+                acc += (uint32_t)(d * d);
+            }
+        }
+    return acc;
+}
+
+/* E(v) = L(S, T, F)_v for every target pixel (Alg. 1, "initialize error matrix"). */
+void fbo_energy(const uint8_t *S, const uint8_t *T, int h, int w, int p,
+                const int32_t *F, uint32_t *E)
+{
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < h; ++r)
+        for (int c = 0; c < w; ++c) {
+            const int32_t *f = F + 2 * (r * w + c);
+            E[r * w + c] = fbo_patch_ssd(S, T, h, w, p, f[0], f[1], r, c);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random initialisation of F (Alg. 1, first step), taken at the coarsest    */
+/* level: F(v) is a uniformly drawn source position; E is its loss.          */
+/* ------------------------------------------------------------------------ */
+void fbo_nnf_init_random(const uint8_t *S, const uint8_t *T, int h, int w, int p,
+                         int level, uint64_t seed, uint32_t pair_id, int32_t *F, uint32_t *E)
+{
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < h; ++r)
+        for (int c = 0; c < w; ++c) {
+            uint32_t x[4];
+            draw_words(seed, (uint32_t)(r * w + c), pair_id, (uint32_t)level, 0xFFFFu, 0u, x);
+            int fr = (int)fbo_uniform16(x[0] & 0xFFFFu, (uint32_t)h);
+            int fc = (int)fbo_uniform16(x[0] >> 16, (uint32_t)w);
+            F[2 * (r * w + c)] = fr;
+            F[2 * (r * w + c) + 1] = fc;
+            E[r * w + c] = fbo_patch_ssd(S, T, h, w, p, fr, fc, r, c);
+        }
+}
+
+/* Initialisation from a given offset field: F(v) = clamp(v + off(v)). */
+void fbo_nnf_init_offsets(const uint8_t *S, const uint8_t *T, int h, int w, int p,
+                          const int32_t *off, int32_t *F, uint32_t *E)
+{
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < h; ++r)
+        for (int c = 0; c < w; ++c) {
+            int fr = clampi(r + off[2 * (r * w + c)], 0, h - 1);
+            int fc = clampi(c + off[2 * (r * w + c) + 1], 0, w - 1);
+            F[2 * (r * w + c)] = fr;
+            F[2 * (r * w + c) + 1] = fc;
+            E[r * w + c] = fbo_patch_ssd(S, T, h, w, p, fr, fc, r, c);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Upsampling F to the next finer level (Alg. 1, "upsample F"), followed by  */
+/* recomputing E.  Reading: nearest-neighbour on the offsets, i.e. a coarse   */
+/* match (R, C) becomes (2R + (r&1), 2C + (c&1)), clamped into the image.    */
+/* (hc, wc) = (ceil(h/2), ceil(w/2)) is the coarse size.                     */
+/* ------------------------------------------------------------------------ */
+void fbo_nnf_upsample(const int32_t *Fc, int hc, int wc, const uint8_t *S, const uint8_t *T,
+                      int h, int w, int p, int32_t *F, uint32_t *E)
+{
+    (void)hc;
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < h; ++r)
+        for (int c = 0; c < w; ++c) {
+            const int32_t *f = Fc + 2 * ((r >> 1) * wc + (c >> 1));
+            int fr = clampi(2 * f[0] + (r & 1), 0, h - 1);
+            int fc = clampi(2 * f[1] + (c & 1), 0, w - 1);
+            F[2 * (r * w + c)] = fr;
+            F[2 * (r * w + c) + 1] = fc;
+            E[r * w + c] = fbo_patch_ssd(S, T, h, w, p, fr, fc, r, c);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One PatchMatch iteration (Alg. 1 inner loop; Section 3.2):                 */
+/*  - propagation: F'(v) = F(v + d) - d for d = (-1,0), (1,0), (0,-1), (0,1)  */
+/*    in that order, skipped where v + d is outside the image;               */
+/*  - random search: F'(v) = best(v) + delta, delta uniform in [-rho, rho]^2, */
+/*    rho = R, R/2, ..., 1 (R = max(h, w)), "declining exponentially";        */
+/*  - a candidate replaces the running best only if its loss is strictly     */
+/*    lower (the F(E' < E) <- F' update).                                    */
+/* Every position is updated independently from the previous iteration's     */
+/* field (Fo, Eo) -- the concurrent update the paper adopts instead of       */
+/* Barnes et al.'s scan order.  Candidates are clamped into the image.       */
+/* ------------------------------------------------------------------------ */
+void fbo_pm_iteration(const uint8_t *S, const uint8_t *T, int h, int w, int p, int level,
+                      int iter, uint64_t seed, uint32_t pair_id,
+                      const int32_t *Fo, const uint32_t *Eo, int32_t *Fn, uint32_t *En)
+{
+    static const int D[4][2] = { { -1, 0 }, { 1, 0 }, { 0, -1 }, { 0, 1 } };
+    const int R = maxi(h, w);
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < h; ++r)
+        for (int c = 0; c < w; ++c) {
+            int br = Fo[2 * (r * w + c)], bc = Fo[2 * (r * w + c) + 1];
+            uint32_t be = Eo[r * w + c];
+            for (int k = 0; k < 4; ++k) {
+                int qr = r + D[k][0], qc = c + D[k][1];
+                if (qr < 0 || qr >= h || qc < 0 || qc >= w) continue;
+                int cr = clampi(Fo[2 * (qr * w + qc)] - D[k][0], 0, h - 1);
+                int cc = clampi(Fo[2 * (qr * w + qc) + 1] - D[k][1], 0, w - 1);
+                uint32_t e = fbo_patch_ssd(S, T, h, w, p, cr, cc, r, c);
+                if (e < be) { br = cr; bc = cc; be = e; }
+            }
+            uint32_t x[4] = { 0, 0, 0, 0 };
+            for (int m = 0; (R >> m) >= 1; ++m) {
+                int rho = R >> m;
+                if ((m & 3) == 0)
+                    draw_words(seed, (uint32_t)(r * w + c), pair_id, (uint32_t)level,
+                               (uint32_t)iter, (uint32_t)(m >> 2), x);
+                uint32_t word = x[m & 3];
+                int dr = (int)fbo_uniform16(word & 0xFFFFu, (uint32_t)(2 * rho + 1)) - rho;
+                int dc = (int)fbo_uniform16(word >> 16, (uint32_t)(2 * rho + 1)) - rho;
+                int cr = clampi(br + dr, 0, h - 1), cc = clampi(bc + dc, 0, w - 1);
+                uint32_t e = fbo_patch_ssd(S, T, h, w, p, cr, cc, r, c);
+                if (e < be) { br = cr; bc = cc; be = e; }
+            }
+            Fn[2 * (r * w + c)] = br;
+            Fn[2 * (r * w + c) + 1] = bc;
+            En[r * w + c] = be;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole coarse-to-fine estimation NNF(S, T) (Alg. 1): pyramid of `levels`   */
+/* levels, random (or offset-seeded) initialisation at the coarsest level,   */
+/* `iters` iterations at every level, upsampling between levels.             */
+/* `seed_off` (optional) is an int32 offset field at the coarsest level.     */
+/* ------------------------------------------------------------------------ */
+int fbo_patchmatch(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, int levels,
+                   int iters, uint64_t seed, uint32_t pair_id, const int32_t *seed_off,
+                   int32_t *F, uint32_t *E)
+{
+    if (levels < 1 || levels > 16 || h < 1 || w < 1 || p < 0) return FBO_E_INVALID;
+    int hs[16], ws[16];
+    const uint8_t *Sl[16], *Tl[16];
+    uint8_t *own[32];
+    int n_own = 0;
+    hs[0] = h; ws[0] = w; Sl[0] = S0; Tl[0] = T0;
+    for (int l = 1; l < levels; ++l) {
+        hs[l] = (hs[l - 1] + 1) / 2;
+        ws[l] = (ws[l - 1] + 1) / 2;
+        uint8_t *s = (uint8_t *)malloc((size_t)hs[l] * ws[l] * 3);
+        uint8_t *t = (uint8_t *)malloc((size_t)hs[l] * ws[l] * 3);
+        if (!s || !t) { free(s); free(t); for (int i = 0; i < n_own; ++i) free(own[i]); return FBO_E_ALLOC; }
+        fbo_downsample(Sl[l - 1], hs[l - 1], ws[l - 1], s);
+        fbo_downsample(Tl[l - 1], hs[l - 1], ws[l - 1], t);
+        own[n_own++] = s; own[n_own++] = t;
+        Sl[l] = s; Tl[l] = t;
+    }
+    size_t n0 = (size_t)h * w;
+    int32_t *Fa = (int32_t *)malloc(n0 * 2 * sizeof(int32_t));
+    int32_t *Fb = (int32_t *)malloc(n0 * 2 * sizeof(int32_t));
+    uint32_t *Ea = (uint32_t *)malloc(n0 * sizeof(uint32_t));
+    uint32_t *Eb = (uint32_t *)malloc(n0 * sizeof(uint32_t));
+    int status = FBO_OK;
+    if (!Fa || !Fb || !Ea || !Eb) { status = FBO_E_ALLOC; goto done; }
+    for (int l = levels - 1; l >= 0; --l) {
+        int hl = hs[l], wl = ws[l];
+        if (l == levels - 1) {
+            if (seed_off) fbo_nnf_init_offsets(Sl[l], Tl[l], hl, wl, p, seed_off, Fa, Ea);
+            else fbo_nnf_init_random(Sl[l], Tl[l], hl, wl, p, l, seed, pair_id, Fa, Ea);
+        } else {
+            /* the previous level's result sits in Fa; upsample into Fb, then swap */
+            fbo_nnf_upsample(Fa, hs[l + 1], ws[l + 1], Sl[l], Tl[l], hl, wl, p, Fb, Eb);
+            int32_t *tf = Fa; Fa = Fb; Fb = tf;
+            uint32_t *te = Ea; Ea = Eb; Eb = te;
+        }
+        for (int it = 0; it < iters; ++it) {
+            fbo_pm_iteration(Sl[l], Tl[l], hl, wl, p, l, it, seed, pair_id, Fa, Ea, Fb, Eb);
+            int32_t *tf = Fa; Fa = Fb; Fb = tf;
+            uint32_t *te = Ea; Ea = Eb; Eb = te;
+        }
+    }
+    memcpy(F, Fa, n0 * 2 * sizeof(int32_t));
+    memcpy(E, Ea, n0 * sizeof(uint32_t));
+done:
+    free(Fa); free(Fb); free(Ea); free(Eb);
+    for (int i = 0; i < n_own; ++i) free(own[i]);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Memory-efficient remapping (Alg. 2): T^(v) is the average, over the       */
+/* offsets d in [-p,p]^2, of S(F(v + d) - d).  Reading at the border: terms  */
+/* whose v + d lies outside the image are left out and the sum is divided by */
+/* how many remain -- the "average at the overlapping parts" definition in   */
+/* Section 3.3; source reads are clamped.  Output in [0, 1] (pixels / 255).  */
+/* ------------------------------------------------------------------------ */
+void fbo_remap(const uint8_t *style, const int32_t *F, int h, int w, int p, double *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < h; ++r)
+        for (int c = 0; c < w; ++c) {
+            long sum[3] = { 0, 0, 0 };
+            int cnt = 0;
+            for (int dr = -p; dr <= p; ++dr)
+                for (int dc = -p; dc <= p; ++dc) {
+                    int qr = r + dr, qc = c + dc;
+                    if (qr < 0 || qr >= h || qc < 0 || qc >= w) continue;
+                    int sr = clampi(F[2 * (qr * w + qc)] - dr, 0, h - 1);
+                    int sc = clampi(F[2 * (qr * w + qc) + 1] - dc, 0, w - 1);
+                    for (int ch = 0; ch < 3; ++ch) sum[ch] += style[(sr * w + sc) * 3 + ch];
+                    ++cnt;
+                }
+            for (int ch = 0; ch < 3; ++ch)
+                out[(r * w + c) * 3 + ch] = (double)sum[ch] / (255.0 * (double)cnt);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sliding-window blending, Eq. (2), balanced mode with the guide-only loss: */
+/* out_i = mean over j in [max(0,i-M), min(N-1,i+M)] of (S_j -> S_i), where  */
+/* S_j -> S_i remaps style frame j with NNF(G_j, G_i) (pair id j*N + i) and  */
+/* the j == i term is S_i itself.  Sum in ascending j.                       */
+/* ------------------------------------------------------------------------ */
+int fbo_blend_window(const uint8_t *guides, const uint8_t *styles, int N, int h, int w, int M,
+                     int p, int levels, int iters, uint64_t seed, double *out)
+{
+    size_t fpix = (size_t)h * w;
+    int32_t *F = (int32_t *)malloc(fpix * 2 * sizeof(int32_t));
+    uint32_t *E = (uint32_t *)malloc(fpix * sizeof(uint32_t));
+    double *tmp = (double *)malloc(fpix * 3 * sizeof(double));
+    int status = FBO_OK;
+    if (!F || !E || !tmp) { status = FBO_E_ALLOC; goto done; }
+    for (int i = 0; i < N; ++i) {
+        int lo = maxi(0, i - M), hi = (i + M < N - 1) ? i + M : N - 1;
+        double *acc = out + (size_t)i * fpix * 3;
+        for (size_t k = 0; k < fpix * 3; ++k) acc[k] = 0.0;
+        for (int j = lo; j <= hi; ++j) {
+            if (j == i) {
+                for (size_t k = 0; k < fpix * 3; ++k) acc[k] += styles[(size_t)i * fpix * 3 + k] / 255.0;
+                continue;
+            }
+            status = fbo_patchmatch(guides + (size_t)j * fpix * 3, guides + (size_t)i * fpix * 3,
+                                    h, w, p, levels, iters, seed, (uint32_t)(j * N + i), NULL, F, E);
+            if (status) goto done;
+            fbo_remap(styles + (size_t)j * fpix * 3, F, h, w, p, tmp);
+            for (size_t k = 0; k < fpix * 3; ++k) acc[k] += tmp[k];
+        }
+        for (size_t k = 0; k < fpix * 3; ++k) acc[k] /= (double)(hi - lo + 1);
+    }
+done:
+    free(F); free(E); free(tmp);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Keyframe interpolation, Eq. (9): for l < i < r (l, r the bracketing keys) */
+/* out_i = (r-i)/(r-l) (S_l -> S_i) + (i-l)/(r-l) (S_r -> S_i); keyframes    */
+/* are passed through unchanged (Section 3.5).  Reading for frames before    */
+/* the first or after the last key: the single nearest key, weight 1.        */
+/* keys: sorted, unique, n_keys >= 1; key_styles[k] belongs to keys[k].      */
+/* ------------------------------------------------------------------------ */
+int fbo_interpolate(const uint8_t *guides, int N, int h, int w, const int32_t *keys,
+                    const uint8_t *key_styles, int n_keys, int p, int levels, int iters,
+                    uint64_t seed, double *out)
+{
+    size_t fpix = (size_t)h * w;
+    int32_t *F = (int32_t *)malloc(fpix * 2 * sizeof(int32_t));
+    uint32_t *E = (uint32_t *)malloc(fpix * sizeof(uint32_t));
+    double *tmp = (double *)malloc(fpix * 3 * sizeof(double));
+    int status = FBO_OK;
+    if (!F || !E || !tmp) { status = FBO_E_ALLOC; goto done; }
+    for (int i = 0; i < N; ++i) {
+        double *o = out + (size_t)i * fpix * 3;
+        int kl = -1, kr = -1, ki = -1;
+        for (int k = 0; k < n_keys; ++k) {
+            if (keys[k] == i) ki = k;
+            if (keys[k] < i) kl = k;
+            if (keys[k] > i && kr < 0) kr = k;
+        }
+        if (ki >= 0) {
+            for (size_t k = 0; k < fpix * 3; ++k) o[k] = key_styles[(size_t)ki * fpix * 3 + k] / 255.0;
+            continue;
+        }
+        for (size_t k = 0; k < fpix * 3; ++k) o[k] = 0.0;
+        int sides[2] = { kl, kr };
+        for (int s = 0; s < 2; ++s) {
+            int k = sides[s];
+            if (k < 0) continue;
+            double wgt = 1.0;
+            if (kl >= 0 && kr >= 0) {
+                int l = keys[kl], r = keys[kr];
+                wgt = (s == 0) ? (double)(r - i) / (double)(r - l) : (double)(i - l) / (double)(r - l);
+            }
+            status = fbo_patchmatch(guides + (size_t)keys[k] * fpix * 3, guides + (size_t)i * fpix * 3,
+                                    h, w, p, levels, iters, seed, (uint32_t)(keys[k] * N + i), NULL, F, E);
+            if (status) goto done;
+            fbo_remap(key_styles + (size_t)k * fpix * 3, F, h, w, p, tmp);
+            for (size_t q = 0; q < fpix * 3; ++q) o[q] += wgt * tmp[q];
+        }
+    }
+done:
+    free(F); free(E); free(tmp);
+    return status;
+}
