@@ -1,0 +1,185 @@
+/*
+ * fastblend.h -- C ABI of the FastBlend hot path on AMD MI355X (gfx950).
+ *
+ * FastBlend (Duan et al., arXiv 2311.09265) removes flicker from a stylised
+ * video by estimating nearest-neighbour fields (NNFs) between guide frames
+ * with PatchMatch (Section 3.2, Algorithm 1), remapping style frames through
+ * them (Section 3.3, Algorithm 2) and averaging the remapped frames over a
+ * sliding window (Section 3.4, Eq. 2), or combining two remapped keyframes
+ * (Section 3.5, Eq. 9).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Images are uint8 RGB, row-major, HWC, contiguous: [h][w][3] (a video is
+ *   [n][h][w][3]).  All pixel, field and output pointers are DEVICE pointers
+ *   owned by the caller; the library never frees or retains them after the
+ *   call's work has run.  Host pointers are marked (host).
+ * - An NNF is int32 [h][w][2]: F(r, c) = (row, col) of the source patch
+ *   centre matched to target pixel (r, c) (the paper's F(x, y) = (x', y'),
+ *   read as row, column).  Energies are uint32 [h][w]: the integer patch
+ *   loss of Eq. 1 for each match.
+ * - Source and target of one NNF have the same h x w (Section 3.2).
+ * - Pyramid level l has size ceil(h / 2^l) x ceil(w / 2^l).
+ * - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL = the
+ *   null stream) and the call returns without waiting, except where noted.
+ * - Every call validates its arguments on the host first and returns
+ *   FB_E_INVALID / FB_E_SHAPE / FB_E_UNSUPPORTED without enqueueing anything.
+ *   A HIP runtime error returns FB_E_HIP.  After a non-OK status the outputs
+ *   are undefined.  fb_last_error() gives a message for the calling thread.
+ * - Results are bit-identical for any batch composition, launch shape or
+ *   graph replay: the random draws of a pixel depend only on (seed, pair id,
+ *   level, iteration, pixel), never on where the pair sits in a batch.
+ * - One fb_ctx may be used by one host thread at a time.
+ */
+#ifndef FASTBLEND_H
+#define FASTBLEND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FB_OK = 0,
+    FB_E_INVALID = -1,     /* null pointer, non-positive size, bad level, ... */
+    FB_E_SHAPE = -2,       /* sizes that do not fit together                  */
+    FB_E_UNSUPPORTED = -3, /* valid but not implemented (e.g. patch radius)   */
+    FB_E_ALLOC = -4,       /* device or host allocation failed                */
+    FB_E_HIP = -5          /* HIP runtime error (launch, copy, graph, ...)    */
+} fb_status;
+
+/* Flags of fb_params.flags */
+#define FB_USE_GRAPH   0x1u  /* replay the batched launch sequence as a HIP graph */
+#define FB_NO_AUTOTUNE 0x2u  /* use the default tile shape, skip the autotuner    */
+
+/* PatchMatch parameters (Algorithm 1).  The paper names p, n and the pyramid
+ * but gives no values; 2 / 3 / 6 are the values of the 512x512 blending
+ * workload. */
+typedef struct {
+    int32_t patch_radius;  /* p: patches are (2p+1) x (2p+1) x 3; 1 <= p <= 4  */
+    int32_t levels;        /* pyramid levels K >= 1                            */
+    int32_t iters;         /* iterations n per level, >= 0                     */
+    uint32_t flags;        /* FB_USE_GRAPH | FB_NO_AUTOTUNE                    */
+    uint64_t seed;         /* key of the Philox4x32-10 draws                   */
+} fb_params;
+
+typedef struct fb_ctx fb_ctx;
+
+/* Create a context on HIP device `device`: it owns the workspace, the
+ * per-shape launch plans, captured graphs and autotuning results.
+ * Returns FB_E_HIP if the device cannot be used. */
+fb_status fb_create(int32_t device, fb_ctx **out);
+/* Wait for the context's outstanding work and release it.  NULL is a no-op. */
+void fb_destroy(fb_ctx *ctx);
+/* Message of the last non-OK status on this thread ("" if none). */
+const char *fb_last_error(void);
+
+/* Tile shapes of the PatchMatch kernels.  By default the first batched call
+ * of every batch shape times each shape on the finest-level iteration and
+ * later calls use the fastest (the first call waits for the stream while it
+ * measures).  fb_set_tile_config(ctx, i) forces shape i in
+ * [0, fb_num_tile_configs()) for all later calls; -1 restores autotuning.
+ * Results never depend on the tile shape. */
+int32_t fb_num_tile_configs(void);
+fb_status fb_set_tile_config(fb_ctx *ctx, int32_t index);
+
+/* ---------------------------------------------------------------------- */
+/* Image pyramid (Algorithm 1, "resize images S, T" for each level).       */
+/* 2x2 box filter with round-half-up, ceil sizes, clamped reads.  The      */
+/* pyramid is an opaque device buffer of fb_pyramid_bytes(h,w,levels,p)    */
+/* bytes allocated by the caller; it holds every level as padded 4-byte    */
+/* pixels plus per-pixel patch norms for patch radius p.                   */
+/* ---------------------------------------------------------------------- */
+size_t fb_pyramid_bytes(int32_t h, int32_t w, int32_t levels, int32_t patch_radius);
+fb_status fb_build_pyramid(fb_ctx *ctx, const uint8_t *rgb, int32_t h, int32_t w,
+                           int32_t levels, int32_t patch_radius, void *pyr, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* (1) NNF initialisation at pyramid level `level` (Algorithm 1, "randomly  */
+/* initialize F"; "initialize error matrix E").  src_pyr / tgt_pyr come     */
+/* from fb_build_pyramid with the same (h, w, levels >= level + 1, p).      */
+/* seed_offsets == NULL: every F(r,c) is a uniform Philox draw keyed by     */
+/* (params->seed, pair_id, level).  Otherwise seed_offsets is an int32      */
+/* [h_l][w_l][2] offset field and F(v) = clamp(v + offset(v)).              */
+/* Writes nnf int32 [h_l][w_l][2] and energy uint32 [h_l][w_l].             */
+/* ---------------------------------------------------------------------- */
+fb_status fb_nnf_init(fb_ctx *ctx, const void *src_pyr, const void *tgt_pyr, int32_t h, int32_t w,
+                      int32_t level, const fb_params *params, uint32_t pair_id,
+                      const int32_t *seed_offsets, int32_t *nnf, uint32_t *energy, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* (2) One pyramid level of PatchMatch (Algorithm 1 body; Section 3.2).     */
+/* If nnf_coarse != NULL it is the level+1 field (int32 [h_{l+1}][w_{l+1}]  */
+/* [2]); it is upsampled (F = clamp(2 F_c + parity)) and re-energised.      */
+/* Otherwise nnf / energy are read as the starting field (e.g. from         */
+/* fb_nnf_init).  Then params->iters concurrent iterations run: each pixel  */
+/* tries propagation F(v+d)-d for d = (-1,0),(1,0),(0,-1),(0,1), then       */
+/* random search around its running best at radii max(h_l,w_l) >> m, and   */
+/* keeps a candidate only if its loss is strictly lower.  Writes nnf and    */
+/* energy (int32 [h_l][w_l][2], uint32 [h_l][w_l]) in place.               */
+/* ---------------------------------------------------------------------- */
+fb_status fb_patchmatch_level(fb_ctx *ctx, const void *src_pyr, const void *tgt_pyr, int32_t h,
+                              int32_t w, int32_t level, const fb_params *params, uint32_t pair_id,
+                              const int32_t *nnf_coarse, int32_t *nnf, uint32_t *energy,
+                              void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* (3) Memory-efficient remapping (Algorithm 2): out(v) = average over      */
+/* d in [-p,p]^2 with v+d inside the image of style(F(v+d) - d) / 255,     */
+/* source reads clamped.  style uint8 [h][w][3], nnf int32 [h][w][2] (every */
+/* entry must lie in [0,h) x [0,w)), out fp32 [h][w][3] in [0, 1].          */
+/* ---------------------------------------------------------------------- */
+fb_status fb_remap(fb_ctx *ctx, const uint8_t *style, const int32_t *nnf, int32_t h, int32_t w,
+                   int32_t patch_radius, float *out, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* (4) Sliding-window blending, Eq. 2 (balanced mode, guide loss Eq. 1):    */
+/* out_i = mean over j in [max(0,i-M), min(N-1,i+M)] of (S_j -> S_i), where */
+/* S_j -> S_i remaps style j with NNF(G_j, G_i) estimated over `levels`     */
+/* levels (pair id j*N + i), and the j == i term is S_i / 255.              */
+/* guides, styles uint8 [N][h][w][3]; out fp32 [N][h][w][3].  Every pair of */
+/* the window runs batched, level by level.  The call may wait for the      */
+/* stream when its launch plan changes (new shapes or pointers).            */
+/* ---------------------------------------------------------------------- */
+fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, int32_t n_frames,
+                          int32_t h, int32_t w, int32_t radius_M, const fb_params *params,
+                          float *out, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* (5) Keyframe interpolation, Eq. 9: keyframes pass through (style / 255); */
+/* a frame i between keys l < i < r gets (r-i)/(r-l) (S_l -> S_i) +         */
+/* (i-l)/(r-l) (S_r -> S_i); frames before the first or after the last key  */
+/* get the single nearest key's remap.  key_idx (host) is sorted, unique,   */
+/* in [0, N); key_styles uint8 [n_keys][h][w][3]; out fp32 [N][h][w][3].    */
+/* ---------------------------------------------------------------------- */
+fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, int32_t h, int32_t w,
+                         const int32_t *key_idx, const uint8_t *key_styles, int32_t n_keys,
+                         const fb_params *params, float *out, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Batched PatchMatch (Section 3.2, "we store images in batches"): the      */
+/* whole pyramid of every pair, pairs of any size mixed, in grouped         */
+/* launches (one per level step and iteration, optionally replayed as a    */
+/* HIP graph).  Results equal n_pairs separate single-pair runs.            */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    const void *src_pyr;          /* fb_build_pyramid output, >= levels levels   */
+    const void *tgt_pyr;
+    int32_t h, w, levels;         /* level-0 size; pyramid levels of this pair   */
+    uint32_t pair_id;
+    const int32_t *seed_offsets;  /* optional int32 offsets at level levels-1   */
+    int32_t *nnf;                 /* out: int32 [h][w][2] level-0 field          */
+    uint32_t *energy;             /* out: uint32 [h][w]                          */
+} fb_pair_desc;
+
+/* pairs (host) holds n_pairs descriptors; params->levels is ignored (each
+ * pair has its own), the other fields apply to all pairs. */
+fb_status fb_patchmatch_batch(fb_ctx *ctx, const fb_pair_desc *pairs, int32_t n_pairs,
+                              const fb_params *params, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FASTBLEND_H */

@@ -1,0 +1,125 @@
+// Internal declarations of the FastBlend HIP library (gfx950).
+//
+// Data layout in device memory
+// ----------------------------
+// * Pyramid of one frame (fb_build_pyramid): for every level l, the image as
+//   4-byte pixels (R, G, B, 0) with a replicated border of p pixels on every
+//   side (so a patch read never needs clamping), row pitch rounded up to 16
+//   pixels, followed by the per-pixel patch norm N(u) = sum over the
+//   (2p+1)^2 x 3 patch at u of the squared pixel values (uint32 [h_l][w_l]).
+//   Since the loss of Eq. 1 is sum (s - t)^2 = N_S(u) + N_T(v) - 2 sum s t,
+//   one candidate costs (2p+1)^2 4-byte dot products (v_dot4_u32_u8), exact in
+//   32-bit integers.
+// * NNFs inside the library are one uint32 per pixel: (row << 16) | col.
+//   The C ABI converts to / from int32 [h][w][2].
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fb {
+
+constexpr int kMaxLevels = 16;
+constexpr int kMaxP = 4;
+constexpr int kPitchAlign = 16;  // pixels
+
+struct LevelGeom {
+    int32_t h, w;        // level size
+    int32_t pitch;       // padded row pitch in pixels
+    int32_t rows;        // padded rows = h + 2p
+    size_t px_off;       // byte offset of the padded pixel block
+    size_t norm_off;     // byte offset of the norm image
+};
+
+struct PyrLayout {
+    int32_t levels, p;
+    LevelGeom lv[kMaxLevels];
+    size_t bytes;
+};
+
+// Host: layout of a pyramid of `levels` levels for patch radius p.
+PyrLayout pyr_layout(int h, int w, int levels, int p);
+// Host: layout of a single padded level-0 image (styles), no norm.
+size_t padded_image_bytes(int h, int w, int p, int32_t *pitch_out);
+
+inline int ceil_half_pow(int x, int l) { return (x + (1 << l) - 1) >> l; }
+
+// One unit of PatchMatch work: one pair at one level, for one launch.
+enum StartMode : int32_t {
+    kStartRandom = 0,     // Philox draw at every pixel
+    kStartOffsets = 1,    // F = clamp(v + aux_off[v])          (aux_off int32 [h][w][2])
+    kStartUpsample = 2,   // F = clamp(2 f_in[v/2] + parity)    (f_in packed, coarse)
+    kStartUpsampleAbi = 3,// as 2, coarse field from aux_off int32 [hc][wc][2]
+    kStartCopyAbi = 4     // F = aux_off[v], E = e_abi[v] (given field and energy)
+};
+
+struct PMJob {
+    const uint32_t *src_px;    // padded pixels of the source level, at padded (0, 0)
+    const uint32_t *tgt_px;    // padded pixels of the target level
+    const uint32_t *src_norm;  // [h][w]
+    const uint32_t *tgt_norm;  // [h][w]
+    const uint32_t *f_in;      // packed field read by the launch
+    const uint32_t *e_in;      // energies read by iterations
+    uint32_t *f_out;           // packed field written by the launch
+    uint32_t *e_out;
+    const int32_t *aux_off;    // ABI int32 field / offsets (start modes 1, 3, 4)
+    const uint32_t *e_abi;     // ABI energies (start mode 4)
+    int32_t *nnf_abi;          // export destinations
+    uint32_t *energy_abi;
+    int32_t h, w, pitch;
+    int32_t hc, wc;            // coarse size for upsampling
+    uint32_t pair_id;
+    int32_t level;
+    int32_t mode;
+    int32_t tile_base;         // first flat tile of this job in the launch
+    int32_t tiles_x;           // tiles along w
+    int32_t pad_[2];
+};
+
+// Tile shape of the PatchMatch kernels (one thread per target pixel).
+struct TileCfg {
+    int32_t tw, th;
+};
+int n_tile_cfgs();
+TileCfg tile_cfg(int i);
+
+// One term of a remap sum: weight * (style remapped through f) or, with
+// f == nullptr, weight * style / 255 (the frame itself).
+struct RemapTerm {
+    const uint32_t *style_px;  // padded level-0 pixels of the style frame
+    const uint32_t *f;         // packed field [h][w] or nullptr
+    float weight;
+    int32_t pad_;
+};
+
+// Output frame of a remap sum: out = (sum of its terms) / divisor.
+struct RemapFrame {
+    float *out;                // fp32 [h][w][3]
+    int32_t term_base, n_terms;
+    float divisor;
+    int32_t pad_;
+};
+
+// ---- launchers (stream-ordered, no synchronisation) ----
+hipError_t launch_pack_level0(const uint8_t *rgb, size_t rgb_stride, int n, int h, int w, int p,
+                              uint8_t *dst, size_t dst_stride, size_t px_off, int pitch,
+                              hipStream_t s);
+hipError_t launch_downsample(const uint8_t *base, size_t stride, int n, const LevelGeom &in,
+                             const LevelGeom &out, int p, hipStream_t s);
+hipError_t launch_norm(uint8_t *base, size_t stride, int n, const LevelGeom &g, int p,
+                       hipStream_t s);
+
+hipError_t launch_pm_start(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
+                           TileCfg cfg, int p, uint64_t seed, hipStream_t s);
+hipError_t launch_pm_iter(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
+                          TileCfg cfg, int p, int iter, uint64_t seed, hipStream_t s);
+hipError_t launch_pm_export(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
+                            TileCfg cfg, hipStream_t s);
+
+hipError_t launch_remap_sum(const RemapFrame *frames, int n_frames, const RemapTerm *terms,
+                            int h, int w, int pitch, int p, hipStream_t s);
+
+hipError_t launch_field_to_packed(const int32_t *abi, uint32_t *packed, int h, int w, hipStream_t s);
+
+}  // namespace fb

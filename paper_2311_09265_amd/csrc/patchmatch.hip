@@ -1,0 +1,337 @@
+// PatchMatch kernels (Algorithm 1 and Section 3.2 of arXiv 2311.09265).
+//
+// One thread per target pixel; a workgroup is a TW x TH tile of one pair at
+// one level, and one launch covers every tile of every pair in the batch
+// (a flat tile list, see PMJob).  Three kernels:
+//
+//  k_pm_start   the first field of a level: a Philox draw at the coarsest
+//               level ("randomly initialize F"), an offset-field seed, or the
+//               upsampled field of the level above ("upsample F"), followed
+//               by its loss ("initialize error matrix E").
+//  k_pm_iter    one iteration of the concurrent update: every pixel reads the
+//               previous field only (its own value and its 4 neighbours), so
+//               launches are the only synchronisation (Jacobi double buffer).
+//               Candidates, in this fixed order, each against the running
+//               best with strict '<':
+//                 propagation F(v+d) - d, d = (-1,0), (1,0), (0,-1), (0,1);
+//                 random search best + delta, delta uniform on [-rho, rho]^2,
+//                 rho = R >> m, m = 0, 1, ... while rho >= 1, R = max(h, w).
+//               A candidate equal to the running best is skipped: its loss
+//               equals the best loss and could never pass '<'.
+//  k_pm_export  packed field -> int32 [h][w][2] and energies for the C ABI.
+//
+// Loss (Eq. 1) of a candidate u for target v, exact in uint32:
+//   N_S(u) + N_T(v) - 2 * sum over the patch of <s, t>,
+// with the dot products as v_dot4_u32_u8 on (R,G,B,0) pixels.  The target
+// patch stays in registers for the whole iteration; a source patch row is one
+// 16-byte + one 4-byte load from the padded image (no clamping needed).
+//
+// Random draws: Philox4x32-10 (Salmon et al., SC'11), key = seed, counter =
+// (pixel index r*w + c, pair id, level << 16 | iteration, m >> 2); word m & 3
+// gives the row offset from its low 16 bits and the column offset from its
+// high 16 bits, a 16-bit draw u mapping to [0, n) as (u * n) >> 16.  The
+// initial draw uses iteration 0xFFFF and word 0.  Draws never depend on the
+// position of a pair in a batch or on the tile shape.
+#include "fb_common.h"
+
+namespace fb {
+
+namespace {
+
+__device__ __forceinline__ int clampi(int x, int lo, int hi) { return min(max(x, lo), hi); }
+
+// Philox4x32-10 block function, from its published definition.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 x, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, x.x), lo0 = 0xD2511F53u * x.x;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, x.z), lo1 = 0xCD9E8D57u * x.z;
+        x = make_uint4(hi1 ^ x.y ^ k0, lo1, hi0 ^ x.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return x;
+}
+
+__device__ __forceinline__ int u16_to_range(uint32_t u16, uint32_t n) {
+    return (int)((u16 * n) >> 16);
+}
+
+// Consecutive workgroups are dispatched round-robin over the 8 XCDs; give
+// each XCD one contiguous range of tiles so a pair's neighbouring tiles (and
+// its source image) share that XCD's L2.  A bijection on [0, total).
+__device__ __forceinline__ int xcd_tile(int b, int total) {
+    const int q = total >> 3, r = total & 7;
+    const int x = b & 7, s = b >> 3;
+    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+}
+
+__device__ __forceinline__ int find_job(const PMJob *__restrict__ jobs, int n, int uniform, int t) {
+    if (uniform > 0) return t / uniform;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile_base <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int K>
+struct __attribute__((packed, aligned(4))) PixRow {
+    uint32_t v[K];
+};
+
+// sum over the K x K patch of <source pixel, target pixel>
+template <int P>
+__device__ __forceinline__ uint32_t patch_dot(const uint32_t *__restrict__ sp, int pitch,
+                                              const uint32_t (&t)[2 * P + 1][2 * P + 1]) {
+    constexpr int K = 2 * P + 1;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const PixRow<K> row = *reinterpret_cast<const PixRow<K> *>(sp + (size_t)i * pitch);
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc = __builtin_amdgcn_udot4(row.v[j], t[i][j], acc, false);
+    }
+    return acc;
+}
+
+template <int P>
+__device__ __forceinline__ void load_target_patch(const uint32_t *__restrict__ tp, int pitch,
+                                                  uint32_t (&t)[2 * P + 1][2 * P + 1]) {
+    constexpr int K = 2 * P + 1;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const PixRow<K> row = *reinterpret_cast<const PixRow<K> *>(tp + (size_t)i * pitch);
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[i][j] = row.v[j];
+    }
+}
+
+struct TileCoord {
+    int job, r, c;
+    bool active;
+};
+
+template <int TW, int TH>
+__device__ __forceinline__ TileCoord locate(const PMJob *__restrict__ jobs, int n_jobs,
+                                            int total_tiles, int uniform_tiles) {
+    const int t = xcd_tile((int)blockIdx.x, total_tiles);
+    const int j = find_job(jobs, n_jobs, uniform_tiles, t);
+    const int lt = t - jobs[j].tile_base;
+    const int tx_n = jobs[j].tiles_x;
+    const int ty = lt / tx_n, tx = lt - ty * tx_n;
+    TileCoord tc;
+    tc.job = j;
+    tc.r = ty * TH + (int)threadIdx.y;
+    tc.c = tx * TW + (int)threadIdx.x;
+    tc.active = tc.r < jobs[j].h && tc.c < jobs[j].w;
+    return tc;
+}
+
+template <int P, int TW, int TH>
+__global__ void __launch_bounds__(TW *TH)
+k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles,
+           uint32_t k0, uint32_t k1) {
+    const TileCoord tc = locate<TW, TH>(jobs, n_jobs, total_tiles, uniform_tiles);
+    if (!tc.active) return;
+    const PMJob &J = jobs[tc.job];
+    const int h = J.h, w = J.w, r = tc.r, c = tc.c;
+    const int v = r * w + c;
+    int fr, fc;
+    switch (J.mode) {
+    case kStartRandom: {
+        const uint4 x = philox4x32_10(make_uint4((uint32_t)v, J.pair_id,
+                                                 ((uint32_t)J.level << 16) | 0xFFFFu, 0u), k0, k1);
+        fr = u16_to_range(x.x & 0xFFFFu, (uint32_t)h);
+        fc = u16_to_range(x.x >> 16, (uint32_t)w);
+        break;
+    }
+    case kStartOffsets:
+        // offsets limited to +-size first, so the sum cannot overflow
+        fr = clampi(r + clampi(J.aux_off[2 * v], -h, h), 0, h - 1);
+        fc = clampi(c + clampi(J.aux_off[2 * v + 1], -w, w), 0, w - 1);
+        break;
+    case kStartUpsample: {
+        const uint32_t q = J.f_in[(r >> 1) * J.wc + (c >> 1)];
+        fr = clampi(2 * (int)(q >> 16) + (r & 1), 0, h - 1);
+        fc = clampi(2 * (int)(q & 0xFFFFu) + (c & 1), 0, w - 1);
+        break;
+    }
+    case kStartUpsampleAbi: {
+        const int qi = (r >> 1) * J.wc + (c >> 1);
+        fr = clampi(2 * clampi(J.aux_off[2 * qi], 0, J.hc - 1) + (r & 1), 0, h - 1);
+        fc = clampi(2 * clampi(J.aux_off[2 * qi + 1], 0, J.wc - 1) + (c & 1), 0, w - 1);
+        break;
+    }
+    default: {  // kStartCopyAbi: the given field and energies (entries clamped into range)
+        fr = clampi(J.aux_off[2 * v], 0, h - 1);
+        fc = clampi(J.aux_off[2 * v + 1], 0, w - 1);
+        J.f_out[v] = ((uint32_t)fr << 16) | (uint32_t)fc;
+        J.e_out[v] = J.e_abi[v];
+        return;
+    }
+    }
+    uint32_t t[2 * P + 1][2 * P + 1];
+    load_target_patch<P>(J.tgt_px + (size_t)r * J.pitch + c, J.pitch, t);
+    const uint32_t dot = patch_dot<P>(J.src_px + (size_t)fr * J.pitch + fc, J.pitch, t);
+    J.f_out[v] = ((uint32_t)fr << 16) | (uint32_t)fc;
+    J.e_out[v] = J.src_norm[fr * w + fc] + J.tgt_norm[v] - 2u * dot;
+}
+
+template <int P, int TW, int TH>
+__global__ void __launch_bounds__(TW *TH)
+k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles, int iter,
+          uint32_t k0, uint32_t k1) {
+    const TileCoord tc = locate<TW, TH>(jobs, n_jobs, total_tiles, uniform_tiles);
+    if (!tc.active) return;
+    const PMJob &J = jobs[tc.job];
+    const int h = J.h, w = J.w, pitch = J.pitch, r = tc.r, c = tc.c;
+    const int v = r * w + c;
+    const uint32_t *__restrict__ f_in = J.f_in;
+    const uint32_t *__restrict__ src_px = J.src_px;
+    const uint32_t *__restrict__ src_norm = J.src_norm;
+
+    uint32_t t[2 * P + 1][2 * P + 1];
+    load_target_patch<P>(J.tgt_px + (size_t)r * pitch + c, pitch, t);
+    const uint32_t tn = J.tgt_norm[v];
+
+    const uint32_t f0 = f_in[v];
+    int br = (int)(f0 >> 16), bc = (int)(f0 & 0xFFFFu);
+    uint32_t be = J.e_in[v];
+
+    auto consider = [&](int cr, int cc) {
+        if (cr == br && cc == bc) return;
+        const uint32_t e = src_norm[cr * w + cc] + tn -
+                           2u * patch_dot<P>(src_px + (size_t)cr * pitch + cc, pitch, t);
+        if (e < be) { br = cr; bc = cc; be = e; }
+    };
+
+    // propagation: F(v + d) - d for d = (-1,0), (1,0), (0,-1), (0,1)
+    if (r > 0) {
+        const uint32_t q = f_in[v - w];
+        consider(min((int)(q >> 16) + 1, h - 1), (int)(q & 0xFFFFu));
+    }
+    if (r < h - 1) {
+        const uint32_t q = f_in[v + w];
+        consider(max((int)(q >> 16) - 1, 0), (int)(q & 0xFFFFu));
+    }
+    if (c > 0) {
+        const uint32_t q = f_in[v - 1];
+        consider((int)(q >> 16), min((int)(q & 0xFFFFu) + 1, w - 1));
+    }
+    if (c < w - 1) {
+        const uint32_t q = f_in[v + 1];
+        consider((int)(q >> 16), max((int)(q & 0xFFFFu) - 1, 0));
+    }
+
+    // random search around the running best, radius halving from max(h, w)
+    const int R = max(h, w);
+    const uint32_t ctr2 = ((uint32_t)J.level << 16) | (uint32_t)iter;
+    uint4 x = make_uint4(0, 0, 0, 0);
+    for (int m = 0; (R >> m) > 0; ++m) {
+        if ((m & 3) == 0) x = philox4x32_10(make_uint4((uint32_t)v, J.pair_id, ctr2, (uint32_t)(m >> 2)), k0, k1);
+        const int s = m & 3;
+        const uint32_t word = s == 0 ? x.x : (s == 1 ? x.y : (s == 2 ? x.z : x.w));
+        const int rho = R >> m;
+        const uint32_t n = 2u * (uint32_t)rho + 1u;
+        const int dr = u16_to_range(word & 0xFFFFu, n) - rho;
+        const int dc = u16_to_range(word >> 16, n) - rho;
+        consider(clampi(br + dr, 0, h - 1), clampi(bc + dc, 0, w - 1));
+    }
+    J.f_out[v] = ((uint32_t)br << 16) | (uint32_t)bc;
+    J.e_out[v] = be;
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW *TH)
+k_pm_export(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles) {
+    const TileCoord tc = locate<TW, TH>(jobs, n_jobs, total_tiles, uniform_tiles);
+    if (!tc.active) return;
+    const PMJob &J = jobs[tc.job];
+    const int v = tc.r * J.w + tc.c;
+    const uint32_t f = J.f_in[v];
+    reinterpret_cast<int2 *>(J.nnf_abi)[v] = make_int2((int)(f >> 16), (int)(f & 0xFFFFu));
+    J.energy_abi[v] = J.e_in[v];
+}
+
+// int32 [h][w][2] field -> packed; entries are clamped into the image so a
+// malformed field can never steer a later gather outside the padded image.
+__global__ void __launch_bounds__(256)
+k_field_to_packed(const int32_t *__restrict__ abi, uint32_t *__restrict__ packed, int h, int w) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= h * w) return;
+    const int2 f = reinterpret_cast<const int2 *>(abi)[i];
+    packed[i] = ((uint32_t)clampi(f.x, 0, h - 1) << 16) | (uint32_t)clampi(f.y, 0, w - 1);
+}
+
+constexpr TileCfg kTileCfgs[] = {{64, 4}, {32, 8}, {16, 16}, {64, 2}};
+
+}  // namespace
+
+int n_tile_cfgs() { return (int)(sizeof(kTileCfgs) / sizeof(kTileCfgs[0])); }
+TileCfg tile_cfg(int i) { return kTileCfgs[i]; }
+
+#define FB_TILE_SWITCH(CFG, MACRO)                                            \
+    if ((CFG).tw == 64 && (CFG).th == 4) { MACRO(64, 4); }                    \
+    else if ((CFG).tw == 32 && (CFG).th == 8) { MACRO(32, 8); }               \
+    else if ((CFG).tw == 16 && (CFG).th == 16) { MACRO(16, 16); }             \
+    else if ((CFG).tw == 64 && (CFG).th == 2) { MACRO(64, 2); }               \
+    else return hipErrorInvalidValue;
+
+#define FB_P_SWITCH(P_, MACRO2, TW, TH)                                       \
+    switch (P_) {                                                             \
+    case 1: MACRO2(1, TW, TH); break;                                         \
+    case 2: MACRO2(2, TW, TH); break;                                         \
+    case 3: MACRO2(3, TW, TH); break;                                         \
+    case 4: MACRO2(4, TW, TH); break;                                         \
+    default: return hipErrorInvalidValue;                                     \
+    }
+
+hipError_t launch_pm_start(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
+                           TileCfg cfg, int p, uint64_t seed, hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#define FB_START2(P_, TW, TH)                                                                 \
+    hipLaunchKernelGGL((k_pm_start<P_, TW, TH>), dim3(total_tiles), dim3(TW, TH), 0, s, jobs, \
+                       n_jobs, total_tiles, uniform_tiles, k0, k1)
+#define FB_START(TW, TH) FB_P_SWITCH(p, FB_START2, TW, TH)
+    FB_TILE_SWITCH(cfg, FB_START)
+#undef FB_START
+#undef FB_START2
+    return hipGetLastError();
+}
+
+hipError_t launch_pm_iter(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
+                          TileCfg cfg, int p, int iter, uint64_t seed, hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#define FB_ITER2(P_, TW, TH)                                                                  \
+    hipLaunchKernelGGL((k_pm_iter<P_, TW, TH>), dim3(total_tiles), dim3(TW, TH), 0, s, jobs,  \
+                       n_jobs, total_tiles, uniform_tiles, iter, k0, k1)
+#define FB_ITER(TW, TH) FB_P_SWITCH(p, FB_ITER2, TW, TH)
+    FB_TILE_SWITCH(cfg, FB_ITER)
+#undef FB_ITER
+#undef FB_ITER2
+    return hipGetLastError();
+}
+
+hipError_t launch_pm_export(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
+                            TileCfg cfg, hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+#define FB_EXPORT(TW, TH)                                                                     \
+    hipLaunchKernelGGL((k_pm_export<TW, TH>), dim3(total_tiles), dim3(TW, TH), 0, s, jobs,    \
+                       n_jobs, total_tiles, uniform_tiles)
+    FB_TILE_SWITCH(cfg, FB_EXPORT)
+#undef FB_EXPORT
+    return hipGetLastError();
+}
+
+hipError_t launch_field_to_packed(const int32_t *abi, uint32_t *packed, int h, int w, hipStream_t s) {
+    const int n = h * w;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_field_to_packed, dim3((n + 255) / 256), dim3(256), 0, s, abi, packed, h, w);
+    return hipGetLastError();
+}
+
+}  // namespace fb

@@ -1,0 +1,139 @@
+// Image pyramid kernels (Algorithm 1, "resize images S, T" at every level).
+//
+// Reading of the paper's unspecified resize: 2x2 box filter with round-half-up,
+// ceil(h/2) x ceil(w/2) output, source reads clamped to the image.  Every
+// level is stored as padded 4-byte pixels (see fb_common.h) so the patch
+// kernels never clamp, plus a per-pixel patch-norm image.
+//
+// All three kernels stream through HBM once per frame and level; they are a
+// negligible share of a blend (one pyramid per frame, shared by every pair
+// that uses the frame).
+#include "fb_common.h"
+
+namespace fb {
+
+__device__ __forceinline__ int clampi(int x, int lo, int hi) { return min(max(x, lo), hi); }
+
+PyrLayout pyr_layout(int h, int w, int levels, int p) {
+    PyrLayout L{};
+    L.levels = levels;
+    L.p = p;
+    size_t off = 0;
+    for (int l = 0; l < levels; ++l) {
+        LevelGeom &g = L.lv[l];
+        g.h = ceil_half_pow(h, l);
+        g.w = ceil_half_pow(w, l);
+        g.rows = g.h + 2 * p;
+        g.pitch = (g.w + 2 * p + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
+        g.px_off = off;
+        off += (size_t)g.rows * g.pitch * 4;
+        off = (off + 255) & ~(size_t)255;
+        g.norm_off = off;
+        off += (size_t)g.h * g.w * 4;
+        off = (off + 255) & ~(size_t)255;
+    }
+    L.bytes = off;
+    return L;
+}
+
+size_t padded_image_bytes(int h, int w, int p, int32_t *pitch_out) {
+    int pitch = (w + 2 * p + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
+    if (pitch_out) *pitch_out = pitch;
+    return (((size_t)(h + 2 * p) * pitch * 4) + 255) & ~(size_t)255;
+}
+
+// RGB8 [h][w][3] -> padded (R,G,B,0) pixels; one thread per padded pixel.
+__global__ void __launch_bounds__(256)
+k_pack_level0(const uint8_t *__restrict__ rgb, size_t rgb_stride, int h, int w, int p,
+              uint8_t *__restrict__ dst, size_t dst_stride, size_t px_off, int pitch) {
+    const int C = blockIdx.x * blockDim.x + threadIdx.x;
+    const int R = blockIdx.y;
+    const int f = blockIdx.z;
+    if (C >= w + 2 * p) return;
+    const int r = clampi(R - p, 0, h - 1), c = clampi(C - p, 0, w - 1);
+    const uint8_t *s = rgb + (size_t)f * rgb_stride + ((size_t)r * w + c) * 3;
+    const uint32_t px = (uint32_t)s[0] | ((uint32_t)s[1] << 8) | ((uint32_t)s[2] << 16);
+    uint32_t *d = reinterpret_cast<uint32_t *>(dst + (size_t)f * dst_stride + px_off);
+    d[(size_t)R * pitch + C] = px;
+}
+
+// Padded level l -> padded level l+1 (2x2 box, round half up, clamped reads).
+__global__ void __launch_bounds__(256)
+k_downsample(uint8_t *__restrict__ base, size_t stride, int hi_, int wi, int pitch_i, size_t off_i,
+             int ho, int wo, int pitch_o, size_t off_o, int p) {
+    const int C = blockIdx.x * blockDim.x + threadIdx.x;
+    const int R = blockIdx.y;
+    const int f = blockIdx.z;
+    if (C >= wo + 2 * p) return;
+    uint8_t *fb = base + (size_t)f * stride;
+    const uint32_t *in = reinterpret_cast<const uint32_t *>(fb + off_i);
+    uint32_t *out = reinterpret_cast<uint32_t *>(fb + off_o);
+    const int r = clampi(R - p, 0, ho - 1), c = clampi(C - p, 0, wo - 1);
+    uint32_t rb = 0, g = 0;  // R and B sums in 16-bit halves; G alone
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int rr = min(2 * r + a, hi_ - 1) + p, cc = min(2 * c + b, wi - 1) + p;
+            const uint32_t px = in[(size_t)rr * pitch_i + cc];
+            rb += px & 0x00FF00FFu;
+            g += (px >> 8) & 0xFFu;
+        }
+    const uint32_t vr = ((rb & 0xFFFFu) + 2) >> 2, vb = ((rb >> 16) + 2) >> 2, vg = (g + 2) >> 2;
+    out[(size_t)R * pitch_o + C] = vr | (vg << 8) | (vb << 16);
+}
+
+// N(u) = sum over the (2p+1)^2 patch at u of r^2 + g^2 + b^2.
+template <int P>
+__global__ void __launch_bounds__(256)
+k_norm(uint8_t *__restrict__ base, size_t stride, int h, int w, int pitch, size_t px_off,
+       size_t norm_off) {
+    constexpr int K = 2 * P + 1;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    const int f = blockIdx.z;
+    if (c >= w) return;
+    uint8_t *fb = base + (size_t)f * stride;
+    const uint32_t *px = reinterpret_cast<const uint32_t *>(fb + px_off) + (size_t)r * pitch + c;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint32_t v = px[(size_t)i * pitch + j];
+            acc = __builtin_amdgcn_udot4(v, v, acc, false);
+        }
+    reinterpret_cast<uint32_t *>(fb + norm_off)[(size_t)r * w + c] = acc;
+}
+
+hipError_t launch_pack_level0(const uint8_t *rgb, size_t rgb_stride, int n, int h, int w, int p,
+                              uint8_t *dst, size_t dst_stride, size_t px_off, int pitch,
+                              hipStream_t s) {
+    dim3 grid((w + 2 * p + 255) / 256, h + 2 * p, n);
+    hipLaunchKernelGGL(k_pack_level0, grid, dim3(256), 0, s, rgb, rgb_stride, h, w, p, dst,
+                       dst_stride, px_off, pitch);
+    return hipGetLastError();
+}
+
+hipError_t launch_downsample(const uint8_t *base, size_t stride, int n, const LevelGeom &in,
+                             const LevelGeom &out, int p, hipStream_t s) {
+    dim3 grid((out.w + 2 * p + 255) / 256, out.rows, n);
+    hipLaunchKernelGGL(k_downsample, grid, dim3(256), 0, s, const_cast<uint8_t *>(base), stride,
+                       in.h, in.w, in.pitch, in.px_off, out.h, out.w, out.pitch, out.px_off, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm(uint8_t *base, size_t stride, int n, const LevelGeom &g, int p,
+                       hipStream_t s) {
+    dim3 grid((g.w + 255) / 256, g.h, n);
+    switch (p) {
+    case 1: hipLaunchKernelGGL(k_norm<1>, grid, dim3(256), 0, s, base, stride, g.h, g.w, g.pitch, g.px_off, g.norm_off); break;
+    case 2: hipLaunchKernelGGL(k_norm<2>, grid, dim3(256), 0, s, base, stride, g.h, g.w, g.pitch, g.px_off, g.norm_off); break;
+    case 3: hipLaunchKernelGGL(k_norm<3>, grid, dim3(256), 0, s, base, stride, g.h, g.w, g.pitch, g.px_off, g.norm_off); break;
+    case 4: hipLaunchKernelGGL(k_norm<4>, grid, dim3(256), 0, s, base, stride, g.h, g.w, g.pitch, g.px_off, g.norm_off); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fb

@@ -1,0 +1,95 @@
+// Remapping and blending kernel (Algorithm 2, Eq. 2 and Eq. 9 of arXiv 2311.09265).
+//
+// out(v) = (sum over terms k of weight_k * R_k(v)) / divisor, where a term is
+// either a style frame remapped through an NNF F,
+//   R(v) = sum_{d in [-p,p]^2, v+d inside} S(F(v+d) - d) / (255 * count_v)
+// (Algorithm 2 computed per output pixel, no patch materialisation; at the
+// border only the in-image neighbours count, i.e. the patch-overlap average of
+// Section 3.3), or the frame itself, R(v) = S(v) / 255.  The window blend of
+// Eq. 2 is one output frame with 2M+1 (truncated) unit-weight terms and
+// divisor = their count; the keyframe combination of Eq. 9 has two terms
+// with weights (r-i)/(r-l), (i-l)/(r-l) and divisor 1.
+//
+// One thread per output pixel of one output frame.  Per remapped term a
+// thread reads (2p+1)^2 packed NNF entries (coalesced along rows, shared
+// through L1 with the neighbouring threads) and gathers the same number of
+// 4-byte style pixels from the padded frame (so F(v+d) - d needs no clamp).
+// Channel sums are integers (R and B in the two halves of one register, G in
+// another); each term costs one fp32 division per channel.  HBM traffic per
+// output frame: its fields and style frames once (L2-resident gathers) plus
+// 12 B per output pixel.
+#include "fb_common.h"
+
+namespace fb {
+
+namespace {
+
+constexpr int kRTW = 64, kRTH = 4;
+
+template <int P>
+__global__ void __launch_bounds__(kRTW *kRTH)
+k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__ terms, int h,
+            int w, int pitch, int tiles_x) {
+    const RemapFrame fr = frames[blockIdx.y];
+    const int ty = (int)blockIdx.x / tiles_x, tx = (int)blockIdx.x - ty * tiles_x;
+    const int r = ty * kRTH + (int)threadIdx.y, c = tx * kRTW + (int)threadIdx.x;
+    if (r >= h || c >= w) return;
+    const int r0 = max(-P, -r), r1 = min(P, h - 1 - r);
+    const int c0 = max(-P, -c), c1 = min(P, w - 1 - c);
+    const float denom = (float)(255 * (r1 - r0 + 1) * (c1 - c0 + 1));
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    for (int k = 0; k < fr.n_terms; ++k) {
+        const RemapTerm T = terms[fr.term_base + k];
+        const uint32_t *__restrict__ sp = T.style_px;
+        if (T.f == nullptr) {
+            const uint32_t px = sp[(size_t)(r + P) * pitch + (c + P)];
+            a0 += T.weight * ((float)(px & 0xFFu) / 255.0f);
+            a1 += T.weight * ((float)((px >> 8) & 0xFFu) / 255.0f);
+            a2 += T.weight * ((float)((px >> 16) & 0xFFu) / 255.0f);
+            continue;
+        }
+        const uint32_t *__restrict__ f = T.f;
+        uint32_t rb = 0, g = 0;
+#pragma unroll
+        for (int dr = -P; dr <= P; ++dr) {
+            if (dr < r0 || dr > r1) continue;
+            const uint32_t *frow = f + (size_t)(r + dr) * w + c;
+#pragma unroll
+            for (int dc = -P; dc <= P; ++dc) {
+                if (dc < c0 || dc > c1) continue;
+                const uint32_t q = frow[dc];
+                const int sr = (int)(q >> 16) - dr + P, sc = (int)(q & 0xFFFFu) - dc + P;
+                const uint32_t px = sp[(size_t)sr * pitch + sc];
+                rb += px & 0x00FF00FFu;
+                g += (px >> 8) & 0xFFu;
+            }
+        }
+        a0 += T.weight * ((float)(rb & 0xFFFFu) / denom);
+        a1 += T.weight * ((float)g / denom);
+        a2 += T.weight * ((float)(rb >> 16) / denom);
+    }
+    float *o = fr.out + ((size_t)r * w + c) * 3;
+    o[0] = a0 / fr.divisor;
+    o[1] = a1 / fr.divisor;
+    o[2] = a2 / fr.divisor;
+}
+
+}  // namespace
+
+hipError_t launch_remap_sum(const RemapFrame *frames, int n_frames, const RemapTerm *terms, int h,
+                            int w, int pitch, int p, hipStream_t s) {
+    if (n_frames <= 0) return hipSuccess;
+    const int tiles_x = (w + kRTW - 1) / kRTW, tiles_y = (h + kRTH - 1) / kRTH;
+    dim3 grid(tiles_x * tiles_y, n_frames);
+    dim3 block(kRTW, kRTH);
+    switch (p) {
+    case 1: hipLaunchKernelGGL(k_remap_sum<1>, grid, block, 0, s, frames, terms, h, w, pitch, tiles_x); break;
+    case 2: hipLaunchKernelGGL(k_remap_sum<2>, grid, block, 0, s, frames, terms, h, w, pitch, tiles_x); break;
+    case 3: hipLaunchKernelGGL(k_remap_sum<3>, grid, block, 0, s, frames, terms, h, w, pitch, tiles_x); break;
+    case 4: hipLaunchKernelGGL(k_remap_sum<4>, grid, block, 0, s, frames, terms, h, w, pitch, tiles_x); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fb

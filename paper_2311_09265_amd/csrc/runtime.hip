@@ -1,0 +1,825 @@
+// Host runtime of the FastBlend library: the C ABI of include/fastblend.h.
+//
+// Every call is turned into a Plan: a list of stream-ordered kernel launches
+// plus one table of launch descriptors (PMJob / RemapTerm / RemapFrame)
+// uploaded to device memory in a single copy.  Batched PatchMatch plans
+// group all pairs that sit at the same pyramid level into one launch per
+// step (start of level, each iteration), the pairs' tiles forming one flat
+// list, so a 290-pair window fills all 256 CUs with ~300k workgroups.
+//
+// Plans are rebuilt on the host at every call (microseconds); the device
+// table is re-uploaded only when its bytes change, and with FB_USE_GRAPH the
+// launch list is captured once into a HIP graph and replayed while the plan
+// stays the same.  The autotuner times the finest-level iteration launch of
+// a batch with every tile shape once per batch shape and keeps the fastest;
+// tile shapes never change results.
+#include <algorithm>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "fastblend.h"
+#include "fb_common.h"
+
+using namespace fb;
+
+namespace {
+
+thread_local std::string g_err;
+
+fb_status fail(fb_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+#define FB_HIP(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(FB_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+struct Buf {
+    void *p = nullptr;
+    size_t n = 0;
+};
+
+using Op = std::function<hipError_t(hipStream_t, const uint8_t *)>;
+
+struct Plan {
+    std::vector<uint8_t> table;  // host image of the device tables
+    std::vector<Op> ops;
+    std::string sig;             // every kernel argument not in the table
+    // autotuning: the finest-level iteration launch of a PatchMatch batch
+    bool has_tune = false;
+    std::vector<PMJob> tune_jobs;
+    int tune_iter = 0;
+    std::string tune_key;
+};
+
+template <class T>
+size_t table_append(Plan &P, const T *data, size_t n) {
+    const size_t off = (P.table.size() + 255) & ~(size_t)255;
+    P.table.resize(off + n * sizeof(T));
+    if (n) std::memcpy(P.table.data() + off, data, n * sizeof(T));
+    return off;
+}
+
+void sig_add(Plan &P, const char *tag, long long a, long long b = 0, long long c = 0,
+             long long d = 0) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s:%lld:%lld:%lld:%lld;", tag, a, b, c, d);
+    P.sig += buf;
+}
+
+void assign_tiles(std::vector<PMJob> &jobs, TileCfg cfg, int *total, int *uniform) {
+    int base = 0, uni = -1;
+    for (PMJob &j : jobs) {
+        const int tx = (j.w + cfg.tw - 1) / cfg.tw, ty = (j.h + cfg.th - 1) / cfg.th;
+        j.tiles_x = tx;
+        j.tile_base = base;
+        base += tx * ty;
+        if (uni == -1) uni = tx * ty;
+        else if (uni != tx * ty) uni = 0;
+    }
+    *total = base;
+    *uniform = uni > 0 ? uni : 0;
+}
+
+enum LaunchKind { kLaunchStart, kLaunchIter, kLaunchExport };
+
+void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cfg, int p,
+                   uint64_t seed, int iter) {
+    if (jobs.empty()) return;
+    int total = 0, uniform = 0;
+    assign_tiles(jobs, cfg, &total, &uniform);
+    const size_t off = table_append(P, jobs.data(), jobs.size());
+    const int n = (int)jobs.size();
+    sig_add(P, "pm", kind, (long long)off, n, ((long long)iter << 32) | (cfg.tw << 8) | cfg.th);
+    switch (kind) {
+    case kLaunchStart:
+        P.ops.push_back([=](hipStream_t s, const uint8_t *tab) {
+            return launch_pm_start(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform,
+                                   cfg, p, seed, s);
+        });
+        break;
+    case kLaunchIter:
+        P.ops.push_back([=](hipStream_t s, const uint8_t *tab) {
+            return launch_pm_iter(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform,
+                                  cfg, p, iter, seed, s);
+        });
+        break;
+    case kLaunchExport:
+        P.ops.push_back([=](hipStream_t s, const uint8_t *tab) {
+            return launch_pm_export(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform,
+                                    cfg, s);
+        });
+        break;
+    }
+}
+
+// Pyramids of n frames (uint8 [n][h][w][3], contiguous) into dst[f * stride].
+void plan_pyramids(Plan &P, const uint8_t *rgb, int n, int h, int w, const PyrLayout &L,
+                   uint8_t *dst, size_t stride) {
+    const int p = L.p;
+    const size_t rgb_stride = (size_t)h * w * 3;
+    sig_add(P, "pyr", (long long)(uintptr_t)rgb, n, ((long long)h << 32) | w,
+            (long long)(uintptr_t)dst + L.levels);
+    P.ops.push_back([=](hipStream_t s, const uint8_t *) {
+        hipError_t e = launch_pack_level0(rgb, rgb_stride, n, h, w, p, dst, stride,
+                                          L.lv[0].px_off, L.lv[0].pitch, s);
+        for (int l = 1; l < L.levels && e == hipSuccess; ++l)
+            e = launch_downsample(dst, stride, n, L.lv[l - 1], L.lv[l], p, s);
+        for (int l = 0; l < L.levels && e == hipSuccess; ++l)
+            e = launch_norm(dst, stride, n, L.lv[l], p, s);
+        return e;
+    });
+}
+
+// Padded level-0 pixels of n style frames (no norms).
+void plan_style_pack(Plan &P, const uint8_t *rgb, int n, int h, int w, int p, uint8_t *dst,
+                     size_t stride, int pitch) {
+    const size_t rgb_stride = (size_t)h * w * 3;
+    sig_add(P, "sty", (long long)(uintptr_t)rgb, n, ((long long)h << 32) | w,
+            (long long)(uintptr_t)dst);
+    P.ops.push_back([=](hipStream_t s, const uint8_t *) {
+        return launch_pack_level0(rgb, rgb_stride, n, h, w, p, dst, stride, 0, pitch, s);
+    });
+}
+
+struct PairSpec {
+    const uint8_t *src_pyr, *tgt_pyr;
+    PyrLayout L;               // L.levels: this pair's pyramid levels
+    uint32_t pair_id;
+    const int32_t *seed_offsets;
+    uint32_t *f[2], *e[2];     // ping-pong buffers (level-0 capacity)
+    int32_t *nnf_abi;          // optional export of the final field
+    uint32_t *energy_abi;
+    int final_buf;             // filled by the planner
+};
+
+PMJob job_geom(const PairSpec &ps, int l) {
+    PMJob j;
+    std::memset(&j, 0, sizeof j);
+    const LevelGeom &g = ps.L.lv[l];
+    j.src_px = reinterpret_cast<const uint32_t *>(ps.src_pyr + g.px_off);
+    j.tgt_px = reinterpret_cast<const uint32_t *>(ps.tgt_pyr + g.px_off);
+    j.src_norm = reinterpret_cast<const uint32_t *>(ps.src_pyr + g.norm_off);
+    j.tgt_norm = reinterpret_cast<const uint32_t *>(ps.tgt_pyr + g.norm_off);
+    j.h = g.h;
+    j.w = g.w;
+    j.pitch = g.pitch;
+    j.pair_id = ps.pair_id;
+    j.level = l;
+    return j;
+}
+
+std::string tune_key_of(const std::vector<PairSpec> &pairs, int p) {
+    std::string k = "p" + std::to_string(p);
+    int run = 0, ph = -1, pw = -1;
+    auto flush = [&]() {
+        if (run) k += ";" + std::to_string(ph) + "x" + std::to_string(pw) + "*" + std::to_string(run);
+    };
+    for (const PairSpec &ps : pairs) {
+        if (ps.L.lv[0].h != ph || ps.L.lv[0].w != pw) {
+            flush();
+            ph = ps.L.lv[0].h;
+            pw = ps.L.lv[0].w;
+            run = 0;
+        }
+        ++run;
+    }
+    flush();
+    return k;
+}
+
+// The whole coarse-to-fine PatchMatch of every pair (Algorithm 1), grouped by
+// level: a pair with K levels joins at pass Kmax - K, so at every pass all
+// active pairs sit at the same level number.
+void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, uint64_t seed,
+                     TileCfg cfg) {
+    int kmax = 0;
+    for (const PairSpec &ps : pairs) kmax = std::max(kmax, ps.L.levels);
+    std::vector<int> cur(pairs.size(), 0);
+    for (int t = 0; t < kmax; ++t) {
+        const int l = kmax - 1 - t;
+        std::vector<size_t> active;
+        for (size_t k = 0; k < pairs.size(); ++k)
+            if (pairs[k].L.levels > l) active.push_back(k);
+        if (active.empty()) continue;
+        std::vector<PMJob> js;
+        for (size_t k : active) {
+            PairSpec &ps = pairs[k];
+            PMJob j = job_geom(ps, l);
+            int dst;
+            if (l == ps.L.levels - 1) {
+                j.mode = ps.seed_offsets ? kStartOffsets : kStartRandom;
+                j.aux_off = ps.seed_offsets;
+                dst = 0;
+            } else {
+                j.mode = kStartUpsample;
+                j.f_in = ps.f[cur[k]];
+                j.hc = ps.L.lv[l + 1].h;
+                j.wc = ps.L.lv[l + 1].w;
+                dst = cur[k] ^ 1;
+            }
+            j.f_out = ps.f[dst];
+            j.e_out = ps.e[dst];
+            cur[k] = dst;
+            js.push_back(j);
+        }
+        add_pm_launch(P, kLaunchStart, js, cfg, p, seed, 0);
+        for (int it = 0; it < iters; ++it) {
+            js.clear();
+            for (size_t k : active) {
+                PairSpec &ps = pairs[k];
+                PMJob j = job_geom(ps, l);
+                j.f_in = ps.f[cur[k]];
+                j.e_in = ps.e[cur[k]];
+                j.f_out = ps.f[cur[k] ^ 1];
+                j.e_out = ps.e[cur[k] ^ 1];
+                cur[k] ^= 1;
+                js.push_back(j);
+            }
+            if (l == 0 && it == iters - 1) {
+                P.has_tune = true;
+                P.tune_jobs = js;
+                P.tune_iter = it;
+            }
+            add_pm_launch(P, kLaunchIter, js, cfg, p, seed, it);
+        }
+    }
+    std::vector<PMJob> ex;
+    for (size_t k = 0; k < pairs.size(); ++k) {
+        pairs[k].final_buf = cur[k];
+        if (!pairs[k].nnf_abi) continue;
+        PMJob j = job_geom(pairs[k], 0);
+        j.f_in = pairs[k].f[cur[k]];
+        j.e_in = pairs[k].e[cur[k]];
+        j.nnf_abi = pairs[k].nnf_abi;
+        j.energy_abi = pairs[k].energy_abi;
+        ex.push_back(j);
+    }
+    add_pm_launch(P, kLaunchExport, ex, cfg, p, seed, 0);
+    if (P.has_tune) P.tune_key = tune_key_of(pairs, p);
+}
+
+void add_remap_launch(Plan &P, const std::vector<RemapFrame> &frames,
+                      const std::vector<RemapTerm> &terms, int h, int w, int pitch, int p) {
+    const size_t toff = table_append(P, terms.data(), terms.size());
+    const size_t foff = table_append(P, frames.data(), frames.size());
+    const int nf = (int)frames.size();
+    sig_add(P, "remap", (long long)toff, (long long)foff, nf, ((long long)h << 32) | w);
+    P.ops.push_back([=](hipStream_t s, const uint8_t *tab) {
+        return launch_remap_sum(reinterpret_cast<const RemapFrame *>(tab + foff), nf,
+                                reinterpret_cast<const RemapTerm *>(tab + toff), h, w, pitch, p, s);
+    });
+}
+
+}  // namespace
+
+struct fb_ctx {
+    int device = 0;
+    Buf table;
+    std::vector<uint8_t> table_host;  // bytes currently in `table`
+    uint64_t table_gen = 0;
+    Buf pyr, style, fe, tune_table;
+    std::map<std::string, int> tuned;
+    int forced_cfg = -1;
+    std::string graph_sig;
+    uint64_t graph_gen = ~0ull;
+    hipStream_t graph_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+};
+
+namespace {
+
+fb_status ensure(fb_ctx *ctx, Buf &b, size_t n) {
+    if (b.n >= n) return FB_OK;
+    // buffers may be in use by enqueued work: wait for it before replacing
+    FB_HIP(hipDeviceSynchronize());
+    if (b.p) FB_HIP(hipFree(b.p));
+    b.p = nullptr;
+    b.n = 0;
+    n = std::max<size_t>(n, 256);
+    if (hipMalloc(&b.p, n) != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return fail(FB_E_ALLOC, "device allocation of " + std::to_string(n) + " bytes failed");
+    }
+    b.n = n;
+    ctx->table_host.clear();  // pointers inside an uploaded table may now be stale
+    return FB_OK;
+}
+
+TileCfg choose_cfg(fb_ctx *ctx, const std::string &key, uint32_t flags) {
+    if (ctx->forced_cfg >= 0) return tile_cfg(ctx->forced_cfg);
+    if (!(flags & FB_NO_AUTOTUNE)) {
+        auto it = ctx->tuned.find(key);
+        if (it != ctx->tuned.end()) return tile_cfg(it->second);
+    }
+    return tile_cfg(0);
+}
+
+// Re-run the plan's finest-level iteration launch with every tile shape and
+// keep the fastest.  That launch reads a buffer nothing later writes and
+// rewrites its output with identical values, so the timing runs are harmless.
+fb_status autotune(fb_ctx *ctx, Plan &P, hipStream_t s, int p, uint64_t seed) {
+    hipEvent_t e0, e1;
+    FB_HIP(hipEventCreate(&e0));
+    FB_HIP(hipEventCreate(&e1));
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int c = 0; c < n_tile_cfgs(); ++c) {
+        std::vector<PMJob> jobs = P.tune_jobs;
+        int total = 0, uniform = 0;
+        assign_tiles(jobs, tile_cfg(c), &total, &uniform);
+        fb_status st = ensure(ctx, ctx->tune_table, jobs.size() * sizeof(PMJob));
+        if (st) return st;
+        FB_HIP(hipStreamSynchronize(s));
+        FB_HIP(hipMemcpy(ctx->tune_table.p, jobs.data(), jobs.size() * sizeof(PMJob),
+                         hipMemcpyHostToDevice));
+        const PMJob *dj = reinterpret_cast<const PMJob *>(ctx->tune_table.p);
+        FB_HIP(launch_pm_iter(dj, (int)jobs.size(), total, uniform, tile_cfg(c), p, P.tune_iter, seed, s));
+        FB_HIP(hipEventRecord(e0, s));
+        for (int rep = 0; rep < 3; ++rep)
+            FB_HIP(launch_pm_iter(dj, (int)jobs.size(), total, uniform, tile_cfg(c), p, P.tune_iter, seed, s));
+        FB_HIP(hipEventRecord(e1, s));
+        FB_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        FB_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    FB_HIP(hipEventDestroy(e0));
+    FB_HIP(hipEventDestroy(e1));
+    ctx->tuned[P.tune_key] = best;
+    return FB_OK;
+}
+
+fb_status run_plan(fb_ctx *ctx, Plan &P, uint32_t flags, hipStream_t s, int p, uint64_t seed) {
+    if (P.table.empty()) P.table.resize(256);
+    if (P.table != ctx->table_host || ctx->table.n < P.table.size()) {
+        fb_status st = ensure(ctx, ctx->table, P.table.size());
+        if (st) return st;
+        // the previous table may still be read by enqueued launches
+        FB_HIP(hipDeviceSynchronize());
+        FB_HIP(hipMemcpy(ctx->table.p, P.table.data(), P.table.size(), hipMemcpyHostToDevice));
+        ctx->table_host = P.table;
+        ++ctx->table_gen;
+    }
+    const uint8_t *tab = static_cast<const uint8_t *>(ctx->table.p);
+    const bool tune = P.has_tune && ctx->forced_cfg < 0 && !(flags & FB_NO_AUTOTUNE) &&
+                      !ctx->tuned.count(P.tune_key);
+    if ((flags & FB_USE_GRAPH) && s != nullptr && !tune) {
+        if (!ctx->graph_exec || ctx->graph_gen != ctx->table_gen || ctx->graph_sig != P.sig ||
+            ctx->graph_stream != s) {
+            if (ctx->graph_exec) FB_HIP(hipGraphExecDestroy(ctx->graph_exec));
+            ctx->graph_exec = nullptr;
+            hipGraph_t g = nullptr;
+            FB_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            for (Op &op : P.ops) {
+                hipError_t e = op(s, tab);
+                if (e != hipSuccess) {
+                    hipGraph_t dummy = nullptr;
+                    (void)hipStreamEndCapture(s, &dummy);
+                    if (dummy) (void)hipGraphDestroy(dummy);
+                    return fail(FB_E_HIP, std::string("launch during capture: ") + hipGetErrorString(e));
+                }
+            }
+            FB_HIP(hipStreamEndCapture(s, &g));
+            hipError_t e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                ctx->graph_exec = nullptr;
+                return fail(FB_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+            ctx->graph_sig = P.sig;
+            ctx->graph_gen = ctx->table_gen;
+            ctx->graph_stream = s;
+        }
+        FB_HIP(hipGraphLaunch(ctx->graph_exec, s));
+        return FB_OK;
+    }
+    for (Op &op : P.ops) FB_HIP(op(s, tab));
+    if (tune) return autotune(ctx, P, s, p, seed);
+    return FB_OK;
+}
+
+bool valid_p(int p) { return p >= 1 && p <= kMaxP; }
+
+fb_status check_params(const fb_params *prm, bool need_levels) {
+    if (!prm) return fail(FB_E_INVALID, "params is NULL");
+    if (!valid_p(prm->patch_radius))
+        return fail(FB_E_UNSUPPORTED, "patch_radius must be in [1, 4]");
+    if (need_levels && (prm->levels < 1 || prm->levels > kMaxLevels))
+        return fail(FB_E_INVALID, "levels must be in [1, 16]");
+    if (prm->iters < 0 || prm->iters > 0xFFFE) return fail(FB_E_INVALID, "iters must be in [0, 65534]");
+    return FB_OK;
+}
+
+fb_status check_size(int h, int w) {
+    if (h < 1 || w < 1) return fail(FB_E_INVALID, "image sizes must be positive");
+    if (h > 32767 || w > 32767) return fail(FB_E_UNSUPPORTED, "image sides are limited to 32767");
+    return FB_OK;
+}
+
+fb_status begin(fb_ctx *ctx) {
+    if (!ctx) return fail(FB_E_INVALID, "ctx is NULL");
+    FB_HIP(hipSetDevice(ctx->device));
+    return FB_OK;
+}
+
+}  // namespace
+
+// ============================== C ABI ==================================
+
+extern "C" {
+
+fb_status fb_create(int32_t device, fb_ctx **out) {
+    if (!out) return fail(FB_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    FB_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(FB_E_INVALID, "no such device");
+    FB_HIP(hipSetDevice(device));
+    fb_ctx *c = new fb_ctx();
+    c->device = device;
+    *out = c;
+    return FB_OK;
+}
+
+void fb_destroy(fb_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    for (Buf *b : {&ctx->table, &ctx->pyr, &ctx->style, &ctx->fe, &ctx->tune_table})
+        if (b->p) (void)hipFree(b->p);
+    delete ctx;
+}
+
+const char *fb_last_error(void) { return g_err.c_str(); }
+
+int32_t fb_num_tile_configs(void) { return n_tile_cfgs(); }
+
+fb_status fb_set_tile_config(fb_ctx *ctx, int32_t index) {
+    if (!ctx) return fail(FB_E_INVALID, "ctx is NULL");
+    if (index < -1 || index >= n_tile_cfgs()) return fail(FB_E_INVALID, "no such tile config");
+    ctx->forced_cfg = index;
+    return FB_OK;
+}
+
+size_t fb_pyramid_bytes(int32_t h, int32_t w, int32_t levels, int32_t patch_radius) {
+    if (h < 1 || w < 1 || levels < 1 || levels > kMaxLevels || !valid_p(patch_radius)) return 0;
+    return pyr_layout(h, w, levels, patch_radius).bytes;
+}
+
+fb_status fb_build_pyramid(fb_ctx *ctx, const uint8_t *rgb, int32_t h, int32_t w, int32_t levels,
+                           int32_t patch_radius, void *pyr, void *stream) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!rgb || !pyr) return fail(FB_E_INVALID, "null pointer");
+    if ((st = check_size(h, w))) return st;
+    if (levels < 1 || levels > kMaxLevels) return fail(FB_E_INVALID, "levels must be in [1, 16]");
+    if (!valid_p(patch_radius)) return fail(FB_E_UNSUPPORTED, "patch_radius must be in [1, 4]");
+    const PyrLayout L = pyr_layout(h, w, levels, patch_radius);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    FB_HIP(launch_pack_level0(rgb, 0, 1, h, w, patch_radius, static_cast<uint8_t *>(pyr), 0,
+                              L.lv[0].px_off, L.lv[0].pitch, s));
+    for (int l = 1; l < levels; ++l)
+        FB_HIP(launch_downsample(static_cast<uint8_t *>(pyr), 0, 1, L.lv[l - 1], L.lv[l],
+                                 patch_radius, s));
+    for (int l = 0; l < levels; ++l)
+        FB_HIP(launch_norm(static_cast<uint8_t *>(pyr), 0, 1, L.lv[l], patch_radius, s));
+    return FB_OK;
+}
+
+fb_status fb_nnf_init(fb_ctx *ctx, const void *src_pyr, const void *tgt_pyr, int32_t h, int32_t w,
+                      int32_t level, const fb_params *params, uint32_t pair_id,
+                      const int32_t *seed_offsets, int32_t *nnf, uint32_t *energy, void *stream) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!src_pyr || !tgt_pyr || !nnf || !energy) return fail(FB_E_INVALID, "null pointer");
+    if ((st = check_size(h, w)) || (st = check_params(params, false))) return st;
+    if (level < 0 || level >= kMaxLevels) return fail(FB_E_INVALID, "level must be in [0, 15]");
+    const int p = params->patch_radius;
+    const PyrLayout L = pyr_layout(h, w, level + 1, p);
+    const size_t npx = (size_t)L.lv[level].h * L.lv[level].w;
+    if ((st = ensure(ctx, ctx->fe, npx * 8))) return st;
+    uint32_t *f = static_cast<uint32_t *>(ctx->fe.p), *e = f + npx;
+    PairSpec ps{};
+    ps.src_pyr = static_cast<const uint8_t *>(src_pyr);
+    ps.tgt_pyr = static_cast<const uint8_t *>(tgt_pyr);
+    ps.L = L;
+    ps.pair_id = pair_id;
+    Plan P;
+    const TileCfg cfg = choose_cfg(ctx, "", FB_NO_AUTOTUNE);
+    PMJob j = job_geom(ps, level);
+    j.mode = seed_offsets ? kStartOffsets : kStartRandom;
+    j.aux_off = seed_offsets;
+    j.f_out = f;
+    j.e_out = e;
+    add_pm_launch(P, kLaunchStart, {j}, cfg, p, params->seed, 0);
+    j = job_geom(ps, level);
+    j.f_in = f;
+    j.e_in = e;
+    j.nnf_abi = nnf;
+    j.energy_abi = energy;
+    add_pm_launch(P, kLaunchExport, {j}, cfg, p, params->seed, 0);
+    return run_plan(ctx, P, params->flags, static_cast<hipStream_t>(stream), p, params->seed);
+}
+
+fb_status fb_patchmatch_level(fb_ctx *ctx, const void *src_pyr, const void *tgt_pyr, int32_t h,
+                              int32_t w, int32_t level, const fb_params *params, uint32_t pair_id,
+                              const int32_t *nnf_coarse, int32_t *nnf, uint32_t *energy,
+                              void *stream) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!src_pyr || !tgt_pyr || !nnf || !energy) return fail(FB_E_INVALID, "null pointer");
+    if ((st = check_size(h, w)) || (st = check_params(params, false))) return st;
+    if (level < 0 || level >= kMaxLevels - 1) return fail(FB_E_INVALID, "level must be in [0, 14]");
+    const int p = params->patch_radius;
+    const PyrLayout L = pyr_layout(h, w, level + 2, p);  // level + 1 for the coarse size only
+    const size_t npx = (size_t)L.lv[level].h * L.lv[level].w;
+    if ((st = ensure(ctx, ctx->fe, npx * 16))) return st;
+    uint32_t *base = static_cast<uint32_t *>(ctx->fe.p);
+    PairSpec ps{};
+    ps.src_pyr = static_cast<const uint8_t *>(src_pyr);
+    ps.tgt_pyr = static_cast<const uint8_t *>(tgt_pyr);
+    ps.L = L;
+    ps.pair_id = pair_id;
+    ps.f[0] = base;
+    ps.f[1] = base + npx;
+    ps.e[0] = base + 2 * npx;
+    ps.e[1] = base + 3 * npx;
+    Plan P;
+    const TileCfg cfg = choose_cfg(ctx, "", FB_NO_AUTOTUNE);
+    PMJob j = job_geom(ps, level);
+    if (nnf_coarse) {
+        j.mode = kStartUpsampleAbi;
+        j.aux_off = nnf_coarse;
+        j.hc = L.lv[level + 1].h;
+        j.wc = L.lv[level + 1].w;
+    } else {
+        j.mode = kStartCopyAbi;
+        j.aux_off = nnf;
+        j.e_abi = energy;
+    }
+    j.f_out = ps.f[0];
+    j.e_out = ps.e[0];
+    add_pm_launch(P, kLaunchStart, {j}, cfg, p, params->seed, 0);
+    int cur = 0;
+    for (int it = 0; it < params->iters; ++it) {
+        j = job_geom(ps, level);
+        j.f_in = ps.f[cur];
+        j.e_in = ps.e[cur];
+        j.f_out = ps.f[cur ^ 1];
+        j.e_out = ps.e[cur ^ 1];
+        cur ^= 1;
+        add_pm_launch(P, kLaunchIter, {j}, cfg, p, params->seed, it);
+    }
+    j = job_geom(ps, level);
+    j.f_in = ps.f[cur];
+    j.e_in = ps.e[cur];
+    j.nnf_abi = nnf;
+    j.energy_abi = energy;
+    add_pm_launch(P, kLaunchExport, {j}, cfg, p, params->seed, 0);
+    return run_plan(ctx, P, params->flags, static_cast<hipStream_t>(stream), p, params->seed);
+}
+
+fb_status fb_remap(fb_ctx *ctx, const uint8_t *style, const int32_t *nnf, int32_t h, int32_t w,
+                   int32_t patch_radius, float *out, void *stream) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!style || !nnf || !out) return fail(FB_E_INVALID, "null pointer");
+    if ((st = check_size(h, w))) return st;
+    if (!valid_p(patch_radius)) return fail(FB_E_UNSUPPORTED, "patch_radius must be in [1, 4]");
+    const int p = patch_radius;
+    int32_t pitch = 0;
+    const size_t sbytes = padded_image_bytes(h, w, p, &pitch);
+    const size_t npx = (size_t)h * w;
+    if ((st = ensure(ctx, ctx->style, sbytes)) || (st = ensure(ctx, ctx->fe, npx * 4))) return st;
+    uint8_t *sty = static_cast<uint8_t *>(ctx->style.p);
+    uint32_t *f = static_cast<uint32_t *>(ctx->fe.p);
+    Plan P;
+    plan_style_pack(P, style, 1, h, w, p, sty, sbytes, pitch);
+    sig_add(P, "f2p", (long long)(uintptr_t)nnf, h, w, (long long)(uintptr_t)f);
+    P.ops.push_back([=](hipStream_t s, const uint8_t *) {
+        return launch_field_to_packed(nnf, f, h, w, s);
+    });
+    RemapTerm t{reinterpret_cast<const uint32_t *>(sty), f, 1.0f, 0};
+    RemapFrame fr{out, 0, 1, 1.0f, 0};
+    add_remap_launch(P, {fr}, {t}, h, w, pitch, p);
+    return run_plan(ctx, P, 0, static_cast<hipStream_t>(stream), p, 0);
+}
+
+fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, int32_t n_frames,
+                          int32_t h, int32_t w, int32_t radius_M, const fb_params *params,
+                          float *out, void *stream) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!guides || !styles || !out) return fail(FB_E_INVALID, "null pointer");
+    if ((st = check_size(h, w)) || (st = check_params(params, true))) return st;
+    if (n_frames < 1) return fail(FB_E_INVALID, "n_frames must be >= 1");
+    if (radius_M < 0) return fail(FB_E_INVALID, "radius_M must be >= 0");
+    const int N = n_frames, M = radius_M, p = params->patch_radius, K = params->levels;
+    if ((uint64_t)N * (uint64_t)N > 0xFFFFFFFFull) return fail(FB_E_UNSUPPORTED, "pair ids j*N+i must fit in 32 bits");
+    const PyrLayout L = pyr_layout(h, w, K, p);
+    int32_t pitch = 0;
+    const size_t sbytes = padded_image_bytes(h, w, p, &pitch);
+    const size_t npx = (size_t)h * w;
+    size_t n_pairs = 0;
+    for (int i = 0; i < N; ++i) n_pairs += (size_t)(std::min(N - 1, i + M) - std::max(0, i - M));
+    if ((st = ensure(ctx, ctx->pyr, (size_t)N * L.bytes)) ||
+        (st = ensure(ctx, ctx->style, (size_t)N * sbytes)) ||
+        (st = ensure(ctx, ctx->fe, std::max<size_t>(n_pairs, 1) * npx * 16)))
+        return st;
+    uint8_t *pyr = static_cast<uint8_t *>(ctx->pyr.p);
+    uint8_t *sty = static_cast<uint8_t *>(ctx->style.p);
+    uint32_t *fe = static_cast<uint32_t *>(ctx->fe.p);
+
+    Plan P;
+    plan_pyramids(P, guides, N, h, w, L, pyr, L.bytes);
+    plan_style_pack(P, styles, N, h, w, p, sty, sbytes, pitch);
+    std::vector<PairSpec> pairs;
+    pairs.reserve(n_pairs);
+    for (int i = 0; i < N; ++i)
+        for (int j = std::max(0, i - M); j <= std::min(N - 1, i + M); ++j) {
+            if (j == i) continue;
+            const size_t k = pairs.size();
+            PairSpec ps{};
+            ps.src_pyr = pyr + (size_t)j * L.bytes;
+            ps.tgt_pyr = pyr + (size_t)i * L.bytes;
+            ps.L = L;
+            ps.pair_id = (uint32_t)j * (uint32_t)N + (uint32_t)i;
+            ps.f[0] = fe + k * npx;
+            ps.f[1] = fe + (n_pairs + k) * npx;
+            ps.e[0] = fe + (2 * n_pairs + k) * npx;
+            ps.e[1] = fe + (3 * n_pairs + k) * npx;
+            pairs.push_back(ps);
+        }
+    const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
+    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg);
+
+    std::vector<RemapTerm> terms;
+    std::vector<RemapFrame> frames;
+    size_t k = 0;
+    for (int i = 0; i < N; ++i) {
+        const int lo = std::max(0, i - M), hi = std::min(N - 1, i + M);
+        RemapFrame fr{out + (size_t)i * npx * 3, (int32_t)terms.size(), hi - lo + 1,
+                      (float)(hi - lo + 1), 0};
+        for (int j = lo; j <= hi; ++j) {
+            const uint32_t *spx = reinterpret_cast<const uint32_t *>(sty + (size_t)j * sbytes);
+            if (j == i) {
+                terms.push_back(RemapTerm{spx, nullptr, 1.0f, 0});
+            } else {
+                terms.push_back(RemapTerm{spx, pairs[k].f[pairs[k].final_buf], 1.0f, 0});
+                ++k;
+            }
+        }
+        frames.push_back(fr);
+    }
+    add_remap_launch(P, frames, terms, h, w, pitch, p);
+    return run_plan(ctx, P, params->flags, static_cast<hipStream_t>(stream), p, params->seed);
+}
+
+fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, int32_t h, int32_t w,
+                         const int32_t *key_idx, const uint8_t *key_styles, int32_t n_keys,
+                         const fb_params *params, float *out, void *stream) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!guides || !key_idx || !key_styles || !out) return fail(FB_E_INVALID, "null pointer");
+    if ((st = check_size(h, w)) || (st = check_params(params, true))) return st;
+    if (n_frames < 1 || n_keys < 1) return fail(FB_E_INVALID, "need n_frames >= 1 and n_keys >= 1");
+    for (int k = 0; k < n_keys; ++k) {
+        if (key_idx[k] < 0 || key_idx[k] >= n_frames) return fail(FB_E_INVALID, "key index out of range");
+        if (k && key_idx[k] <= key_idx[k - 1]) return fail(FB_E_INVALID, "key indices must be sorted and unique");
+    }
+    const int N = n_frames, p = params->patch_radius, K = params->levels;
+    if ((uint64_t)N * (uint64_t)N > 0xFFFFFFFFull) return fail(FB_E_UNSUPPORTED, "pair ids key*N+i must fit in 32 bits");
+    const PyrLayout L = pyr_layout(h, w, K, p);
+    int32_t pitch = 0;
+    const size_t sbytes = padded_image_bytes(h, w, p, &pitch);
+    const size_t npx = (size_t)h * w;
+    // bracketing keys of every frame
+    std::vector<int> kl(N, -1), kr(N, -1), kself(N, -1);
+    for (int i = 0; i < N; ++i)
+        for (int k = 0; k < n_keys; ++k) {
+            if (key_idx[k] == i) kself[i] = k;
+            if (key_idx[k] < i) kl[i] = k;
+            if (key_idx[k] > i && kr[i] < 0) kr[i] = k;
+        }
+    size_t n_pairs = 0;
+    for (int i = 0; i < N; ++i)
+        if (kself[i] < 0) n_pairs += (kl[i] >= 0) + (kr[i] >= 0);
+    if ((st = ensure(ctx, ctx->pyr, (size_t)N * L.bytes)) ||
+        (st = ensure(ctx, ctx->style, (size_t)n_keys * sbytes)) ||
+        (st = ensure(ctx, ctx->fe, std::max<size_t>(n_pairs, 1) * npx * 16)))
+        return st;
+    uint8_t *pyr = static_cast<uint8_t *>(ctx->pyr.p);
+    uint8_t *sty = static_cast<uint8_t *>(ctx->style.p);
+    uint32_t *fe = static_cast<uint32_t *>(ctx->fe.p);
+
+    Plan P;
+    plan_pyramids(P, guides, N, h, w, L, pyr, L.bytes);
+    plan_style_pack(P, key_styles, n_keys, h, w, p, sty, sbytes, pitch);
+    std::vector<PairSpec> pairs;
+    std::vector<int> pair_key;
+    for (int i = 0; i < N; ++i) {
+        if (kself[i] >= 0) continue;
+        for (int side = 0; side < 2; ++side) {
+            const int k = side == 0 ? kl[i] : kr[i];
+            if (k < 0) continue;
+            const size_t q = pairs.size();
+            PairSpec ps{};
+            ps.src_pyr = pyr + (size_t)key_idx[k] * L.bytes;
+            ps.tgt_pyr = pyr + (size_t)i * L.bytes;
+            ps.L = L;
+            ps.pair_id = (uint32_t)key_idx[k] * (uint32_t)N + (uint32_t)i;
+            ps.f[0] = fe + q * npx;
+            ps.f[1] = fe + (n_pairs + q) * npx;
+            ps.e[0] = fe + (2 * n_pairs + q) * npx;
+            ps.e[1] = fe + (3 * n_pairs + q) * npx;
+            pairs.push_back(ps);
+            pair_key.push_back(k);
+        }
+    }
+    const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
+    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg);
+
+    std::vector<RemapTerm> terms;
+    std::vector<RemapFrame> frames;
+    size_t q = 0;
+    for (int i = 0; i < N; ++i) {
+        RemapFrame fr{out + (size_t)i * npx * 3, (int32_t)terms.size(), 0, 1.0f, 0};
+        if (kself[i] >= 0) {
+            terms.push_back(RemapTerm{reinterpret_cast<const uint32_t *>(sty + (size_t)kself[i] * sbytes),
+                                      nullptr, 1.0f, 0});
+        } else {
+            const bool both = kl[i] >= 0 && kr[i] >= 0;
+            const int l = both ? key_idx[kl[i]] : 0, r = both ? key_idx[kr[i]] : 0;
+            for (int side = 0; side < 2; ++side) {
+                const int k = side == 0 ? kl[i] : kr[i];
+                if (k < 0) continue;
+                float wgt = 1.0f;
+                if (both) wgt = side == 0 ? (float)(r - i) / (float)(r - l) : (float)(i - l) / (float)(r - l);
+                terms.push_back(RemapTerm{reinterpret_cast<const uint32_t *>(sty + (size_t)pair_key[q] * sbytes),
+                                          pairs[q].f[pairs[q].final_buf], wgt, 0});
+                ++q;
+            }
+        }
+        fr.n_terms = (int32_t)terms.size() - fr.term_base;
+        frames.push_back(fr);
+    }
+    add_remap_launch(P, frames, terms, h, w, pitch, p);
+    return run_plan(ctx, P, params->flags, static_cast<hipStream_t>(stream), p, params->seed);
+}
+
+fb_status fb_patchmatch_batch(fb_ctx *ctx, const fb_pair_desc *pairs_in, int32_t n_pairs,
+                              const fb_params *params, void *stream) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!pairs_in || n_pairs < 1) return fail(FB_E_INVALID, "need n_pairs >= 1 descriptors");
+    if ((st = check_params(params, false))) return st;
+    const int p = params->patch_radius;
+    size_t total_px = 0;
+    for (int k = 0; k < n_pairs; ++k) {
+        const fb_pair_desc &d = pairs_in[k];
+        if (!d.src_pyr || !d.tgt_pyr || !d.nnf || !d.energy) return fail(FB_E_INVALID, "null pointer in pair descriptor");
+        if ((st = check_size(d.h, d.w))) return st;
+        if (d.levels < 1 || d.levels > kMaxLevels) return fail(FB_E_INVALID, "levels must be in [1, 16]");
+        total_px += (size_t)d.h * d.w;
+    }
+    if ((st = ensure(ctx, ctx->fe, total_px * 16))) return st;
+    uint32_t *fe = static_cast<uint32_t *>(ctx->fe.p);
+    std::vector<PairSpec> pairs;
+    size_t off = 0;
+    for (int k = 0; k < n_pairs; ++k) {
+        const fb_pair_desc &d = pairs_in[k];
+        PairSpec ps{};
+        ps.src_pyr = static_cast<const uint8_t *>(d.src_pyr);
+        ps.tgt_pyr = static_cast<const uint8_t *>(d.tgt_pyr);
+        ps.L = pyr_layout(d.h, d.w, d.levels, p);
+        ps.pair_id = d.pair_id;
+        ps.seed_offsets = d.seed_offsets;
+        ps.f[0] = fe + off;
+        ps.f[1] = fe + total_px + off;
+        ps.e[0] = fe + 2 * total_px + off;
+        ps.e[1] = fe + 3 * total_px + off;
+        ps.nnf_abi = d.nnf;
+        ps.energy_abi = d.energy;
+        off += (size_t)d.h * d.w;
+        pairs.push_back(ps);
+    }
+    const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
+    Plan P;
+    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg);
+    return run_plan(ctx, P, params->flags, static_cast<hipStream_t>(stream), p, params->seed);
+}
+
+}  // extern "C"

@@ -1,0 +1,261 @@
+"""Thin Python binding of the FastBlend C ABI (``include/fastblend.h``).
+
+Only argument marshalling happens here: tensors are checked (device, dtype,
+shape, contiguity) and their device pointers, together with the current HIP
+stream of PyTorch, are handed to ``libfastblend.so``.  Every step of the hot
+path runs in the library's HIP kernels.  If the library is not built, every
+call raises; there is no fallback.
+
+The function names are the C names (``fb_nnf_init`` ...), taking tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfastblend.so")
+
+FB_OK = 0
+FB_USE_GRAPH = 0x1
+FB_NO_AUTOTUNE = 0x2
+STATUS = {0: "FB_OK", -1: "FB_E_INVALID", -2: "FB_E_SHAPE", -3: "FB_E_UNSUPPORTED",
+          -4: "FB_E_ALLOC", -5: "FB_E_HIP"}
+
+
+class FastBlendError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__("%s: %s (%s)" % (where, STATUS.get(status, status), msg))
+        self.status = status
+
+
+class fb_params(ctypes.Structure):
+    _fields_ = [("patch_radius", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+class fb_pair_desc(ctypes.Structure):
+    _fields_ = [("src_pyr", ctypes.c_void_p), ("tgt_pyr", ctypes.c_void_p),
+                ("h", ctypes.c_int32), ("w", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("pair_id", ctypes.c_uint32), ("seed_offsets", ctypes.c_void_p),
+                ("nnf", ctypes.c_void_p), ("energy", ctypes.c_void_p)]
+
+
+_lib = None
+_EXPORTS = ["fb_create", "fb_destroy", "fb_last_error", "fb_num_tile_configs", "fb_set_tile_config",
+            "fb_pyramid_bytes", "fb_build_pyramid", "fb_nnf_init", "fb_patchmatch_level", "fb_remap",
+            "fb_blend_window", "fb_interpolate", "fb_patchmatch_batch"]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load ``libfastblend.so`` and declare its signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libfastblend.so is not built (%s); run __graft_entry__.build()" % path)
+    L = ctypes.CDLL(path)
+    vp, i32, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
+    P = ctypes.POINTER(fb_params)
+    sig = {
+        "fb_create": (i32, [i32, ctypes.POINTER(vp)]),
+        "fb_destroy": (None, [vp]),
+        "fb_last_error": (ctypes.c_char_p, []),
+        "fb_num_tile_configs": (i32, []),
+        "fb_set_tile_config": (i32, [vp, i32]),
+        "fb_pyramid_bytes": (sz, [i32, i32, i32, i32]),
+        "fb_build_pyramid": (i32, [vp, vp, i32, i32, i32, i32, vp, vp]),
+        "fb_nnf_init": (i32, [vp, vp, vp, i32, i32, i32, P, u32, vp, vp, vp, vp]),
+        "fb_patchmatch_level": (i32, [vp, vp, vp, i32, i32, i32, P, u32, vp, vp, vp, vp]),
+        "fb_remap": (i32, [vp, vp, vp, i32, i32, i32, vp, vp]),
+        "fb_blend_window": (i32, [vp, vp, vp, i32, i32, i32, i32, P, vp, vp]),
+        "fb_interpolate": (i32, [vp, vp, i32, i32, i32, vp, vp, i32, P, vp, vp]),
+        "fb_patchmatch_batch": (i32, [vp, ctypes.POINTER(fb_pair_desc), i32, P, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != FB_OK:
+        msg = load_library().fb_last_error()
+        raise FastBlendError(status, where, msg.decode() if msg else "")
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _dev(t: Optional[torch.Tensor], name: str, dtype=None, shape=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a GPU tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_pyr(pyr: torch.Tensor, name: str, h: int, w: int, levels: int, patch_radius: int):
+    need = load_library().fb_pyramid_bytes(h, w, levels, patch_radius)
+    if need == 0 or pyr.numel() < need:
+        raise ValueError("%s holds %d bytes, a %d-level pyramid of %dx%d needs %d"
+                         % (name, pyr.numel(), levels, h, w, need))
+
+
+def make_params(patch_radius: int = 2, levels: int = 3, iters: int = 6, seed: int = 0,
+                flags: int = 0) -> fb_params:
+    return fb_params(patch_radius, levels, iters, flags, seed & 0xFFFFFFFFFFFFFFFF)
+
+
+def level_size(h: int, w: int, level: int):
+    return -(-h // (1 << level)), -(-w // (1 << level))
+
+
+class Context:
+    """An ``fb_ctx`` on one device (workspace, plans, graphs, autotuning)."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        _check(load_library().fb_create(device, ctypes.byref(h)), "fb_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            load_library().fb_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---- tuning ---------------------------------------------------------
+    def fb_set_tile_config(self, index: int):
+        _check(load_library().fb_set_tile_config(self.handle, index), "fb_set_tile_config")
+
+    # ---- pyramid --------------------------------------------------------
+    def fb_build_pyramid(self, rgb: torch.Tensor, levels: int, patch_radius: int = 2) -> torch.Tensor:
+        h, w = rgb.shape[:2]
+        _dev(rgb, "rgb", torch.uint8, (h, w, 3))
+        nbytes = load_library().fb_pyramid_bytes(h, w, levels, patch_radius)
+        if nbytes == 0:
+            raise ValueError("invalid pyramid parameters")
+        pyr = torch.empty(nbytes, dtype=torch.uint8, device=rgb.device)
+        _check(load_library().fb_build_pyramid(self.handle, _dev(rgb, "rgb"), h, w, levels, patch_radius,
+                                               _dev(pyr, "pyr"), _stream(rgb)), "fb_build_pyramid")
+        return pyr
+
+    # ---- per-pair PatchMatch ------------------------------------------------
+    def fb_nnf_init(self, src_pyr, tgt_pyr, h: int, w: int, level: int, params: fb_params,
+                    pair_id: int, seed_offsets: Optional[torch.Tensor] = None):
+        hl, wl = level_size(h, w, level)
+        _check_pyr(src_pyr, "src_pyr", h, w, level + 1, params.patch_radius)
+        _check_pyr(tgt_pyr, "tgt_pyr", h, w, level + 1, params.patch_radius)
+        nnf = torch.empty((hl, wl, 2), dtype=torch.int32, device=src_pyr.device)
+        energy = torch.empty((hl, wl), dtype=torch.int32, device=src_pyr.device)
+        _check(load_library().fb_nnf_init(
+            self.handle, _dev(src_pyr, "src_pyr", torch.uint8), _dev(tgt_pyr, "tgt_pyr", torch.uint8),
+            h, w, level, ctypes.byref(params), pair_id,
+            _dev(seed_offsets, "seed_offsets", torch.int32, (hl, wl, 2)),
+            _dev(nnf, "nnf"), _dev(energy, "energy"), _stream(src_pyr)), "fb_nnf_init")
+        return nnf, energy
+
+    def fb_patchmatch_level(self, src_pyr, tgt_pyr, h: int, w: int, level: int, params: fb_params,
+                            pair_id: int, nnf: Optional[torch.Tensor] = None,
+                            energy: Optional[torch.Tensor] = None,
+                            nnf_coarse: Optional[torch.Tensor] = None):
+        """Returns (nnf, energy) at ``level``; nnf/energy (int32) are updated in place if given."""
+        hl, wl = level_size(h, w, level)
+        _check_pyr(src_pyr, "src_pyr", h, w, level + 1, params.patch_radius)
+        _check_pyr(tgt_pyr, "tgt_pyr", h, w, level + 1, params.patch_radius)
+        if nnf is None:
+            nnf = torch.empty((hl, wl, 2), dtype=torch.int32, device=src_pyr.device)
+            energy = torch.empty((hl, wl), dtype=torch.int32, device=src_pyr.device)
+        if nnf_coarse is None and energy is None:
+            raise ValueError("need nnf_coarse, or a starting nnf and energy")
+        hc, wc = level_size(h, w, level + 1)
+        _check(load_library().fb_patchmatch_level(
+            self.handle, _dev(src_pyr, "src_pyr", torch.uint8), _dev(tgt_pyr, "tgt_pyr", torch.uint8),
+            h, w, level, ctypes.byref(params), pair_id,
+            _dev(nnf_coarse, "nnf_coarse", torch.int32, (hc, wc, 2)),
+            _dev(nnf, "nnf", torch.int32, (hl, wl, 2)), _dev(energy, "energy", torch.int32, (hl, wl)),
+            _stream(src_pyr)), "fb_patchmatch_level")
+        return nnf, energy
+
+    # ---- remap / blend / interpolate --------------------------------------
+    def fb_remap(self, style: torch.Tensor, nnf: torch.Tensor, patch_radius: int = 2) -> torch.Tensor:
+        h, w = style.shape[:2]
+        out = torch.empty((h, w, 3), dtype=torch.float32, device=style.device)
+        _check(load_library().fb_remap(self.handle, _dev(style, "style", torch.uint8, (h, w, 3)),
+                                       _dev(nnf, "nnf", torch.int32, (h, w, 2)), h, w, patch_radius,
+                                       _dev(out, "out"), _stream(style)), "fb_remap")
+        return out
+
+    def fb_blend_window(self, guides: torch.Tensor, styles: torch.Tensor, radius_M: int,
+                        params: fb_params, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        n, h, w = guides.shape[:3]
+        if out is None:
+            out = torch.empty((n, h, w, 3), dtype=torch.float32, device=guides.device)
+        _check(load_library().fb_blend_window(
+            self.handle, _dev(guides, "guides", torch.uint8, (n, h, w, 3)),
+            _dev(styles, "styles", torch.uint8, (n, h, w, 3)), n, h, w, radius_M, ctypes.byref(params),
+            _dev(out, "out", torch.float32, (n, h, w, 3)), _stream(guides)), "fb_blend_window")
+        return out
+
+    def fb_interpolate(self, guides: torch.Tensor, key_idx: Sequence[int], key_styles: torch.Tensor,
+                       params: fb_params, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        n, h, w = guides.shape[:3]
+        keys = (ctypes.c_int32 * len(key_idx))(*[int(k) for k in key_idx])
+        if out is None:
+            out = torch.empty((n, h, w, 3), dtype=torch.float32, device=guides.device)
+        _check(load_library().fb_interpolate(
+            self.handle, _dev(guides, "guides", torch.uint8, (n, h, w, 3)), n, h, w,
+            ctypes.cast(keys, ctypes.c_void_p),
+            _dev(key_styles, "key_styles", torch.uint8, (len(key_idx), h, w, 3)), len(key_idx),
+            ctypes.byref(params), _dev(out, "out", torch.float32, (n, h, w, 3)), _stream(guides)),
+            "fb_interpolate")
+        return out
+
+    def fb_patchmatch_batch(self, pairs: Sequence[dict], params: fb_params):
+        """pairs: dicts with src_pyr, tgt_pyr, h, w, levels, pair_id[, seed_offsets].
+        Returns a list of (nnf int32 [h][w][2], energy int32 [h][w])."""
+        descs = (fb_pair_desc * len(pairs))()
+        outs, keep = [], []
+        for k, d in enumerate(pairs):
+            h, w = d["h"], d["w"]
+            dev = d["src_pyr"].device
+            _check_pyr(d["src_pyr"], "src_pyr", h, w, d["levels"], params.patch_radius)
+            _check_pyr(d["tgt_pyr"], "tgt_pyr", h, w, d["levels"], params.patch_radius)
+            nnf = torch.empty((h, w, 2), dtype=torch.int32, device=dev)
+            energy = torch.empty((h, w), dtype=torch.int32, device=dev)
+            so = d.get("seed_offsets")
+            hc, wc = level_size(h, w, d["levels"] - 1)
+            descs[k] = fb_pair_desc(_dev(d["src_pyr"], "src_pyr", torch.uint8),
+                                    _dev(d["tgt_pyr"], "tgt_pyr", torch.uint8), h, w, d["levels"],
+                                    d["pair_id"], _dev(so, "seed_offsets", torch.int32, (hc, wc, 2)),
+                                    _dev(nnf, "nnf"), _dev(energy, "energy"))
+            outs.append((nnf, energy))
+            keep.append(so)
+        _check(load_library().fb_patchmatch_batch(self.handle, descs, len(pairs), ctypes.byref(params),
+                                                   _stream(pairs[0]["src_pyr"])), "fb_patchmatch_batch")
+        return outs

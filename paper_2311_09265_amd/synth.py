@@ -150,9 +150,11 @@ def sprite_video(n: int, h: int, w: int, seed: int, n_sprites: int = 6,
     bg = value_noise(h, bw, seed ^ 0xB6)
     speeds = np.array([v for v in range(-vmax, vmax + 1) if v != 0])
     sprites: List[_Sprite] = []
+    # sprite sides are limited to the frame (small test frames)
+    lo_h, lo_w = max(1, min(side[0], h // 3)), max(1, min(side[0], w // 3))
     for k in range(n_sprites):
-        sh = int(rng.integers(side[0], min(side[1], h - 1) + 1))
-        sw = int(rng.integers(side[0], min(side[1], w - 1) + 1))
+        sh = int(rng.integers(lo_h, max(lo_h, min(side[1], h - 1)) + 1))
+        sw = int(rng.integers(lo_w, max(lo_w, min(side[1], w - 1)) + 1))
         sprites.append(_Sprite(sh, sw, float(rng.integers(0, h - sh + 1)),
                                float(rng.integers(0, w - sw + 1)),
                                int(rng.choice(speeds)), int(rng.choice(speeds)),

@@ -1,0 +1,69 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/fastblend.h declares, and its host-only entry points behave
+(no GPU call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fastblend.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fb_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2311_09265_amd import build, fastblend
+    if not os.path.exists(fastblend.LIB_PATH):
+        build.build()
+    return fastblend.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 12, names
+    raw = ctypes.CDLL(os.path.join(ROOT, "paper_2311_09265_amd", "libfastblend.so"))
+    missing = [n for n in names if not hasattr(raw, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header(lib):
+    from paper_2311_09265_amd import fastblend
+    assert set(_declared()) == set(fastblend._EXPORTS)
+
+
+def test_pyramid_bytes_layout(lib):
+    # level l: (h_l + 2p) rows x pitch (w_l + 2p rounded up to 16 pixels) x 4 bytes,
+    # then an h_l x w_l uint32 norm image, each block 256-byte aligned
+    def expect(h, w, levels, p):
+        off = 0
+        for l in range(levels):
+            hl, wl = -(-h // (1 << l)), -(-w // (1 << l))
+            pitch = -(-(wl + 2 * p) // 16) * 16
+            off += (hl + 2 * p) * pitch * 4
+            off = -(-off // 256) * 256
+            off += hl * wl * 4
+            off = -(-off // 256) * 256
+        return off
+    for args in [(64, 64, 1, 2), (512, 512, 3, 2), (576, 1024, 4, 2), (37, 53, 3, 1), (5, 3, 2, 4)]:
+        assert lib.fb_pyramid_bytes(*args) == expect(*args), args
+    # invalid arguments give 0
+    assert lib.fb_pyramid_bytes(0, 5, 1, 2) == 0
+    assert lib.fb_pyramid_bytes(5, 5, 17, 2) == 0
+    assert lib.fb_pyramid_bytes(5, 5, 1, 5) == 0
+
+
+def test_null_context_is_rejected_without_gpu(lib):
+    from paper_2311_09265_amd import fastblend as fbm
+    prm = fbm.make_params()
+    st = lib.fb_blend_window(None, None, None, 4, 8, 8, 1, ctypes.byref(prm), None, None)
+    assert st == -1
+    assert b"ctx" in lib.fb_last_error()
+    assert lib.fb_num_tile_configs() >= 2
+    assert lib.fb_set_tile_config(None, 0) == -1

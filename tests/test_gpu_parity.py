@@ -1,0 +1,233 @@
+"""GPU parity: the HIP library through its C ABI against the CPU oracle.
+
+NNFs and energies must be bit-exact; remapped, blended and interpolated
+frames within 1e-5 max abs in fp32 on [0, 1].  Sizes are small enough for the
+oracle to finish in seconds, yet span several 64x4 tiles with ragged tails.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2311_09265_amd import fastblend as fbm
+from paper_2311_09265_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = fbm.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def assert_field_equal(nnf, energy, F, E, what=""):
+    n, e = host(nnf), host(energy).astype(np.int64)
+    bad = np.argwhere((n != F).any(axis=-1) | (e != E.astype(np.int64)))
+    assert bad.size == 0, "%s: %d pixels differ, first %s gpu %s/%d oracle %s/%d" % (
+        what, len(bad), bad[0], n[tuple(bad[0])], e[tuple(bad[0])], F[tuple(bad[0])], E[tuple(bad[0])])
+
+
+def pair_images(h, w, seed, kind="sprites"):
+    if kind == "noise" or min(h, w) < 16:
+        rng = np.random.default_rng(seed)
+        a = rng.integers(0, 256, (h, w, 3)).astype(np.uint8)
+        b = rng.integers(0, 256, (h, w, 3)).astype(np.uint8)
+        return a, b
+    v = synth.sprite_video(3, h, w, seed, n_sprites=2, side=(max(2, min(h, w) // 6), max(3, min(h, w) // 3)))
+    return v[0], v[2]
+
+
+def test_config1_translation_pair(ctx):
+    """64x64 value-noise pair shifted by (3,-2) + noise, 1 level, 5 iterations."""
+    A, B, _ = synth.translation_pair(synth.CONFIG_SEED[1])
+    seed = synth.PHILOX_SEED[1]
+    prm = fbm.make_params(2, 1, 5, seed)
+    F, E = oracle.patchmatch(A, B, 2, 1, 5, seed, 0)
+    pa, pb = ctx.fb_build_pyramid(dev(A), 1), ctx.fb_build_pyramid(dev(B), 1)
+    (nnf, en), = ctx.fb_patchmatch_batch([dict(src_pyr=pa, tgt_pyr=pb, h=64, w=64, levels=1, pair_id=0)], prm)
+    assert_field_equal(nnf, en, F, E, "batch")
+    n0, e0 = ctx.fb_nnf_init(pa, pb, 64, 64, 0, prm, 0)
+    F0, E0 = oracle.nnf_init_random(A, B, 2, 0, seed, 0)
+    assert_field_equal(n0, e0, F0, E0, "init")
+    n1, e1 = ctx.fb_patchmatch_level(pa, pb, 64, 64, 0, prm, 0, nnf=n0, energy=e0)
+    assert_field_equal(n1, e1, F, E, "level")
+
+
+@pytest.mark.parametrize("h,w,levels,p,iters", [
+    (37, 53, 3, 2, 3), (20, 9, 2, 1, 4), (33, 70, 2, 3, 2), (16, 24, 2, 4, 2), (1, 17, 1, 2, 3), (70, 1, 2, 1, 2),
+])
+def test_per_level_api_matches_oracle(ctx, h, w, levels, p, iters):
+    """fb_nnf_init at the coarsest level, then fb_patchmatch_level level by level
+    (upsampling from the coarse field), against the oracle's Algorithm 1."""
+    S, T = pair_images(h, w, 100 + h + w)
+    seed, pair = 0xABCDEF1234 + h, 7 * w + 3
+    prm = fbm.make_params(p, levels, iters, seed)
+    pa, pb = ctx.fb_build_pyramid(dev(S), levels, p), ctx.fb_build_pyramid(dev(T), levels, p)
+    Sp, Tp = oracle.pyramid(S, levels), oracle.pyramid(T, levels)
+    K = levels
+    nnf, en = ctx.fb_nnf_init(pa, pb, h, w, K - 1, prm, pair)
+    Fo, Eo = oracle.nnf_init_random(Sp[K - 1], Tp[K - 1], p, K - 1, seed, pair)
+    assert_field_equal(nnf, en, Fo, Eo, "init level %d" % (K - 1))
+    for l in range(K - 1, -1, -1):
+        if l == K - 1:
+            nnf, en = ctx.fb_patchmatch_level(pa, pb, h, w, l, prm, pair, nnf=nnf, energy=en)
+        else:
+            nnf, en = ctx.fb_patchmatch_level(pa, pb, h, w, l, prm, pair, nnf_coarse=nnf)
+            Fo, Eo = oracle.nnf_upsample(Fo, Sp[l], Tp[l], p)
+        for it in range(iters):
+            Fo, Eo = oracle.pm_iteration(Sp[l], Tp[l], p, l, it, seed, pair, Fo, Eo)
+        assert_field_equal(nnf, en, Fo, Eo, "level %d" % l)
+
+
+def test_seed_offsets_init(ctx):
+    h, w, p = 45, 66, 2
+    S, T = pair_images(h, w, 5)
+    rng = np.random.default_rng(1)
+    off = rng.integers(-30, 30, size=(h, w, 2)).astype(np.int32)
+    off[0, 0] = (10**6, -10**6)   # far outside: clamped
+    prm = fbm.make_params(p, 1, 0, 9)
+    pa, pb = ctx.fb_build_pyramid(dev(S), 1), ctx.fb_build_pyramid(dev(T), 1)
+    nnf, en = ctx.fb_nnf_init(pa, pb, h, w, 0, prm, 3, seed_offsets=dev(off))
+    F, E = oracle.nnf_init_offsets(S, T, p, off)
+    assert_field_equal(nnf, en, F, E, "offsets")
+
+
+def _batch_cases():
+    cases = []
+    for k, (h, w, lv) in enumerate([(48, 64, 2), (30, 70, 3), (64, 64, 1), (13, 29, 2), (48, 64, 2)]):
+        S, T = pair_images(h, w, 40 + k, "noise" if k == 3 else "sprites")
+        cases.append((S, T, h, w, lv, 1000 + 17 * k))
+    return cases
+
+
+def test_batch_mixed_sizes_bit_exact(ctx):
+    iters, seed = 3, 0x5EED
+    prm = fbm.make_params(2, 3, iters, seed)
+    cases = _batch_cases()
+    descs = []
+    for S, T, h, w, lv, pid in cases:
+        descs.append(dict(src_pyr=ctx.fb_build_pyramid(dev(S), lv), tgt_pyr=ctx.fb_build_pyramid(dev(T), lv),
+                          h=h, w=w, levels=lv, pair_id=pid))
+    # one pair seeded at its coarsest level
+    hs, ws = fbm.level_size(cases[1][2], cases[1][3], cases[1][4] - 1)
+    seed_off = np.full((hs, ws, 2), 1, np.int32)
+    descs[1]["seed_offsets"] = dev(seed_off)
+    outs = ctx.fb_patchmatch_batch(descs, prm)
+    for k, ((S, T, h, w, lv, pid), (nnf, en)) in enumerate(zip(cases, outs)):
+        F, E = oracle.patchmatch(S, T, 2, lv, iters, seed, pid, seed_offsets=seed_off if k == 1 else None)
+        assert_field_equal(nnf, en, F, E, "pair %d" % k)
+
+
+def test_tile_shapes_give_identical_results(ctx):
+    prm = fbm.make_params(2, 3, 2, 77)
+    cases = _batch_cases()
+    descs = [dict(src_pyr=ctx.fb_build_pyramid(dev(S), lv), tgt_pyr=ctx.fb_build_pyramid(dev(T), lv),
+                  h=h, w=w, levels=lv, pair_id=pid) for S, T, h, w, lv, pid in cases]
+    ref = None
+    try:
+        for cfg in range(fbm.load_library().fb_num_tile_configs()):
+            ctx.fb_set_tile_config(cfg)
+            outs = [(host(n), host(e)) for n, e in ctx.fb_patchmatch_batch(descs, prm)]
+            if ref is None:
+                ref = outs
+            for (n, e), (rn, re) in zip(outs, ref):
+                assert np.array_equal(n, rn) and np.array_equal(e, re), cfg
+    finally:
+        ctx.fb_set_tile_config(-1)
+
+
+@pytest.mark.parametrize("h,w,p", [(31, 45, 2), (64, 64, 1), (17, 9, 3), (8, 40, 4), (1, 12, 2)])
+def test_remap_matches_oracle(ctx, h, w, p):
+    rng = np.random.default_rng(h * w)
+    style = rng.integers(0, 256, (h, w, 3)).astype(np.uint8)
+    F = np.stack([rng.integers(0, h, (h, w)), rng.integers(0, w, (h, w))], -1).astype(np.int32)
+    out = host(ctx.fb_remap(dev(style), dev(F), p))
+    ref = oracle.remap(style, F, p)
+    assert np.abs(out - ref).max() <= TOL
+
+
+@pytest.mark.parametrize("N,h,w,M,levels,iters", [
+    (6, 48, 40, 2, 2, 3), (4, 33, 70, 1, 3, 2), (3, 20, 20, 0, 1, 2), (1, 24, 24, 3, 2, 2), (5, 16, 80, 9, 2, 2),
+])
+def test_blend_window_matches_oracle(ctx, N, h, w, M, levels, iters):
+    guides, styles = synth.blend_workload(N, h, w, seed=0xB1 + N + h)
+    seed = 0xFB5EED02
+    prm = fbm.make_params(2, levels, iters, seed)
+    out = host(ctx.fb_blend_window(dev(guides), dev(styles), M, prm))
+    ref = oracle.blend_window(guides, styles, M, 2, levels, iters, seed)
+    assert np.abs(out.astype(np.float64) - ref).max() <= TOL
+
+
+@pytest.mark.parametrize("keys", [[0, 4, 8], [3], [2, 5], [0, 1, 2, 3, 4, 5, 6, 7, 8]])
+def test_interpolate_matches_oracle(ctx, keys):
+    N, h, w = 9, 36, 52
+    guides = synth.sprite_video(N, h, w, 11, n_sprites=2, side=(6, 14), pan=1)
+    kst = np.stack([synth.apply_lut(guides[k], synth.random_lut(k)) for k in keys])
+    seed = 0xFB5EED03
+    prm = fbm.make_params(2, 2, 3, seed)
+    out = host(ctx.fb_interpolate(dev(guides), keys, dev(kst), prm))
+    ref = oracle.interpolate(guides, np.array(keys, np.int32), kst, 2, 2, 3, seed)
+    assert np.abs(out.astype(np.float64) - ref).max() <= TOL
+    for k, i in enumerate(keys):
+        assert np.array_equal(out[i], (kst[k] / np.float32(255)).astype(np.float32)) or \
+            np.abs(out[i] - kst[k] / 255.0).max() <= 1e-7
+
+
+def test_graph_replay_matches_eager(ctx):
+    """The batched launch sequence captured as a HIP graph and replayed several
+    times, with other GPU work between replays, gives the eager result each time."""
+    N, h, w, M = 5, 40, 48, 2
+    guides, styles = synth.blend_workload(N, h, w, seed=0xB7)
+    g, s = dev(guides), dev(styles)
+    eager = host(ctx.fb_blend_window(g, s, M, fbm.make_params(2, 2, 3, 21)))
+    side = torch.cuda.Stream()
+    out = torch.empty_like(torch.from_numpy(eager)).cuda()
+    for rep in range(4):
+        out.fill_(-1.0)
+        with torch.cuda.stream(side):
+            ctx.fb_blend_window(g, s, M, fbm.make_params(2, 2, 3, 21, fbm.FB_USE_GRAPH), out=out)
+        side.synchronize()
+        junk = torch.randn(1 << 20, device="cuda").sum()   # unrelated eager work
+        assert np.array_equal(host(out), eager), rep
+        del junk
+
+
+def test_run_twice_is_deterministic(ctx):
+    N, h, w = 4, 32, 64
+    guides, styles = synth.blend_workload(N, h, w, seed=0xD1)
+    prm = fbm.make_params(2, 2, 4, 5)
+    a = host(ctx.fb_blend_window(dev(guides), dev(styles), 2, prm))
+    b = host(ctx.fb_blend_window(dev(guides), dev(styles), 2, prm))
+    assert np.array_equal(a, b)
+
+
+def test_invalid_arguments_are_rejected(ctx):
+    g = dev(np.zeros((2, 8, 8, 3), np.uint8))
+    with pytest.raises(fbm.FastBlendError) as e:
+        ctx.fb_blend_window(g, g, 1, fbm.make_params(5, 1, 1, 0))
+    assert e.value.status == -3
+    with pytest.raises(fbm.FastBlendError) as e:
+        ctx.fb_blend_window(g, g, -1, fbm.make_params(2, 1, 1, 0))
+    assert e.value.status == -1
+    with pytest.raises(fbm.FastBlendError) as e:
+        ctx.fb_blend_window(g, g, 1, fbm.make_params(2, 0, 1, 0))
+    assert e.value.status == -1
+    with pytest.raises(fbm.FastBlendError) as e:
+        ctx.fb_interpolate(g, [1, 0], dev(np.zeros((2, 8, 8, 3), np.uint8)), fbm.make_params(2, 1, 1, 0))
+    assert e.value.status == -1
+    with pytest.raises(ValueError):
+        small = ctx.fb_build_pyramid(g[0], 1)
+        ctx.fb_nnf_init(small, small, 8, 8, 2, fbm.make_params(2, 3, 1, 0), 0)
