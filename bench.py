@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the FastBlend blending hot path on one MI355X.
+
+Workload (one step): blending mode over a 32-frame 512x512 RGB uint8 video,
+window radius 5 (290 ordered frame pairs), patch 5x5, 3 pyramid levels x 6
+PatchMatch iterations: pyramids of all frames, batched PatchMatch of every
+pair, remapping and the window average of Eq. 2, from uint8 guides/styles
+resident in HBM to fp32 blended frames.  Inputs are seeded synthetic sprite
+videos with flickering LUT styles (paper_2311_09265_amd.synth).
+
+Prints one JSON line:
+  value      whole-job PatchMatch throughput, Mpix*iter/s = pixel-iterations
+             of all pairs and levels per step / step wall time
+  roofline   the dominant kernel (the PatchMatch iteration) against the
+             integer dot-product ALU peak: algorithmic byte-terms (one per
+             squared channel difference of Eq. 1) / summed HIP-event time of
+             its launches in the timed region
+  cpu_baseline  the CPU oracle on a bounded sample of the same pairs
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mpix·iter/s of PatchMatch + blended frames/s at 512², window 5; learned vs plain"
+# v_dot4_u32_u8: 4 byte multiply-accumulates per lane per clock,
+# 256 CUs x 64 lanes x 2.4 GHz x 4
+DOT4_PEAK_TOPS = 256 * 64 * 2.4e9 * 4 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def level_sizes(h, w, levels):
+    return [(-(-h // (1 << l)), -(-w // (1 << l))) for l in range(levels)]
+
+
+def window_pairs(N, M):
+    return [(j, i) for i in range(N) for j in range(max(0, i - M), min(N - 1, i + M) + 1) if j != i]
+
+
+def pm_work(n_pairs, h, w, levels, iters, p):
+    """(pixel-iterations, algorithmic byte-terms of the iteration kernel) per step."""
+    pix, terms = 0, 0
+    K = (2 * p + 1) ** 2 * 3
+    for hl, wl in level_sizes(h, w, levels):
+        R = max(hl, wl)
+        n_random = R.bit_length()               # radii R >> m >= 1
+        n_prop = 4 * hl * wl - 2 * hl - 2 * wl  # in-image neighbours, summed over pixels
+        pix += n_pairs * hl * wl * iters
+        terms += n_pairs * iters * (n_prop + hl * wl * n_random) * K
+    return pix, terms
+
+
+def cpu_baseline(guides, pairs, p, levels, iters, seed, N, budget_s):
+    import oracle
+    h, w = guides.shape[1:3]
+    done, t0 = 0, time.perf_counter()
+    for (j, i) in pairs:
+        oracle.patchmatch(guides[j], guides[i], p, levels, iters, seed, j * N + i)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    pix, _ = pm_work(done, h, w, levels, iters, p)
+    return {"value": round(pix / dt / 1e6, 3), "unit": "Mpix·iter/s", "cores": oracle.get_threads(),
+            "kind": "oracle",
+            "sample": "%d of %d pairs, each the full %d-level x %d-iteration PatchMatch of a %dx%d pair "
+                      "(C oracle, OpenMP over rows), %.1f s" % (done, len(pairs), levels, iters, h, w, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=32)
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB once (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2311_09265_amd import fastblend as fbm
+    from paper_2311_09265_amd import synth
+
+    N, h, w, M, p, levels, iters = args.frames, args.size, args.size, 5, 2, 3, 6
+    seed = synth.PHILOX_SEED[2]
+    log("generating %d-frame %dx%d synthetic video" % (N, h, w))
+    guides, styles = synth.blend_workload(N, h, w)
+    pairs = window_pairs(N, M)
+    pix, terms = pm_work(len(pairs), h, w, levels, iters, p)
+
+    dev = torch.device("cuda", 0)
+    ctx = fbm.Context(0)
+    g = torch.from_numpy(guides).to(dev)
+    s = torch.from_numpy(styles).to(dev)
+    out = torch.empty((N, h, w, 3), dtype=torch.float32, device=dev)
+    prm = fbm.make_params(p, levels, iters, seed)
+    for k in range(args.warmup):
+        ctx.fb_blend_window(g, s, M, prm, out=out)
+        torch.cuda.synchronize()
+        log("warmup step %d done" % k)
+
+    # timed region: eager launches, every launch bracketed by HIP events on the library's stream
+    ctx.fb_profile_enable(True)
+    ctx.fb_profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.fb_blend_window(g, s, M, prm, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.fb_profile_read(reset=True)
+    ctx.fb_profile_enable(False)
+    ms = (t1 - t0) / args.steps * 1e3
+    log("timed %d steps: %.2f ms/step" % (args.steps, ms))
+
+    # the same steps replayed as one HIP graph per step
+    gprm = fbm.make_params(p, levels, iters, seed, fbm.FB_USE_GRAPH)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        ctx.fb_blend_window(g, s, M, gprm, out=out)
+        side.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(args.steps):
+            ctx.fb_blend_window(g, s, M, gprm, out=out)
+        side.synchronize()
+        t3 = time.perf_counter()
+    graph_ms = (t3 - t2) / args.steps * 1e3
+    log("graph replay: %.2f ms/step" % graph_ms)
+
+    # quality: mean level-0 patch energy of all pairs (outside the timed region)
+    pyrs = [ctx.fb_build_pyramid(g[f], levels, p) for f in range(N)]
+    descs = [dict(src_pyr=pyrs[j], tgt_pyr=pyrs[i], h=h, w=w, levels=levels, pair_id=j * N + i)
+             for (j, i) in pairs]
+    energies = [e for _, e in ctx.fb_patchmatch_batch(descs, prm)]
+    mean_energy = float(torch.stack(energies).double().mean().item())
+    del energies, pyrs
+
+    n_iter, iter_ms = prof["pm_iter"]
+    iter_ms_step = iter_ms / args.steps
+    achieved = terms / (iter_ms_step / 1e3) / 1e12
+    kernel_ms = {k: round(v[1] / args.steps, 3) for k, v in prof.items() if v[0]}
+
+    if args.calib_copy_mib:
+        x = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("calibration copy of %d MiB done" % args.calib_copy_mib)
+        del x, y
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) for up to %.0f s" % args.cpu_seconds)
+        cpu = cpu_baseline(guides, pairs, p, levels, iters, seed, N, args.cpu_seconds)
+        log("cpu baseline: %s" % cpu)
+
+    res = {
+        "metric": METRIC,
+        "value": round(pix / (ms / 1e3) / 1e6, 3),
+        "unit": "Mpix·iter/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "blend %d frames %dx%d RGB u8, window radius %d (%d pairs), patch %dx%d, "
+                               "%d levels x %d iterations, plain random init" % (
+                                   N, h, w, M, len(pairs), 2 * p + 1, 2 * p + 1, levels, iters),
+                   "frames": N, "height": h, "width": w, "window_radius": M, "pairs": len(pairs),
+                   "patch": 2 * p + 1, "levels": levels, "iters": iters},
+        "blended_frames_per_s": round(N / (ms / 1e3), 3),
+        "graph_ms_per_step": round(graph_ms, 3),
+        "pixel_iterations_per_step": pix,
+        "mean_level0_patch_energy": round(mean_energy, 2),
+        "kernel_ms_per_step": kernel_ms,
+        "roofline": {"bound": "alu", "kernel": "k_pm_iter",
+                     "achieved": round(achieved, 3), "peak": round(DOT4_PEAK_TOPS, 1), "unit": "TOP/s",
+                     "frac": round(achieved / DOT4_PEAK_TOPS, 4), "traffic": None,
+                     "work": "byte-terms of Eq. 1 (one per squared channel difference) per step: %d" % terms,
+                     "avg_launch_ms": round(iter_ms / max(n_iter, 1), 4), "launches": n_iter},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

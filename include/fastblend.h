@@ -89,8 +89,8 @@ fb_status fb_set_tile_config(fb_ctx *ctx, int32_t index);
 /* Image pyramid (Algorithm 1, "resize images S, T" for each level).       */
 /* 2x2 box filter with round-half-up, ceil sizes, clamped reads.  The      */
 /* pyramid is an opaque device buffer of fb_pyramid_bytes(h,w,levels,p)    */
-/* bytes allocated by the caller; it holds every level as padded 4-byte    */
-/* pixels plus per-pixel patch norms for patch radius p.                   */
+/* bytes allocated by the caller; it holds every level as 4-byte pixels   */
+/* with a border of p replicated pixels (p = patch radius).                */
 /* ---------------------------------------------------------------------- */
 size_t fb_pyramid_bytes(int32_t h, int32_t w, int32_t levels, int32_t patch_radius);
 fb_status fb_build_pyramid(fb_ctx *ctx, const uint8_t *rgb, int32_t h, int32_t w,
@@ -178,6 +178,31 @@ typedef struct {
  * pair has its own), the other fields apply to all pairs. */
 fb_status fb_patchmatch_batch(fb_ctx *ctx, const fb_pair_desc *pairs, int32_t n_pairs,
                               const fb_params *params, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Kernel timing (measurement support).  While profiling is on, every      */
+/* launch is bracketed by HIP events recorded on the call's stream and the */
+/* calls run their launches eagerly (no graph replay).  fb_profile_read    */
+/* waits for the recorded events and returns, per kernel kind, the number  */
+/* of launches and the summed event-to-event time since profiling began    */
+/* (or since the last read with reset != 0).                               */
+/* ---------------------------------------------------------------------- */
+enum {
+    FB_KERNEL_PYRAMID = 0,   /* pack + downsample + norm of a batch of frames */
+    FB_KERNEL_PM_START = 1,  /* init / upsample + energy                      */
+    FB_KERNEL_PM_ITER = 2,   /* one PatchMatch iteration over a batch         */
+    FB_KERNEL_PM_EXPORT = 3, /* packed field -> int32 NNF + energies          */
+    FB_KERNEL_REMAP = 4,     /* remap-sum (Alg. 2 + Eq. 2 / Eq. 9)            */
+    FB_KERNEL_OTHER = 5,
+    FB_KERNEL_KINDS = 8
+};
+typedef struct {
+    int64_t launches[FB_KERNEL_KINDS];
+    double milliseconds[FB_KERNEL_KINDS];
+} fb_profile;
+
+fb_status fb_profile_enable(fb_ctx *ctx, int32_t on);
+fb_status fb_profile_read(fb_ctx *ctx, fb_profile *out, int32_t reset);
 
 #ifdef __cplusplus
 }

@@ -3,13 +3,12 @@
 // Data layout in device memory
 // ----------------------------
 // * Pyramid of one frame (fb_build_pyramid): for every level l, the image as
-//   4-byte pixels (R, G, B, 0) with a replicated border of p pixels on every
+//   4-byte (R, G, B, 0) pixels with a replicated border of p pixels on every
 //   side (so a patch read never needs clamping), row pitch rounded up to 16
-//   pixels, followed by the per-pixel patch norm N(u) = sum over the
-//   (2p+1)^2 x 3 patch at u of the squared pixel values (uint32 [h_l][w_l]).
-//   Since the loss of Eq. 1 is sum (s - t)^2 = N_S(u) + N_T(v) - 2 sum s t,
-//   one candidate costs (2p+1)^2 4-byte dot products (v_dot4_u32_u8), exact in
-//   32-bit integers.
+//   pixels.  A (2p+1)-pixel patch row is one 16-byte + one 4-byte aligned
+//   load for p = 2.
+// * Style frames: the same format at full resolution (one aligned 4-byte
+//   gather per remapped pixel).
 // * NNFs inside the library are one uint32 per pixel: (row << 16) | col.
 //   The C ABI converts to / from int32 [h][w][2].
 #pragma once
@@ -28,8 +27,7 @@ struct LevelGeom {
     int32_t h, w;        // level size
     int32_t pitch;       // padded row pitch in pixels
     int32_t rows;        // padded rows = h + 2p
-    size_t px_off;       // byte offset of the padded pixel block
-    size_t norm_off;     // byte offset of the norm image
+    size_t px_off;       // byte offset of the level in the pyramid
 };
 
 struct PyrLayout {
@@ -40,7 +38,7 @@ struct PyrLayout {
 
 // Host: layout of a pyramid of `levels` levels for patch radius p.
 PyrLayout pyr_layout(int h, int w, int levels, int p);
-// Host: layout of a single padded level-0 image (styles), no norm.
+// Host: layout of a single padded level-0 image (styles); pitch in pixels.
 size_t padded_image_bytes(int h, int w, int p, int32_t *pitch_out);
 
 inline int ceil_half_pow(int x, int l) { return (x + (1 << l) - 1) >> l; }
@@ -57,8 +55,6 @@ enum StartMode : int32_t {
 struct PMJob {
     const uint32_t *src_px;    // padded pixels of the source level, at padded (0, 0)
     const uint32_t *tgt_px;    // padded pixels of the target level
-    const uint32_t *src_norm;  // [h][w]
-    const uint32_t *tgt_norm;  // [h][w]
     const uint32_t *f_in;      // packed field read by the launch
     const uint32_t *e_in;      // energies read by iterations
     uint32_t *f_out;           // packed field written by the launch
@@ -67,7 +63,7 @@ struct PMJob {
     const uint32_t *e_abi;     // ABI energies (start mode 4)
     int32_t *nnf_abi;          // export destinations
     uint32_t *energy_abi;
-    int32_t h, w, pitch;
+    int32_t h, w, pitch;       // level size; row pitch in pixels
     int32_t hc, wc;            // coarse size for upsampling
     uint32_t pair_id;
     int32_t level;
@@ -76,6 +72,7 @@ struct PMJob {
     int32_t tiles_x;           // tiles along w
     int32_t pad_[2];
 };
+static_assert(sizeof(PMJob) % 8 == 0, "PMJob is copied as an array");
 
 // Tile shape of the PatchMatch kernels (one thread per target pixel).
 struct TileCfg {
@@ -102,13 +99,11 @@ struct RemapFrame {
 };
 
 // ---- launchers (stream-ordered, no synchronisation) ----
-hipError_t launch_pack_level0(const uint8_t *rgb, size_t rgb_stride, int n, int h, int w, int p,
-                              uint8_t *dst, size_t dst_stride, size_t px_off, int pitch,
-                              hipStream_t s);
+hipError_t launch_pack_rgbx(const uint8_t *rgb, size_t rgb_stride, int n, int h, int w, int p,
+                            uint8_t *dst, size_t dst_stride, size_t px_off, int pitch,
+                            hipStream_t s);
 hipError_t launch_downsample(const uint8_t *base, size_t stride, int n, const LevelGeom &in,
                              const LevelGeom &out, int p, hipStream_t s);
-hipError_t launch_norm(uint8_t *base, size_t stride, int n, const LevelGeom &g, int p,
-                       hipStream_t s);
 
 hipError_t launch_pm_start(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
                            TileCfg cfg, int p, uint64_t seed, hipStream_t s);

@@ -20,11 +20,14 @@
 //               equals the best loss and could never pass '<'.
 //  k_pm_export  packed field -> int32 [h][w][2] and energies for the C ABI.
 //
-// Loss (Eq. 1) of a candidate u for target v, exact in uint32:
-//   N_S(u) + N_T(v) - 2 * sum over the patch of <s, t>,
-// with the dot products as v_dot4_u32_u8 on (R,G,B,0) pixels.  The target
-// patch stays in registers for the whole iteration; a source patch row is one
-// 16-byte + one 4-byte load from the padded image (no clamping needed).
+// Loss (Eq. 1) of a candidate u for target v, exact in uint32, row by row:
+//   sum s^2 + sum t^2 - 2 sum s t   over each (2p+1)-pixel patch row,
+// all as v_dot4_u32_u8 on (R,G,B,0) pixels.  The target patch and its row
+// sums t^2 stay in registers for the whole iteration; a source patch row is
+// one 16-byte + one 4-byte load from the padded image (no clamping needed).
+// Random-search candidates are divergent gathers, so the iteration kernel
+// fetches a candidate's first row alone and rejects it when that row's loss
+// already reaches the running best (exact: each row's loss is >= 0).
 //
 // Random draws: Philox4x32-10 (Salmon et al., SC'11), key = seed, counter =
 // (pixel index r*w + c, pair id, level << 16 | iteration, m >> 2); word m & 3
@@ -76,36 +79,63 @@ __device__ __forceinline__ int find_job(const PMJob *__restrict__ jobs, int n, i
     return lo;
 }
 
+// A patch row: K = 2P+1 aligned 4-byte (R,G,B,0) pixels, one 16-byte and one
+// 4-byte load for P = 2.
 template <int K>
 struct __attribute__((packed, aligned(4))) PixRow {
     uint32_t v[K];
 };
 
-// sum over the K x K patch of <source pixel, target pixel>
 template <int P>
-__device__ __forceinline__ uint32_t patch_dot(const uint32_t *__restrict__ sp, int pitch,
-                                              const uint32_t (&t)[2 * P + 1][2 * P + 1]) {
-    constexpr int K = 2 * P + 1;
-    uint32_t acc = 0;
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const PixRow<K> row = *reinterpret_cast<const PixRow<K> *>(sp + (size_t)i * pitch);
-#pragma unroll
-        for (int j = 0; j < K; ++j) acc = __builtin_amdgcn_udot4(row.v[j], t[i][j], acc, false);
-    }
-    return acc;
-}
+struct TargetPatch {
+    static constexpr int K = 2 * P + 1;
+    uint32_t px[K][K];
+    uint32_t row_tt[K];  // sum t^2 of every row
+    uint32_t tt;         // sum t^2 of the patch
+};
 
 template <int P>
 __device__ __forceinline__ void load_target_patch(const uint32_t *__restrict__ tp, int pitch,
-                                                  uint32_t (&t)[2 * P + 1][2 * P + 1]) {
+                                                  TargetPatch<P> &t) {
     constexpr int K = 2 * P + 1;
+    t.tt = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const PixRow<K> row = *reinterpret_cast<const PixRow<K> *>(tp + (size_t)i * pitch);
+        uint32_t acc = 0;
 #pragma unroll
-        for (int j = 0; j < K; ++j) t[i][j] = row.v[j];
+        for (int j = 0; j < K; ++j) {
+            t.px[i][j] = row.v[j];
+            acc = __builtin_amdgcn_udot4(row.v[j], row.v[j], acc, false);
+        }
+        t.row_tt[i] = acc;
+        t.tt += acc;
     }
+}
+
+// Eq. 1 restricted to patch row i: sum s^2 + sum t^2 - 2 sum s t over that row
+template <int P>
+__device__ __forceinline__ uint32_t row_loss(const uint32_t *__restrict__ sp, const TargetPatch<P> &t,
+                                             int i) {
+    constexpr int K = 2 * P + 1;
+    const PixRow<K> row = *reinterpret_cast<const PixRow<K> *>(sp);
+    uint32_t st = 0, ss = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        st = __builtin_amdgcn_udot4(row.v[j], t.px[i][j], st, false);
+        ss = __builtin_amdgcn_udot4(row.v[j], row.v[j], ss, false);
+    }
+    return ss + t.row_tt[i] - 2u * st;
+}
+
+// Eq. 1 for the source patch whose top-left padded pixel is sp
+template <int P>
+__device__ __forceinline__ uint32_t patch_loss(const uint32_t *__restrict__ sp, int pitch,
+                                               const TargetPatch<P> &t) {
+    uint32_t e = 0;
+#pragma unroll
+    for (int i = 0; i < 2 * P + 1; ++i) e += row_loss<P>(sp + (size_t)i * pitch, t, i);
+    return e;
 }
 
 struct TileCoord {
@@ -172,11 +202,10 @@ k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unif
         return;
     }
     }
-    uint32_t t[2 * P + 1][2 * P + 1];
+    TargetPatch<P> t;
     load_target_patch<P>(J.tgt_px + (size_t)r * J.pitch + c, J.pitch, t);
-    const uint32_t dot = patch_dot<P>(J.src_px + (size_t)fr * J.pitch + fc, J.pitch, t);
     J.f_out[v] = ((uint32_t)fr << 16) | (uint32_t)fc;
-    J.e_out[v] = J.src_norm[fr * w + fc] + J.tgt_norm[v] - 2u * dot;
+    J.e_out[v] = patch_loss<P>(J.src_px + (size_t)fr * J.pitch + fc, J.pitch, t);
 }
 
 template <int P, int TW, int TH>
@@ -190,20 +219,24 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     const int v = r * w + c;
     const uint32_t *__restrict__ f_in = J.f_in;
     const uint32_t *__restrict__ src_px = J.src_px;
-    const uint32_t *__restrict__ src_norm = J.src_norm;
 
-    uint32_t t[2 * P + 1][2 * P + 1];
+    TargetPatch<P> t;
     load_target_patch<P>(J.tgt_px + (size_t)r * pitch + c, pitch, t);
-    const uint32_t tn = J.tgt_norm[v];
 
     const uint32_t f0 = f_in[v];
     int br = (int)(f0 >> 16), bc = (int)(f0 & 0xFFFFu);
     uint32_t be = J.e_in[v];
 
+    // Every row's share of the loss is a sum of squares, so once the first row
+    // alone reaches the running best the candidate cannot pass '<': the other
+    // rows are never fetched.  Far random-search candidates usually stop there.
     auto consider = [&](int cr, int cc) {
         if (cr == br && cc == bc) return;
-        const uint32_t e = src_norm[cr * w + cc] + tn -
-                           2u * patch_dot<P>(src_px + (size_t)cr * pitch + cc, pitch, t);
+        const uint32_t *sp = src_px + (size_t)cr * pitch + cc;
+        uint32_t e = row_loss<P>(sp, t, 0);
+        if (e >= be) return;
+#pragma unroll
+        for (int i = 1; i < 2 * P + 1; ++i) e += row_loss<P>(sp + (size_t)i * pitch, t, i);
         if (e < be) { br = cr; bc = cc; be = e; }
     };
 

@@ -1,18 +1,25 @@
-// Image pyramid kernels (Algorithm 1, "resize images S, T" at every level).
+// Image pyramid and frame-packing kernels (Algorithm 1, "resize images S, T"
+// at every level).
 //
 // Reading of the paper's unspecified resize: 2x2 box filter with round-half-up,
-// ceil(h/2) x ceil(w/2) output, source reads clamped to the image.  Every
-// level is stored as padded 4-byte pixels (see fb_common.h) so the patch
-// kernels never clamp, plus a per-pixel patch-norm image.
+// ceil(h/2) x ceil(w/2) output, source reads clamped to the image.
 //
-// All three kernels stream through HBM once per frame and level; they are a
+// Every level, and every style frame, is stored as 4-byte (R, G, B, 0) pixels
+// with a replicated border of p pixels on every side, so that the patch and
+// remap kernels never clamp and each pixel is one aligned 4-byte word.
+//
+// All kernels stream through HBM once per frame and level; they are a
 // negligible share of a blend (one pyramid per frame, shared by every pair
 // that uses the frame).
 #include "fb_common.h"
 
 namespace fb {
 
+namespace {
 __device__ __forceinline__ int clampi(int x, int lo, int hi) { return min(max(x, lo), hi); }
+
+int padded_pitch(int w, int p) { return (w + 2 * p + kPitchAlign - 1) / kPitchAlign * kPitchAlign; }
+}  // namespace
 
 PyrLayout pyr_layout(int h, int w, int levels, int p) {
     PyrLayout L{};
@@ -24,12 +31,9 @@ PyrLayout pyr_layout(int h, int w, int levels, int p) {
         g.h = ceil_half_pow(h, l);
         g.w = ceil_half_pow(w, l);
         g.rows = g.h + 2 * p;
-        g.pitch = (g.w + 2 * p + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
+        g.pitch = padded_pitch(g.w, p);
         g.px_off = off;
         off += (size_t)g.rows * g.pitch * 4;
-        off = (off + 255) & ~(size_t)255;
-        g.norm_off = off;
-        off += (size_t)g.h * g.w * 4;
         off = (off + 255) & ~(size_t)255;
     }
     L.bytes = off;
@@ -37,15 +41,17 @@ PyrLayout pyr_layout(int h, int w, int levels, int p) {
 }
 
 size_t padded_image_bytes(int h, int w, int p, int32_t *pitch_out) {
-    int pitch = (w + 2 * p + kPitchAlign - 1) / kPitchAlign * kPitchAlign;
+    const int pitch = padded_pitch(w, p);
     if (pitch_out) *pitch_out = pitch;
     return (((size_t)(h + 2 * p) * pitch * 4) + 255) & ~(size_t)255;
 }
 
+namespace {
+
 // RGB8 [h][w][3] -> padded (R,G,B,0) pixels; one thread per padded pixel.
 __global__ void __launch_bounds__(256)
-k_pack_level0(const uint8_t *__restrict__ rgb, size_t rgb_stride, int h, int w, int p,
-              uint8_t *__restrict__ dst, size_t dst_stride, size_t px_off, int pitch) {
+k_pack_rgbx(const uint8_t *__restrict__ rgb, size_t rgb_stride, int h, int w, int p,
+            uint8_t *__restrict__ dst, size_t dst_stride, size_t px_off, int pitch) {
     const int C = blockIdx.x * blockDim.x + threadIdx.x;
     const int R = blockIdx.y;
     const int f = blockIdx.z;
@@ -83,34 +89,13 @@ k_downsample(uint8_t *__restrict__ base, size_t stride, int hi_, int wi, int pit
     out[(size_t)R * pitch_o + C] = vr | (vg << 8) | (vb << 16);
 }
 
-// N(u) = sum over the (2p+1)^2 patch at u of r^2 + g^2 + b^2.
-template <int P>
-__global__ void __launch_bounds__(256)
-k_norm(uint8_t *__restrict__ base, size_t stride, int h, int w, int pitch, size_t px_off,
-       size_t norm_off) {
-    constexpr int K = 2 * P + 1;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = blockIdx.y;
-    const int f = blockIdx.z;
-    if (c >= w) return;
-    uint8_t *fb = base + (size_t)f * stride;
-    const uint32_t *px = reinterpret_cast<const uint32_t *>(fb + px_off) + (size_t)r * pitch + c;
-    uint32_t acc = 0;
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const uint32_t v = px[(size_t)i * pitch + j];
-            acc = __builtin_amdgcn_udot4(v, v, acc, false);
-        }
-    reinterpret_cast<uint32_t *>(fb + norm_off)[(size_t)r * w + c] = acc;
-}
+}  // namespace
 
-hipError_t launch_pack_level0(const uint8_t *rgb, size_t rgb_stride, int n, int h, int w, int p,
-                              uint8_t *dst, size_t dst_stride, size_t px_off, int pitch,
-                              hipStream_t s) {
+hipError_t launch_pack_rgbx(const uint8_t *rgb, size_t rgb_stride, int n, int h, int w, int p,
+                            uint8_t *dst, size_t dst_stride, size_t px_off, int pitch,
+                            hipStream_t s) {
     dim3 grid((w + 2 * p + 255) / 256, h + 2 * p, n);
-    hipLaunchKernelGGL(k_pack_level0, grid, dim3(256), 0, s, rgb, rgb_stride, h, w, p, dst,
+    hipLaunchKernelGGL(k_pack_rgbx, grid, dim3(256), 0, s, rgb, rgb_stride, h, w, p, dst,
                        dst_stride, px_off, pitch);
     return hipGetLastError();
 }
@@ -120,19 +105,6 @@ hipError_t launch_downsample(const uint8_t *base, size_t stride, int n, const Le
     dim3 grid((out.w + 2 * p + 255) / 256, out.rows, n);
     hipLaunchKernelGGL(k_downsample, grid, dim3(256), 0, s, const_cast<uint8_t *>(base), stride,
                        in.h, in.w, in.pitch, in.px_off, out.h, out.w, out.pitch, out.px_off, p);
-    return hipGetLastError();
-}
-
-hipError_t launch_norm(uint8_t *base, size_t stride, int n, const LevelGeom &g, int p,
-                       hipStream_t s) {
-    dim3 grid((g.w + 255) / 256, g.h, n);
-    switch (p) {
-    case 1: hipLaunchKernelGGL(k_norm<1>, grid, dim3(256), 0, s, base, stride, g.h, g.w, g.pitch, g.px_off, g.norm_off); break;
-    case 2: hipLaunchKernelGGL(k_norm<2>, grid, dim3(256), 0, s, base, stride, g.h, g.w, g.pitch, g.px_off, g.norm_off); break;
-    case 3: hipLaunchKernelGGL(k_norm<3>, grid, dim3(256), 0, s, base, stride, g.h, g.w, g.pitch, g.px_off, g.norm_off); break;
-    case 4: hipLaunchKernelGGL(k_norm<4>, grid, dim3(256), 0, s, base, stride, g.h, g.w, g.pitch, g.px_off, g.norm_off); break;
-    default: return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 

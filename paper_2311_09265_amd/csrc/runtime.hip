@@ -46,7 +46,10 @@ struct Buf {
     size_t n = 0;
 };
 
-using Op = std::function<hipError_t(hipStream_t, const uint8_t *)>;
+struct Op {
+    int kind;  // FB_KERNEL_*
+    std::function<hipError_t(hipStream_t, const uint8_t *)> fn;
+};
 
 struct Plan {
     std::vector<uint8_t> table;  // host image of the device tables
@@ -100,22 +103,22 @@ void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cf
     sig_add(P, "pm", kind, (long long)off, n, ((long long)iter << 32) | (cfg.tw << 8) | cfg.th);
     switch (kind) {
     case kLaunchStart:
-        P.ops.push_back([=](hipStream_t s, const uint8_t *tab) {
+        P.ops.push_back({FB_KERNEL_PM_START, [=](hipStream_t s, const uint8_t *tab) {
             return launch_pm_start(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform,
                                    cfg, p, seed, s);
-        });
+        }});
         break;
     case kLaunchIter:
-        P.ops.push_back([=](hipStream_t s, const uint8_t *tab) {
+        P.ops.push_back({FB_KERNEL_PM_ITER, [=](hipStream_t s, const uint8_t *tab) {
             return launch_pm_iter(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform,
                                   cfg, p, iter, seed, s);
-        });
+        }});
         break;
     case kLaunchExport:
-        P.ops.push_back([=](hipStream_t s, const uint8_t *tab) {
+        P.ops.push_back({FB_KERNEL_PM_EXPORT, [=](hipStream_t s, const uint8_t *tab) {
             return launch_pm_export(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform,
                                     cfg, s);
-        });
+        }});
         break;
     }
 }
@@ -127,26 +130,24 @@ void plan_pyramids(Plan &P, const uint8_t *rgb, int n, int h, int w, const PyrLa
     const size_t rgb_stride = (size_t)h * w * 3;
     sig_add(P, "pyr", (long long)(uintptr_t)rgb, n, ((long long)h << 32) | w,
             (long long)(uintptr_t)dst + L.levels);
-    P.ops.push_back([=](hipStream_t s, const uint8_t *) {
-        hipError_t e = launch_pack_level0(rgb, rgb_stride, n, h, w, p, dst, stride,
-                                          L.lv[0].px_off, L.lv[0].pitch, s);
+    P.ops.push_back({FB_KERNEL_PYRAMID, [=](hipStream_t s, const uint8_t *) {
+        hipError_t e = launch_pack_rgbx(rgb, rgb_stride, n, h, w, p, dst, stride, L.lv[0].px_off,
+                                        L.lv[0].pitch, s);
         for (int l = 1; l < L.levels && e == hipSuccess; ++l)
             e = launch_downsample(dst, stride, n, L.lv[l - 1], L.lv[l], p, s);
-        for (int l = 0; l < L.levels && e == hipSuccess; ++l)
-            e = launch_norm(dst, stride, n, L.lv[l], p, s);
         return e;
-    });
+    }});
 }
 
-// Padded level-0 pixels of n style frames (no norms).
+// Padded 4-byte pixels of n style frames.
 void plan_style_pack(Plan &P, const uint8_t *rgb, int n, int h, int w, int p, uint8_t *dst,
                      size_t stride, int pitch) {
     const size_t rgb_stride = (size_t)h * w * 3;
     sig_add(P, "sty", (long long)(uintptr_t)rgb, n, ((long long)h << 32) | w,
             (long long)(uintptr_t)dst);
-    P.ops.push_back([=](hipStream_t s, const uint8_t *) {
-        return launch_pack_level0(rgb, rgb_stride, n, h, w, p, dst, stride, 0, pitch, s);
-    });
+    P.ops.push_back({FB_KERNEL_PYRAMID, [=](hipStream_t s, const uint8_t *) {
+        return launch_pack_rgbx(rgb, rgb_stride, n, h, w, p, dst, stride, 0, pitch, s);
+    }});
 }
 
 struct PairSpec {
@@ -166,8 +167,6 @@ PMJob job_geom(const PairSpec &ps, int l) {
     const LevelGeom &g = ps.L.lv[l];
     j.src_px = reinterpret_cast<const uint32_t *>(ps.src_pyr + g.px_off);
     j.tgt_px = reinterpret_cast<const uint32_t *>(ps.tgt_pyr + g.px_off);
-    j.src_norm = reinterpret_cast<const uint32_t *>(ps.src_pyr + g.norm_off);
-    j.tgt_norm = reinterpret_cast<const uint32_t *>(ps.tgt_pyr + g.norm_off);
     j.h = g.h;
     j.w = g.w;
     j.pitch = g.pitch;
@@ -272,10 +271,10 @@ void add_remap_launch(Plan &P, const std::vector<RemapFrame> &frames,
     const size_t foff = table_append(P, frames.data(), frames.size());
     const int nf = (int)frames.size();
     sig_add(P, "remap", (long long)toff, (long long)foff, nf, ((long long)h << 32) | w);
-    P.ops.push_back([=](hipStream_t s, const uint8_t *tab) {
+    P.ops.push_back({FB_KERNEL_REMAP, [=](hipStream_t s, const uint8_t *tab) {
         return launch_remap_sum(reinterpret_cast<const RemapFrame *>(tab + foff), nf,
                                 reinterpret_cast<const RemapTerm *>(tab + toff), h, w, pitch, p, s);
-    });
+    }});
 }
 
 }  // namespace
@@ -292,6 +291,12 @@ struct fb_ctx {
     uint64_t graph_gen = ~0ull;
     hipStream_t graph_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // kernel timing: events bracketing each launch, read lazily
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct Mark { int kind; hipEvent_t a, b; };
+    std::vector<Mark> marks;
+    fb_profile acc{};
 };
 
 namespace {
@@ -375,7 +380,7 @@ fb_status run_plan(fb_ctx *ctx, Plan &P, uint32_t flags, hipStream_t s, int p, u
     const uint8_t *tab = static_cast<const uint8_t *>(ctx->table.p);
     const bool tune = P.has_tune && ctx->forced_cfg < 0 && !(flags & FB_NO_AUTOTUNE) &&
                       !ctx->tuned.count(P.tune_key);
-    if ((flags & FB_USE_GRAPH) && s != nullptr && !tune) {
+    if ((flags & FB_USE_GRAPH) && s != nullptr && !tune && !ctx->profiling) {
         if (!ctx->graph_exec || ctx->graph_gen != ctx->table_gen || ctx->graph_sig != P.sig ||
             ctx->graph_stream != s) {
             if (ctx->graph_exec) FB_HIP(hipGraphExecDestroy(ctx->graph_exec));
@@ -383,7 +388,7 @@ fb_status run_plan(fb_ctx *ctx, Plan &P, uint32_t flags, hipStream_t s, int p, u
             hipGraph_t g = nullptr;
             FB_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             for (Op &op : P.ops) {
-                hipError_t e = op(s, tab);
+                hipError_t e = op.fn(s, tab);
                 if (e != hipSuccess) {
                     hipGraph_t dummy = nullptr;
                     (void)hipStreamEndCapture(s, &dummy);
@@ -405,8 +410,41 @@ fb_status run_plan(fb_ctx *ctx, Plan &P, uint32_t flags, hipStream_t s, int p, u
         FB_HIP(hipGraphLaunch(ctx->graph_exec, s));
         return FB_OK;
     }
-    for (Op &op : P.ops) FB_HIP(op(s, tab));
+    for (Op &op : P.ops) {
+        if (ctx->profiling) {
+            fb_ctx::Mark m{op.kind, nullptr, nullptr};
+            for (hipEvent_t *e : {&m.a, &m.b}) {
+                if (!ctx->ev_pool.empty()) {
+                    *e = ctx->ev_pool.back();
+                    ctx->ev_pool.pop_back();
+                } else {
+                    FB_HIP(hipEventCreate(e));
+                }
+            }
+            FB_HIP(hipEventRecord(m.a, s));
+            FB_HIP(op.fn(s, tab));
+            FB_HIP(hipEventRecord(m.b, s));
+            ctx->marks.push_back(m);
+        } else {
+            FB_HIP(op.fn(s, tab));
+        }
+    }
     if (tune) return autotune(ctx, P, s, p, seed);
+    return FB_OK;
+}
+
+fb_status drain_marks(fb_ctx *ctx) {
+    for (fb_ctx::Mark &m : ctx->marks) {
+        FB_HIP(hipEventSynchronize(m.b));
+        float ms = 0.f;
+        FB_HIP(hipEventElapsedTime(&ms, m.a, m.b));
+        const int k = (m.kind >= 0 && m.kind < FB_KERNEL_KINDS) ? m.kind : FB_KERNEL_OTHER;
+        ctx->acc.launches[k] += 1;
+        ctx->acc.milliseconds[k] += ms;
+        ctx->ev_pool.push_back(m.a);
+        ctx->ev_pool.push_back(m.b);
+    }
+    ctx->marks.clear();
     return FB_OK;
 }
 
@@ -458,12 +496,35 @@ void fb_destroy(fb_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    for (fb_ctx::Mark &m : ctx->marks) {
+        (void)hipEventDestroy(m.a);
+        (void)hipEventDestroy(m.b);
+    }
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (Buf *b : {&ctx->table, &ctx->pyr, &ctx->style, &ctx->fe, &ctx->tune_table})
         if (b->p) (void)hipFree(b->p);
     delete ctx;
 }
 
 const char *fb_last_error(void) { return g_err.c_str(); }
+
+fb_status fb_profile_enable(fb_ctx *ctx, int32_t on) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!on && (st = drain_marks(ctx))) return st;
+    ctx->profiling = on != 0;
+    return FB_OK;
+}
+
+fb_status fb_profile_read(fb_ctx *ctx, fb_profile *out, int32_t reset) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!out) return fail(FB_E_INVALID, "out is NULL");
+    if ((st = drain_marks(ctx))) return st;
+    *out = ctx->acc;
+    if (reset) ctx->acc = fb_profile{};
+    return FB_OK;
+}
 
 int32_t fb_num_tile_configs(void) { return n_tile_cfgs(); }
 
@@ -489,13 +550,11 @@ fb_status fb_build_pyramid(fb_ctx *ctx, const uint8_t *rgb, int32_t h, int32_t w
     if (!valid_p(patch_radius)) return fail(FB_E_UNSUPPORTED, "patch_radius must be in [1, 4]");
     const PyrLayout L = pyr_layout(h, w, levels, patch_radius);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    FB_HIP(launch_pack_level0(rgb, 0, 1, h, w, patch_radius, static_cast<uint8_t *>(pyr), 0,
-                              L.lv[0].px_off, L.lv[0].pitch, s));
+    FB_HIP(launch_pack_rgbx(rgb, 0, 1, h, w, patch_radius, static_cast<uint8_t *>(pyr), 0,
+                            L.lv[0].px_off, L.lv[0].pitch, s));
     for (int l = 1; l < levels; ++l)
         FB_HIP(launch_downsample(static_cast<uint8_t *>(pyr), 0, 1, L.lv[l - 1], L.lv[l],
                                  patch_radius, s));
-    for (int l = 0; l < levels; ++l)
-        FB_HIP(launch_norm(static_cast<uint8_t *>(pyr), 0, 1, L.lv[l], patch_radius, s));
     return FB_OK;
 }
 
@@ -609,9 +668,9 @@ fb_status fb_remap(fb_ctx *ctx, const uint8_t *style, const int32_t *nnf, int32_
     Plan P;
     plan_style_pack(P, style, 1, h, w, p, sty, sbytes, pitch);
     sig_add(P, "f2p", (long long)(uintptr_t)nnf, h, w, (long long)(uintptr_t)f);
-    P.ops.push_back([=](hipStream_t s, const uint8_t *) {
+    P.ops.push_back({FB_KERNEL_OTHER, [=](hipStream_t s, const uint8_t *) {
         return launch_field_to_packed(nnf, f, h, w, s);
-    });
+    }});
     RemapTerm t{reinterpret_cast<const uint32_t *>(sty), f, 1.0f, 0};
     RemapFrame fr{out, 0, 1, 1.0f, 0};
     add_remap_launch(P, {fr}, {t}, h, w, pitch, p);

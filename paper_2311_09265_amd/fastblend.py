@@ -44,10 +44,18 @@ class fb_pair_desc(ctypes.Structure):
                 ("nnf", ctypes.c_void_p), ("energy", ctypes.c_void_p)]
 
 
+KERNEL_KINDS = ["pyramid", "pm_start", "pm_iter", "pm_export", "remap", "other"]
+
+
+class fb_profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 8), ("milliseconds", ctypes.c_double * 8)]
+
+
 _lib = None
 _EXPORTS = ["fb_create", "fb_destroy", "fb_last_error", "fb_num_tile_configs", "fb_set_tile_config",
             "fb_pyramid_bytes", "fb_build_pyramid", "fb_nnf_init", "fb_patchmatch_level", "fb_remap",
-            "fb_blend_window", "fb_interpolate", "fb_patchmatch_batch"]
+            "fb_blend_window", "fb_interpolate", "fb_patchmatch_batch", "fb_profile_enable",
+            "fb_profile_read"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -74,6 +82,8 @@ def load_library(path: str = LIB_PATH):
         "fb_blend_window": (i32, [vp, vp, vp, i32, i32, i32, i32, P, vp, vp]),
         "fb_interpolate": (i32, [vp, vp, i32, i32, i32, vp, vp, i32, P, vp, vp]),
         "fb_patchmatch_batch": (i32, [vp, ctypes.POINTER(fb_pair_desc), i32, P, vp]),
+        "fb_profile_enable": (i32, [vp, i32]),
+        "fb_profile_read": (i32, [vp, ctypes.POINTER(fb_profile), i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -148,6 +158,17 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+    # ---- measurement ----------------------------------------------------
+    def fb_profile_enable(self, on: bool = True):
+        _check(load_library().fb_profile_enable(self.handle, 1 if on else 0), "fb_profile_enable")
+
+    def fb_profile_read(self, reset: bool = False) -> dict:
+        """{kernel kind: (launches, summed milliseconds)} from the HIP events."""
+        pr = fb_profile()
+        _check(load_library().fb_profile_read(self.handle, ctypes.byref(pr), 1 if reset else 0),
+               "fb_profile_read")
+        return {k: (int(pr.launches[i]), float(pr.milliseconds[i])) for i, k in enumerate(KERNEL_KINDS)}
 
     # ---- tuning ---------------------------------------------------------
     def fb_set_tile_config(self, index: int):
