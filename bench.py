@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
+    ap.add_argument("--no-energy", action="store_true", help="skip the mean-energy pass")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (counter calibration)")
     args = ap.parse_args()
@@ -132,27 +134,31 @@ def main():
     ms = (t1 - t0) / args.steps * 1e3
     log("timed %d steps: %.2f ms/step" % (args.steps, ms))
 
-    # the same steps replayed as one HIP graph per step
-    gprm = fbm.make_params(p, levels, iters, seed, fbm.FB_USE_GRAPH)
-    side = torch.cuda.Stream()
-    with torch.cuda.stream(side):
-        ctx.fb_blend_window(g, s, M, gprm, out=out)
-        side.synchronize()
-        t2 = time.perf_counter()
-        for _ in range(args.steps):
+    graph_ms = None
+    if not args.no_graph:
+        # the same steps replayed as one HIP graph per step
+        gprm = fbm.make_params(p, levels, iters, seed, fbm.FB_USE_GRAPH)
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
             ctx.fb_blend_window(g, s, M, gprm, out=out)
-        side.synchronize()
-        t3 = time.perf_counter()
-    graph_ms = (t3 - t2) / args.steps * 1e3
-    log("graph replay: %.2f ms/step" % graph_ms)
+            side.synchronize()
+            t2 = time.perf_counter()
+            for _ in range(args.steps):
+                ctx.fb_blend_window(g, s, M, gprm, out=out)
+            side.synchronize()
+            t3 = time.perf_counter()
+        graph_ms = round((t3 - t2) / args.steps * 1e3, 3)
+        log("graph replay: %.2f ms/step" % graph_ms)
 
-    # quality: mean level-0 patch energy of all pairs (outside the timed region)
-    pyrs = [ctx.fb_build_pyramid(g[f], levels, p) for f in range(N)]
-    descs = [dict(src_pyr=pyrs[j], tgt_pyr=pyrs[i], h=h, w=w, levels=levels, pair_id=j * N + i)
-             for (j, i) in pairs]
-    energies = [e for _, e in ctx.fb_patchmatch_batch(descs, prm)]
-    mean_energy = float(torch.stack(energies).double().mean().item())
-    del energies, pyrs
+    mean_energy = None
+    if not args.no_energy:
+        # quality: mean level-0 patch energy of all pairs (outside the timed region)
+        pyrs = [ctx.fb_build_pyramid(g[f], levels, p) for f in range(N)]
+        descs = [dict(src_pyr=pyrs[j], tgt_pyr=pyrs[i], h=h, w=w, levels=levels, pair_id=j * N + i)
+                 for (j, i) in pairs]
+        energies = [e for _, e in ctx.fb_patchmatch_batch(descs, prm)]
+        mean_energy = round(float(torch.stack(energies).double().mean().item()), 2)
+        del energies, pyrs
 
     n_iter, iter_ms = prof["pm_iter"]
     iter_ms_step = iter_ms / args.steps
@@ -188,9 +194,9 @@ def main():
                    "frames": N, "height": h, "width": w, "window_radius": M, "pairs": len(pairs),
                    "patch": 2 * p + 1, "levels": levels, "iters": iters},
         "blended_frames_per_s": round(N / (ms / 1e3), 3),
-        "graph_ms_per_step": round(graph_ms, 3),
+        "graph_ms_per_step": graph_ms,
         "pixel_iterations_per_step": pix,
-        "mean_level0_patch_energy": round(mean_energy, 2),
+        "mean_level0_patch_energy": mean_energy,
         "kernel_ms_per_step": kernel_ms,
         "roofline": {"bound": "alu", "kernel": "k_pm_iter",
                      "achieved": round(achieved, 3), "peak": round(DOT4_PEAK_TOPS, 1), "unit": "TOP/s",

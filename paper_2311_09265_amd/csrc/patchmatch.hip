@@ -79,62 +79,92 @@ __device__ __forceinline__ int find_job(const PMJob *__restrict__ jobs, int n, i
     return lo;
 }
 
-// A patch row: K = 2P+1 aligned 4-byte (R,G,B,0) pixels, one 16-byte and one
-// 4-byte load for P = 2.
-template <int K>
-struct __attribute__((packed, aligned(4))) PixRow {
-    uint32_t v[K];
+// Device data is read through global (address space 1) pointers: the job
+// table only holds generic pointers, and generic loads would compile to flat
+// instructions, which wait on both memory counters.  Offsets from the
+// wave-uniform image base stay 32-bit.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T *;
+template <class T>
+using gptr_mut = __attribute__((address_space(1))) T *;
+
+// (a C-style cast is the one that may change the address space)
+template <class T>
+__device__ __forceinline__ T gload(const void *base, uint32_t byte_off) {
+    return *(gptr<T>)((gptr<char>)base + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void gstore(void *base, uint32_t byte_off, T v) {
+    *(gptr_mut<T>)((gptr_mut<char>)base + byte_off) = v;
+}
+
+// N aligned 4-byte (R,G,B,0) pixels: one 16-byte and one 4-byte load for N = 5.
+template <int N>
+struct PixRow {
+    uint32_t v[N];
 };
+
+template <int N>
+__device__ __forceinline__ PixRow<N> load_pixrow(const void *base, uint32_t byte_off) {
+    gptr<uint32_t> p = (gptr<uint32_t>)((gptr<char>)base + byte_off);
+    PixRow<N> r;
+#pragma unroll
+    for (int j = 0; j < N; ++j) r.v[j] = p[j];
+    return r;
+}
 
 template <int P>
 struct TargetPatch {
     static constexpr int K = 2 * P + 1;
+    static constexpr int S1 = K < 4 ? K : 4;  // pixels of the first-row test
     uint32_t px[K][K];
     uint32_t row_tt[K];  // sum t^2 of every row
+    uint32_t head_tt;    // sum t^2 of the first S1 pixels of row 0
     uint32_t tt;         // sum t^2 of the patch
 };
 
 template <int P>
-__device__ __forceinline__ void load_target_patch(const uint32_t *__restrict__ tp, int pitch,
+__device__ __forceinline__ void load_target_patch(const uint32_t *tp, uint32_t off, uint32_t pitch_b,
                                                   TargetPatch<P> &t) {
     constexpr int K = 2 * P + 1;
     t.tt = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const PixRow<K> row = *reinterpret_cast<const PixRow<K> *>(tp + (size_t)i * pitch);
+        const PixRow<K> row = load_pixrow<K>(tp, off + (uint32_t)i * pitch_b);
         uint32_t acc = 0;
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             t.px[i][j] = row.v[j];
             acc = __builtin_amdgcn_udot4(row.v[j], row.v[j], acc, false);
+            if (i == 0 && j == TargetPatch<P>::S1 - 1) t.head_tt = acc;
         }
         t.row_tt[i] = acc;
         t.tt += acc;
     }
 }
 
-// Eq. 1 restricted to patch row i: sum s^2 + sum t^2 - 2 sum s t over that row
-template <int P>
-__device__ __forceinline__ uint32_t row_loss(const uint32_t *__restrict__ sp, const TargetPatch<P> &t,
+// sum s^2 - 2 sum s t over pixels [J0, J0 + N) of patch row i
+template <int P, int J0, int N>
+__device__ __forceinline__ uint32_t seg_loss(const uint32_t *sp, uint32_t off, const TargetPatch<P> &t,
                                              int i) {
-    constexpr int K = 2 * P + 1;
-    const PixRow<K> row = *reinterpret_cast<const PixRow<K> *>(sp);
+    const PixRow<N> row = load_pixrow<N>(sp, off);
     uint32_t st = 0, ss = 0;
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        st = __builtin_amdgcn_udot4(row.v[j], t.px[i][j], st, false);
+    for (int j = 0; j < N; ++j) {
+        st = __builtin_amdgcn_udot4(row.v[j], t.px[i][J0 + j], st, false);
         ss = __builtin_amdgcn_udot4(row.v[j], row.v[j], ss, false);
     }
-    return ss + t.row_tt[i] - 2u * st;
+    return ss - 2u * st;
 }
 
-// Eq. 1 for the source patch whose top-left padded pixel is sp
+// Eq. 1 for the source patch whose top-left padded pixel is at byte offset off
 template <int P>
-__device__ __forceinline__ uint32_t patch_loss(const uint32_t *__restrict__ sp, int pitch,
+__device__ __forceinline__ uint32_t patch_loss(const uint32_t *sp, uint32_t off, uint32_t pitch_b,
                                                const TargetPatch<P> &t) {
-    uint32_t e = 0;
+    constexpr int K = 2 * P + 1;
+    uint32_t e = t.tt;
 #pragma unroll
-    for (int i = 0; i < 2 * P + 1; ++i) e += row_loss<P>(sp + (size_t)i * pitch, t, i);
+    for (int i = 0; i < K; ++i) e += seg_loss<P, 0, K>(sp, off + (uint32_t)i * pitch_b, t, i);
     return e;
 }
 
@@ -202,10 +232,11 @@ k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unif
         return;
     }
     }
+    const uint32_t pitch_b = 4u * (uint32_t)J.pitch;
     TargetPatch<P> t;
-    load_target_patch<P>(J.tgt_px + (size_t)r * J.pitch + c, J.pitch, t);
-    J.f_out[v] = ((uint32_t)fr << 16) | (uint32_t)fc;
-    J.e_out[v] = patch_loss<P>(J.src_px + (size_t)fr * J.pitch + fc, J.pitch, t);
+    load_target_patch<P>(J.tgt_px, 4u * (uint32_t)(r * J.pitch + c), pitch_b, t);
+    gstore<uint32_t>(J.f_out, 4u * v, ((uint32_t)fr << 16) | (uint32_t)fc);
+    gstore<uint32_t>(J.e_out, 4u * v, patch_loss<P>(J.src_px, 4u * (uint32_t)(fr * J.pitch + fc), pitch_b, t));
 }
 
 template <int P, int TW, int TH>
@@ -217,44 +248,49 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     const PMJob &J = jobs[tc.job];
     const int h = J.h, w = J.w, pitch = J.pitch, r = tc.r, c = tc.c;
     const int v = r * w + c;
-    const uint32_t *__restrict__ f_in = J.f_in;
-    const uint32_t *__restrict__ src_px = J.src_px;
+    const uint32_t pitch_b = 4u * (uint32_t)pitch;
+    const uint32_t *f_in = J.f_in;
+    const uint32_t *src_px = J.src_px;
+    constexpr int K = 2 * P + 1, S1 = TargetPatch<P>::S1;
 
     TargetPatch<P> t;
-    load_target_patch<P>(J.tgt_px + (size_t)r * pitch + c, pitch, t);
+    load_target_patch<P>(J.tgt_px, 4u * (uint32_t)(r * pitch + c), pitch_b, t);
 
-    const uint32_t f0 = f_in[v];
+    const uint32_t f0 = gload<uint32_t>(f_in, 4u * v);
     int br = (int)(f0 >> 16), bc = (int)(f0 & 0xFFFFu);
-    uint32_t be = J.e_in[v];
+    uint32_t be = gload<uint32_t>(J.e_in, 4u * v);
 
-    // Every row's share of the loss is a sum of squares, so once the first row
-    // alone reaches the running best the candidate cannot pass '<': the other
-    // rows are never fetched.  Far random-search candidates usually stop there.
+    // Every pixel's share of the loss is a square, so once the first S1
+    // pixels of row 0 alone reach the running best the candidate cannot pass
+    // '<': the rest of its patch is never fetched.  Far random-search
+    // candidates, divergent gathers, usually stop after that one load.
     auto consider = [&](int cr, int cc) {
         if (cr == br && cc == bc) return;
-        const uint32_t *sp = src_px + (size_t)cr * pitch + cc;
-        uint32_t e = row_loss<P>(sp, t, 0);
+        const uint32_t off = 4u * (uint32_t)(cr * pitch + cc);
+        uint32_t e = t.head_tt + seg_loss<P, 0, S1>(src_px, off, t, 0);
         if (e >= be) return;
+        if constexpr (S1 < K)
+            e += (t.row_tt[0] - t.head_tt) + seg_loss<P, S1, K - S1>(src_px, off + 4u * S1, t, 0);
 #pragma unroll
-        for (int i = 1; i < 2 * P + 1; ++i) e += row_loss<P>(sp + (size_t)i * pitch, t, i);
+        for (int i = 1; i < K; ++i) e += t.row_tt[i] + seg_loss<P, 0, K>(src_px, off + (uint32_t)i * pitch_b, t, i);
         if (e < be) { br = cr; bc = cc; be = e; }
     };
 
     // propagation: F(v + d) - d for d = (-1,0), (1,0), (0,-1), (0,1)
     if (r > 0) {
-        const uint32_t q = f_in[v - w];
+        const uint32_t q = gload<uint32_t>(f_in, 4u * (v - w));
         consider(min((int)(q >> 16) + 1, h - 1), (int)(q & 0xFFFFu));
     }
     if (r < h - 1) {
-        const uint32_t q = f_in[v + w];
+        const uint32_t q = gload<uint32_t>(f_in, 4u * (v + w));
         consider(max((int)(q >> 16) - 1, 0), (int)(q & 0xFFFFu));
     }
     if (c > 0) {
-        const uint32_t q = f_in[v - 1];
+        const uint32_t q = gload<uint32_t>(f_in, 4u * (v - 1));
         consider((int)(q >> 16), min((int)(q & 0xFFFFu) + 1, w - 1));
     }
     if (c < w - 1) {
-        const uint32_t q = f_in[v + 1];
+        const uint32_t q = gload<uint32_t>(f_in, 4u * (v + 1));
         consider((int)(q >> 16), max((int)(q & 0xFFFFu) - 1, 0));
     }
 
@@ -272,8 +308,8 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
         const int dc = u16_to_range(word >> 16, n) - rho;
         consider(clampi(br + dr, 0, h - 1), clampi(bc + dc, 0, w - 1));
     }
-    J.f_out[v] = ((uint32_t)br << 16) | (uint32_t)bc;
-    J.e_out[v] = be;
+    gstore<uint32_t>(J.f_out, 4u * v, ((uint32_t)br << 16) | (uint32_t)bc);
+    gstore<uint32_t>(J.e_out, 4u * v, be);
 }
 
 template <int TW, int TH>

@@ -463,6 +463,9 @@ fb_status check_params(const fb_params *prm, bool need_levels) {
 fb_status check_size(int h, int w) {
     if (h < 1 || w < 1) return fail(FB_E_INVALID, "image sizes must be positive");
     if (h > 32767 || w > 32767) return fail(FB_E_UNSUPPORTED, "image sides are limited to 32767");
+    // kernels address a padded frame with 32-bit byte offsets
+    if ((uint64_t)(h + 2 * kMaxP) * (uint64_t)(w + 2 * kMaxP + kPitchAlign) * 4u >= (1ull << 31))
+        return fail(FB_E_UNSUPPORTED, "a padded frame must stay below 2 GiB");
     return FB_OK;
 }
 
