@@ -53,6 +53,7 @@ typedef enum {
 /* Flags of fb_params.flags */
 #define FB_USE_GRAPH   0x1u  /* replay the batched launch sequence as a HIP graph */
 #define FB_NO_AUTOTUNE 0x2u  /* use the default tile shape, skip the autotuner    */
+#define FB_LEARNED_SEED 0x4u /* seed the coarsest level with the proposal network */
 
 /* PatchMatch parameters (Algorithm 1).  The paper names p, n and the pyramid
  * but gives no values; 2 / 3 / 6 are the values of the 512x512 blending
@@ -194,6 +195,7 @@ enum {
     FB_KERNEL_PM_EXPORT = 3, /* packed field -> int32 NNF + energies          */
     FB_KERNEL_REMAP = 4,     /* remap-sum (Alg. 2 + Eq. 2 / Eq. 9)            */
     FB_KERNEL_OTHER = 5,
+    FB_KERNEL_UNET = 6,      /* proposal network forward for a group of pairs */
     FB_KERNEL_KINDS = 8
 };
 typedef struct {
@@ -203,6 +205,42 @@ typedef struct {
 
 fb_status fb_profile_enable(fb_ctx *ctx, int32_t on);
 fb_status fb_profile_read(fb_ctx *ctx, fb_profile *out, int32_t reset);
+
+/* ---------------------------------------------------------------------- */
+/* Learned proposal (a project addition; the paper's method is model-free, */
+/* Section 3.1).  A 4-level U-Net with (32, 48, 96, 192) channels maps a   */
+/* frame pair at the coarsest pyramid level (6 channels: source RGB,       */
+/* target RGB, in [0, 1]) to a 2-channel offset field (row, col, pixels of */
+/* that level).  bf16 weights and activations, fp32 accumulation on the    */
+/* matrix cores.  With FB_LEARNED_SEED in fb_params.flags, the blend,      */
+/* interpolation and batch calls seed every pair's coarsest level with the */
+/* rounded prediction (F = clamp(v + offset)) instead of the random draw;  */
+/* the plain random initialisation stays the default and the fallback.     */
+/*                                                                         */
+/* Parameters are a flat fp32 vector of fb_unet_param_count() values: for */
+/* each of the 15 convolutions in order, its weight [cout][cin][3][3] then */
+/* its bias [cout].  Tensors below are device pointers, NHWC:              */
+/*   pair6 float [B][h][w][6]; offsets / target float [B][h][w][2];        */
+/*   mask float [B][h][w] (per-pixel loss weight); h, w multiples of 8.    */
+/* Training minimises sum(mask * |pred - target|_1) / max(sum(mask), 1)    */
+/* with Adam (beta 0.9 / 0.999, eps 1e-8); `loss` receives the value       */
+/* before the update.  Loading parameters resets the Adam state.           */
+/* ---------------------------------------------------------------------- */
+int64_t fb_unet_param_count(void);
+double fb_unet_forward_flops(int32_t B, int32_t h, int32_t w);
+fb_status fb_unet_load(fb_ctx *ctx, const float *params, void *stream);
+fb_status fb_unet_save(fb_ctx *ctx, float *params, void *stream);
+fb_status fb_unet_forward(fb_ctx *ctx, const float *pair6, int32_t B, int32_t h, int32_t w,
+                          float *offsets, void *stream);
+fb_status fb_unet_gradients(fb_ctx *ctx, const float *pair6, const float *target, const float *mask,
+                            int32_t B, int32_t h, int32_t w, float *grads, float *loss, void *stream);
+fb_status fb_unet_train_step(fb_ctx *ctx, const float *pair6, const float *target, const float *mask,
+                             int32_t B, int32_t h, int32_t w, float lr, float *loss, void *stream);
+/* The network input of one pair exactly as FB_LEARNED_SEED builds it: the
+ * coarsest level (levels - 1) of both pyramids, padded to multiples of 8 by
+ * repeating the last row / column, pair6 float [H8][W8][6] = pixels / 255. */
+fb_status fb_unet_pair_input(fb_ctx *ctx, const void *src_pyr, const void *tgt_pyr, int32_t h, int32_t w,
+                             int32_t levels, int32_t patch_radius, float *pair6, void *stream);
 
 #ifdef __cplusplus
 }

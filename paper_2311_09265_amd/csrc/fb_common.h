@@ -117,4 +117,62 @@ hipError_t launch_remap_sum(const RemapFrame *frames, int n_frames, const RemapT
 
 hipError_t launch_field_to_packed(const int32_t *abi, uint32_t *packed, int h, int w, hipStream_t s);
 
+// ---- learned proposal network (unet.hip, unet_net.hip) ----
+// one pair's coarsest pyramid level as network input
+struct UNetPairIn {
+    const uint32_t *src, *tgt;  // padded pixels of the level
+    int32_t h, w, pitch, pad;
+};
+
+hipError_t launch_conv3x3(const uint16_t *in, int B, int H, int W, int cin, const uint16_t *wt,
+                          const float *bias, void *out, int cout, bool relu, bool out_f32, hipStream_t s);
+hipError_t launch_conv_wgrad(const uint16_t *in, const uint16_t *g, int B, int H, int W, int cin, int cout,
+                             int chunk_px, float *partial, float *bias_partial, hipStream_t s);
+hipError_t launch_reduce_chunks(const float *partial, int n_chunks, long n, float *out, hipStream_t s);
+hipError_t launch_pool2(const uint16_t *in, int B, int H, int W, int C, uint16_t *out, hipStream_t s);
+hipError_t launch_pool2_bwd_add(const uint16_t *gout, int B, int H, int W, int C, uint16_t *gin, hipStream_t s);
+hipError_t launch_upcat(const uint16_t *deep, const uint16_t *skip, int B, int H, int W, int C1, int C2,
+                        uint16_t *out, hipStream_t s);
+hipError_t launch_upcat_bwd(const uint16_t *gcat, int B, int H, int W, int C1, int C2, uint16_t *gdeep,
+                            uint16_t *gskip, hipStream_t s);
+hipError_t launch_relu_mask(uint16_t *g, const uint16_t *y, long n, hipStream_t s);
+hipError_t launch_input_from_f32(const float *x6, long n_px, uint16_t *out, hipStream_t s);
+hipError_t launch_input_from_pyramids(const UNetPairIn *pairs, int n, int H8, int W8, uint16_t *out,
+                                      hipStream_t s);
+hipError_t launch_pred_to_seed(const float *pred, int H8, int W8, const UNetPairIn *pairs, int32_t *const *seeds,
+                               int n, hipStream_t s);
+hipError_t launch_pred_extract(const float *pred, long n_px, float *out, hipStream_t s);
+hipError_t launch_input_f32_from_pyramid(const UNetPairIn &pair, int H8, int W8, float *out, hipStream_t s);
+hipError_t launch_loss(const float *pred, const float *target, const float *mask, long n_px, float *partial,
+                       float *totals, uint16_t *grad, hipStream_t s);
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, long n_w, long n_total, int cout, int cin,
+                       float lr, float b1, float b2, float eps, float c1, float c2, uint16_t *w16, uint16_t *wt16,
+                       hipStream_t s);
+hipError_t launch_weights_to_bf16(const float *w, long n_w, int cout, int cin, uint16_t *w16, uint16_t *wt16,
+                                  hipStream_t s);
+hipError_t launch_param_layout(float *flat, float *padded, int cout_r, int cin_r, int cout, int cin, bool to_padded,
+                               hipStream_t s);
+hipError_t launch_fill_zero(float *p, long n, hipStream_t s);
+
+struct UNet;
+UNet *unet_create();
+void unet_destroy(UNet *u);
+int64_t unet_param_count();
+bool unet_loaded(const UNet *u);
+hipError_t unet_load(UNet *u, const float *flat, hipStream_t s);
+hipError_t unet_save(UNet *u, float *flat, hipStream_t s);
+hipError_t unet_grads_flat(UNet *u, float *flat, hipStream_t s);
+// reserve: allocate (if needed) and bind the workspace for this shape;
+// shape: bind a shape that fits the reserved workspace, never allocating
+hipError_t unet_reserve(UNet *u, int B, int H, int W, bool training);
+hipError_t unet_shape(UNet *u, int B, int H, int W, bool training);
+uint16_t *unet_input_buffer(UNet *u);
+float *unet_pred_buffer(UNet *u);
+float *unet_loss_buffer(UNet *u);
+hipError_t unet_input_from_f32(UNet *u, const float *x6, hipStream_t s);
+hipError_t unet_forward(UNet *u, hipStream_t s);
+hipError_t unet_loss_backward(UNet *u, const float *target, const float *mask, bool backward, hipStream_t s);
+hipError_t unet_adam(UNet *u, float lr, hipStream_t s);
+double unet_forward_flops(int B, int H, int W);
+
 }  // namespace fb

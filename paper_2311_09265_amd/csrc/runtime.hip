@@ -292,6 +292,8 @@ struct fb_ctx {
     hipStream_t graph_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     // kernel timing: events bracketing each launch, read lazily
+    UNet *unet = nullptr;
+    Buf seeds, unet_tab;
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;
     struct Mark { int kind; hipEvent_t a, b; };
@@ -450,6 +452,88 @@ fb_status drain_marks(fb_ctx *ctx) {
 
 bool valid_p(int p) { return p >= 1 && p <= kMaxP; }
 
+constexpr int kUNetChunk = 64;  // pairs per network launch sequence
+
+// Learned proposal: the network predicts each pair's offset field at its
+// coarsest level from the two coarsest pyramid levels; the rounded offsets
+// seed the level (kStartOffsets) instead of the random draw.  Pairs that
+// already carry seed offsets keep them.  Consecutive pairs with the same
+// coarsest size share network launches (up to kUNetChunk pairs).
+fb_status plan_learned_seeds(fb_ctx *ctx, Plan &P, std::vector<PairSpec> &pairs) {
+    if (!unet_loaded(ctx->unet))
+        return fail(FB_E_INVALID, "FB_LEARNED_SEED needs network parameters (fb_unet_load)");
+    struct Group { size_t first, count; int H8, W8; };
+    std::vector<Group> groups;
+    size_t seed_elems = 0;
+    std::vector<size_t> seed_off(pairs.size(), 0);
+    int maxB = 0, maxH8 = 8, maxW8 = 8;
+    for (size_t k = 0; k < pairs.size(); ++k) {
+        if (pairs[k].seed_offsets) continue;
+        const LevelGeom &g = pairs[k].L.lv[pairs[k].L.levels - 1];
+        const int H8 = (g.h + 7) / 8 * 8, W8 = (g.w + 7) / 8 * 8;
+        if (!groups.empty() && groups.back().first + groups.back().count == k && groups.back().H8 == H8 &&
+            groups.back().W8 == W8 && groups.back().count < (size_t)kUNetChunk)
+            ++groups.back().count;
+        else
+            groups.push_back({k, 1, H8, W8});
+        seed_off[k] = seed_elems;
+        seed_elems += (size_t)g.h * g.w * 2;
+    }
+    if (groups.empty()) return FB_OK;
+    // the largest group shape bounds the workspace (bound without allocating later)
+    size_t best = 0;
+    for (const Group &gr : groups) {
+        const size_t need = gr.count * (size_t)gr.H8 * gr.W8;
+        if (need > best) { best = need; maxB = (int)gr.count; maxH8 = gr.H8; maxW8 = gr.W8; }
+    }
+    fb_status st;
+    if ((st = ensure(ctx, ctx->seeds, std::max<size_t>(seed_elems, 1) * 4))) return st;
+    for (const Group &gr : groups) {
+        // reserve for every group shape so that binding any of them later fits
+        hipError_t e = unet_reserve(ctx->unet, (int)gr.count, gr.H8, gr.W8, false);
+        if (e != hipSuccess) return fail(FB_E_ALLOC, std::string("network workspace: ") + hipGetErrorString(e));
+    }
+    (void)maxB; (void)maxH8; (void)maxW8;
+    int32_t *seeds = static_cast<int32_t *>(ctx->seeds.p);
+    UNet *u = ctx->unet;
+    // captured launches hold workspace addresses: a new workspace is a new plan
+    sig_add(P, "unetws", (long long)(uintptr_t)unet_input_buffer(u), (long long)(uintptr_t)seeds);
+    for (const Group &gr : groups) {
+        std::vector<UNetPairIn> in(gr.count);
+        std::vector<int32_t *> dst(gr.count);
+        for (size_t q = 0; q < gr.count; ++q) {
+            PairSpec &ps = pairs[gr.first + q];
+            const LevelGeom &g = ps.L.lv[ps.L.levels - 1];
+            in[q] = UNetPairIn{reinterpret_cast<const uint32_t *>(ps.src_pyr + g.px_off),
+                               reinterpret_cast<const uint32_t *>(ps.tgt_pyr + g.px_off), g.h, g.w, g.pitch,
+                               ps.L.p};
+            dst[q] = seeds + seed_off[gr.first + q];
+            ps.seed_offsets = dst[q];
+        }
+        const size_t in_off = table_append(P, in.data(), in.size());
+        const size_t dst_off = table_append(P, dst.data(), dst.size());
+        const int B = (int)gr.count, H8 = gr.H8, W8 = gr.W8;
+        sig_add(P, "unet", (long long)in_off, (long long)dst_off, B, ((long long)H8 << 32) | W8);
+        P.ops.push_back({FB_KERNEL_UNET, [=](hipStream_t s, const uint8_t *tab) {
+            hipError_t e = unet_shape(u, B, H8, W8, false);
+            if (e != hipSuccess) return e;
+            const UNetPairIn *pin = reinterpret_cast<const UNetPairIn *>(tab + in_off);
+            if ((e = launch_input_from_pyramids(pin, B, H8, W8, unet_input_buffer(u), s)) != hipSuccess) return e;
+            if ((e = unet_forward(u, s)) != hipSuccess) return e;
+            return launch_pred_to_seed(unet_pred_buffer(u), H8, W8, pin,
+                                       reinterpret_cast<int32_t *const *>(tab + dst_off), B, s);
+        }});
+    }
+    return FB_OK;
+}
+
+fb_status check_unet_shape(int B, int h, int w) {
+    if (B < 1 || h < 8 || w < 8 || h % 8 || w % 8)
+        return fail(FB_E_SHAPE, "network input needs B >= 1 and h, w positive multiples of 8");
+    if ((long long)B * h * w > (1LL << 28)) return fail(FB_E_UNSUPPORTED, "network batch too large");
+    return FB_OK;
+}
+
 fb_status check_params(const fb_params *prm, bool need_levels) {
     if (!prm) return fail(FB_E_INVALID, "params is NULL");
     if (!valid_p(prm->patch_radius))
@@ -504,6 +588,9 @@ void fb_destroy(fb_ctx *ctx) {
         (void)hipEventDestroy(m.b);
     }
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+    unet_destroy(ctx->unet);
+    for (Buf *b : {&ctx->seeds, &ctx->unet_tab})
+        if (b->p) (void)hipFree(b->p);
     for (Buf *b : {&ctx->table, &ctx->pyr, &ctx->style, &ctx->fe, &ctx->tune_table})
         if (b->p) (void)hipFree(b->p);
     delete ctx;
@@ -725,6 +812,8 @@ fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *sty
             ps.e[1] = fe + (3 * n_pairs + k) * npx;
             pairs.push_back(ps);
         }
+    if (params->flags & FB_LEARNED_SEED)
+        if ((st = plan_learned_seeds(ctx, P, pairs))) return st;
     const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
     plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg);
 
@@ -811,6 +900,8 @@ fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, i
             pair_key.push_back(k);
         }
     }
+    if (params->flags & FB_LEARNED_SEED)
+        if ((st = plan_learned_seeds(ctx, P, pairs))) return st;
     const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
     plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg);
 
@@ -878,10 +969,110 @@ fb_status fb_patchmatch_batch(fb_ctx *ctx, const fb_pair_desc *pairs_in, int32_t
         off += (size_t)d.h * d.w;
         pairs.push_back(ps);
     }
-    const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
     Plan P;
+    if (params->flags & FB_LEARNED_SEED)
+        if ((st = plan_learned_seeds(ctx, P, pairs))) return st;
+    const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
     plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg);
     return run_plan(ctx, P, params->flags, static_cast<hipStream_t>(stream), p, params->seed);
+}
+
+int64_t fb_unet_param_count(void) { return unet_param_count(); }
+
+static fb_status unet_ctx(fb_ctx *ctx) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!ctx->unet) ctx->unet = unet_create();
+    return FB_OK;
+}
+
+fb_status fb_unet_load(fb_ctx *ctx, const float *params, void *stream) {
+    fb_status st = unet_ctx(ctx);
+    if (st) return st;
+    if (!params) return fail(FB_E_INVALID, "params is NULL");
+    FB_HIP(unet_load(ctx->unet, params, static_cast<hipStream_t>(stream)));
+    return FB_OK;
+}
+
+fb_status fb_unet_save(fb_ctx *ctx, float *params, void *stream) {
+    fb_status st = unet_ctx(ctx);
+    if (st) return st;
+    if (!params) return fail(FB_E_INVALID, "params is NULL");
+    if (!unet_loaded(ctx->unet)) return fail(FB_E_INVALID, "no network parameters loaded");
+    FB_HIP(unet_save(ctx->unet, params, static_cast<hipStream_t>(stream)));
+    return FB_OK;
+}
+
+fb_status fb_unet_forward(fb_ctx *ctx, const float *pair6, int32_t B, int32_t h, int32_t w, float *offsets,
+                          void *stream) {
+    fb_status st = unet_ctx(ctx);
+    if (st) return st;
+    if (!pair6 || !offsets) return fail(FB_E_INVALID, "null pointer");
+    if ((st = check_unet_shape(B, h, w))) return st;
+    if (!unet_loaded(ctx->unet)) return fail(FB_E_INVALID, "no network parameters loaded");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    UNet *u = ctx->unet;
+    FB_HIP(unet_reserve(u, B, h, w, false));
+    FB_HIP(unet_input_from_f32(u, pair6, s));
+    FB_HIP(unet_forward(u, s));
+    FB_HIP(launch_pred_extract(unet_pred_buffer(u), (long)B * h * w, offsets, s));
+    return FB_OK;
+}
+
+static fb_status unet_backward_common(fb_ctx *ctx, const float *pair6, const float *target, const float *mask,
+                                      int32_t B, int32_t h, int32_t w, float *loss, hipStream_t s) {
+    fb_status st = unet_ctx(ctx);
+    if (st) return st;
+    if (!pair6 || !target || !mask) return fail(FB_E_INVALID, "null pointer");
+    if ((st = check_unet_shape(B, h, w))) return st;
+    if (!unet_loaded(ctx->unet)) return fail(FB_E_INVALID, "no network parameters loaded");
+    UNet *u = ctx->unet;
+    FB_HIP(unet_reserve(u, B, h, w, true));
+    FB_HIP(unet_input_from_f32(u, pair6, s));
+    FB_HIP(unet_forward(u, s));
+    FB_HIP(unet_loss_backward(u, target, mask, true, s));
+    if (loss) FB_HIP(hipMemcpyAsync(loss, unet_loss_buffer(u), sizeof(float), hipMemcpyDeviceToDevice, s));
+    return FB_OK;
+}
+
+fb_status fb_unet_gradients(fb_ctx *ctx, const float *pair6, const float *target, const float *mask, int32_t B,
+                            int32_t h, int32_t w, float *grads, float *loss, void *stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!grads) return fail(FB_E_INVALID, "grads is NULL");
+    fb_status st = unet_backward_common(ctx, pair6, target, mask, B, h, w, loss, s);
+    if (st) return st;
+    FB_HIP(unet_grads_flat(ctx->unet, grads, s));
+    return FB_OK;
+}
+
+fb_status fb_unet_train_step(fb_ctx *ctx, const float *pair6, const float *target, const float *mask, int32_t B,
+                             int32_t h, int32_t w, float lr, float *loss, void *stream) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!(lr > 0.f)) return fail(FB_E_INVALID, "lr must be positive");
+    fb_status st = unet_backward_common(ctx, pair6, target, mask, B, h, w, loss, s);
+    if (st) return st;
+    FB_HIP(unet_adam(ctx->unet, lr, s));
+    return FB_OK;
+}
+
+double fb_unet_forward_flops(int32_t B, int32_t h, int32_t w) { return unet_forward_flops(B, h, w); }
+
+fb_status fb_unet_pair_input(fb_ctx *ctx, const void *src_pyr, const void *tgt_pyr, int32_t h, int32_t w,
+                             int32_t levels, int32_t patch_radius, float *pair6, void *stream) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!src_pyr || !tgt_pyr || !pair6) return fail(FB_E_INVALID, "null pointer");
+    if ((st = check_size(h, w))) return st;
+    if (levels < 1 || levels > kMaxLevels) return fail(FB_E_INVALID, "levels must be in [1, 16]");
+    if (!valid_p(patch_radius)) return fail(FB_E_UNSUPPORTED, "patch_radius must be in [1, 4]");
+    const PyrLayout L = pyr_layout(h, w, levels, patch_radius);
+    const LevelGeom &g = L.lv[levels - 1];
+    const UNetPairIn in{reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(src_pyr) + g.px_off),
+                        reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(tgt_pyr) + g.px_off),
+                        g.h, g.w, g.pitch, patch_radius};
+    FB_HIP(launch_input_f32_from_pyramid(in, (g.h + 7) / 8 * 8, (g.w + 7) / 8 * 8, pair6,
+                                         static_cast<hipStream_t>(stream)));
+    return FB_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,592 @@
+// Kernels of the learned proposal network (a small U-Net that predicts an
+// initial offset field for PatchMatch).  The network is not part of the
+// paper: FastBlend is model-free; this proposal only seeds the coarsest
+// pyramid level of Algorithm 1, and plain PatchMatch stays the fallback.
+//
+// Tensors are NHWC with the channel count padded to a multiple of 16;
+// activations and activation gradients are bf16, weights are bf16 copies of
+// fp32 master weights, all products accumulate in fp32.
+//
+// 3x3 convolutions (padding 1, stride 1) are implicit GEMMs on the matrix
+// cores: v_mfma_f32_16x16x16_bf16 with M = pixels, N = output channels,
+// K = 9 taps x input channels in chunks of 16 channels of one tap.  The same
+// kernel computes the data gradient with the flipped, transposed weights.
+// Weight gradients are a second implicit GEMM with K = pixels, split into
+// chunks whose partial sums a reduction kernel adds in a fixed order.
+//
+// Matrix-core lane layout of the 16x16x16 bf16 instruction (wave64):
+//   A (16 x 16, M x K): lane l holds A[l % 16][4 (l / 16) + j], j = 0..3
+//   B (16 x 16, K x N): lane l holds B[4 (l / 16) + j][l % 16]
+//   D (16 x 16):        lane l holds D[4 (l / 16) + j][l % 16]
+#include "fb_common.h"
+
+namespace fb {
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    // round to nearest even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x4 load_bf16x4(const uint16_t *p) {
+    const uint2 u = *reinterpret_cast<const uint2 *>(p);
+    bf16x4 r;
+    r[0] = (short)(u.x & 0xFFFFu);
+    r[1] = (short)(u.x >> 16);
+    r[2] = (short)(u.y & 0xFFFFu);
+    r[3] = (short)(u.y >> 16);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Forward / data-gradient convolution.  Workgroup: 4 waves = 64 consecutive
+// pixels of one image row; wave w owns pixels [16w, 16w+16) and NB blocks of
+// 16 output channels starting at blockIdx.y * 16 NB.
+// ---------------------------------------------------------------------------
+template <int NB, bool RELU, bool OUT_F32>
+__global__ void __launch_bounds__(256)
+k_conv3x3(const uint16_t *__restrict__ in, int B, int H, int W, int cin,
+          const uint16_t *__restrict__ wt, const float *__restrict__ bias, void *__restrict__ out,
+          int cout) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tiles_x = (W + 63) / 64;
+    int t = blockIdx.x;
+    const int tx = t % tiles_x;
+    t /= tiles_x;
+    const int y = t % H;
+    const int n = t / H;
+    const int co0 = blockIdx.y * 16 * NB;
+    const int px = tx * 64 + wave * 16 + (lane & 15);   // pixel of the A row this lane loads
+    const int kq = 4 * (lane >> 4);                       // channel quad within a 16-chunk
+    f32x4 acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tap = 0; tap < 9; ++tap) {
+        const int yy = y + tap / 3 - 1, xx = px + tap % 3 - 1;
+        const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W && px < W;
+        const uint16_t *arow = in + (((size_t)n * H + (ok ? yy : 0)) * W + (ok ? xx : 0)) * cin + kq;
+        const uint16_t *wrow = wt + ((size_t)tap * cout + co0 + (lane & 15)) * cin + kq;
+        for (int c0 = 0; c0 < cin; c0 += 16) {
+            bf16x4 a = ok ? load_bf16x4(arow + c0) : bf16x4{0, 0, 0, 0};
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                if (co0 + 16 * b >= cout) break;
+                const bf16x4 bw = load_bf16x4(wrow + (size_t)16 * b * cin + c0);
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[b], 0, 0, 0);
+            }
+        }
+    }
+    // epilogue: lane holds D[4 (lane/16) + j][lane % 16] -> pixels rows, channel column
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int co = co0 + 16 * b + (lane & 15);
+        if (co0 + 16 * b >= cout) break;
+        const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p = tx * 64 + wave * 16 + 4 * (lane >> 4) + j;
+            if (p >= W) continue;
+            float v = acc[b][j] + bv;
+            if (RELU) v = fmaxf(v, 0.f);
+            const size_t o = (((size_t)n * H + y) * W + p) * cout + co;
+            if (OUT_F32) reinterpret_cast<float *>(out)[o] = v;
+            else reinterpret_cast<uint16_t *>(out)[o] = f32_to_bf16(v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: partial[chunk][tap][co][ci] = sum over the chunk's pixels of
+// g[p][co] * in[p shifted by the tap][ci].  One wave per (chunk, tap, 16x16
+// block of (co, ci)); A = g^T (co x pixels), B = shifted input (pixels x ci).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64)
+k_conv_wgrad(const uint16_t *__restrict__ in, const uint16_t *__restrict__ g, int B, int H, int W,
+             int cin, int cout, int chunk_px, float *__restrict__ partial) {
+    const int lane = threadIdx.x;
+    const int chunk = blockIdx.x, tap = blockIdx.y;
+    const int ci_blocks = cin / 16;
+    const int cb = blockIdx.z % ci_blocks, ob = blockIdx.z / ci_blocks;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const long total = (long)B * H * W;
+    const long p0 = (long)chunk * chunk_px;
+    const int co = ob * 16 + (lane & 15), ci = cb * 16 + (lane & 15);
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < chunk_px; k0 += 16) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const long p = p0 + k0 + 4 * (lane >> 4) + j;
+            short av = 0, bv = 0;
+            if (p < total) {
+                av = (short)g[p * cout + co];
+                const int x = (int)(p % W), yq = (int)((p / W) % H);
+                const int yy = yq + dy, xx = x + dx;
+                if (yy >= 0 && yy < H && xx >= 0 && xx < W) bv = (short)in[(p + (long)dy * W + dx) * cin + ci];
+            }
+            a[j] = av;
+            b[j] = bv;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    // D[4 (lane/16) + j][lane % 16]: rows = co, columns = ci
+    float *dst = partial + (((size_t)chunk * 9 + tap) * cout) * cin;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dst[(size_t)(ob * 16 + 4 * (lane >> 4) + j) * cin + ci] = acc[j];
+}
+
+// bias gradient partial sums: partial[chunk][co] = sum of g[p][co] over the chunk
+__global__ void __launch_bounds__(256)
+k_bias_grad(const uint16_t *__restrict__ g, long total, int cout, int chunk_px, float *__restrict__ partial) {
+    const int chunk = blockIdx.x;
+    for (int co = threadIdx.x; co < cout; co += blockDim.x) {
+        float s = 0.f;
+        const long p1 = min((long)(chunk + 1) * chunk_px, total);
+        for (long p = (long)chunk * chunk_px; p < p1; ++p) s += bf16_to_f32(g[p * cout + co]);
+        partial[(size_t)chunk * cout + co] = s;
+    }
+}
+
+// out[i] = sum over chunks of partial[chunk][i], in chunk order
+__global__ void __launch_bounds__(256)
+k_reduce_chunks(const float *__restrict__ partial, int n_chunks, long n, float *__restrict__ out) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int c = 0; c < n_chunks; ++c) s += partial[(size_t)c * n + i];
+    out[i] = s;
+}
+
+// 2x2 average pooling (even sizes), bf16
+__global__ void __launch_bounds__(256)
+k_pool2(const uint16_t *__restrict__ in, int B, int H, int W, int C, uint16_t *__restrict__ out) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int Ho = H / 2, Wo = W / 2;
+    if (i >= (long)B * Ho * Wo * C) return;
+    const int c = (int)(i % C);
+    long q = i / C;
+    const int x = (int)(q % Wo);
+    q /= Wo;
+    const int y = (int)(q % Ho);
+    const int n = (int)(q / Ho);
+    const size_t base = (((size_t)n * H + 2 * y) * W + 2 * x) * C + c;
+    const float s = bf16_to_f32(in[base]) + bf16_to_f32(in[base + C]) +
+                    bf16_to_f32(in[base + (size_t)W * C]) + bf16_to_f32(in[base + (size_t)W * C + C]);
+    out[i] = f32_to_bf16(0.25f * s);
+}
+
+// gradient of 2x2 average pooling, added to gin: gin[y][x] += gout[y/2][x/2] / 4
+__global__ void __launch_bounds__(256)
+k_pool2_bwd_add(const uint16_t *__restrict__ gout, int B, int H, int W, int C, uint16_t *__restrict__ gin) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)B * H * W * C) return;
+    const int c = (int)(i % C);
+    long q = i / C;
+    const int x = (int)(q % W);
+    q /= W;
+    const int y = (int)(q % H);
+    const int n = (int)(q / H);
+    const float g = bf16_to_f32(gout[(((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c]);
+    gin[i] = f32_to_bf16(bf16_to_f32(gin[i]) + 0.25f * g);
+}
+
+// concat(nearest 2x upsample of deep [H/2][W/2][C1], skip [H][W][C2]) -> [H][W][C1 + C2]
+__global__ void __launch_bounds__(256)
+k_upcat(const uint16_t *__restrict__ deep, const uint16_t *__restrict__ skip, int B, int H, int W,
+        int C1, int C2, uint16_t *__restrict__ out) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int C = C1 + C2;
+    if (i >= (long)B * H * W * C) return;
+    const int c = (int)(i % C);
+    long q = i / C;
+    const int x = (int)(q % W);
+    q /= W;
+    const int y = (int)(q % H);
+    const int n = (int)(q / H);
+    out[i] = c < C1 ? deep[(((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * C1 + c]
+                    : skip[(((size_t)n * H + y) * W + x) * C2 + (c - C1)];
+}
+
+// gradient of k_upcat: gdeep = sum of the 2x2 block of the first C1 channels
+// (written), gskip = the other C2 channels (written)
+__global__ void __launch_bounds__(256)
+k_upcat_bwd(const uint16_t *__restrict__ gcat, int B, int H, int W, int C1, int C2,
+            uint16_t *__restrict__ gdeep, uint16_t *__restrict__ gskip) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int C = C1 + C2;
+    const long n_deep = (long)B * (H / 2) * (W / 2) * C1;
+    const long n_skip = (long)B * H * W * C2;
+    if (i < n_deep) {
+        const int c = (int)(i % C1);
+        long q = i / C1;
+        const int x = (int)(q % (W / 2));
+        q /= (W / 2);
+        const int y = (int)(q % (H / 2));
+        const int n = (int)(q / (H / 2));
+        const size_t base = (((size_t)n * H + 2 * y) * W + 2 * x) * C + c;
+        const float s = bf16_to_f32(gcat[base]) + bf16_to_f32(gcat[base + C]) +
+                        bf16_to_f32(gcat[base + (size_t)W * C]) + bf16_to_f32(gcat[base + (size_t)W * C + C]);
+        gdeep[i] = f32_to_bf16(s);
+    } else if (i < n_deep + n_skip) {
+        const long k = i - n_deep;
+        const int c = (int)(k % C2);
+        const long pix = k / C2;
+        gskip[k] = gcat[pix * C + C1 + c];
+    }
+}
+
+// g *= (y > 0): ReLU gradient through the post-activation output y
+__global__ void __launch_bounds__(256)
+k_relu_mask(uint16_t *__restrict__ g, const uint16_t *__restrict__ y, long n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!(bf16_to_f32(y[i]) > 0.f)) g[i] = 0;
+}
+
+// fp32 [n_px][6] in [0,1] -> bf16 [n_px][16] (channels 6..15 zero)
+__global__ void __launch_bounds__(256)
+k_input_from_f32(const float *__restrict__ x6, long n_px, uint16_t *__restrict__ out) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_px * 16) return;
+    const int c = (int)(i % 16);
+    out[i] = c < 6 ? f32_to_bf16(x6[(i / 16) * 6 + c]) : (uint16_t)0;
+}
+
+// network input from the coarsest pyramid level of every pair: channels
+// (source R,G,B, target R,G,B) / 255 at [H8][W8] (the level padded to a
+// multiple of 8 by replicating its last row / column)
+__global__ void __launch_bounds__(256)
+k_input_from_pyramids(const UNetPairIn *__restrict__ pairs, int H8, int W8, uint16_t *__restrict__ out) {
+    const int n = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= H8 * W8) return;
+    const UNetPairIn P = pairs[n];
+    const int y = min(i / W8, P.h - 1), x = min(i % W8, P.w - 1);
+    const uint32_t s = P.src[(size_t)(y + P.pad) * P.pitch + x + P.pad];
+    const uint32_t t = P.tgt[(size_t)(y + P.pad) * P.pitch + x + P.pad];
+    uint16_t *o = out + ((size_t)n * H8 * W8 + i) * 16;
+    // pixel / 255 as a correctly rounded fp32 division, then bf16
+    o[0] = f32_to_bf16((float)(s & 0xFF) / 255.0f);
+    o[1] = f32_to_bf16((float)((s >> 8) & 0xFF) / 255.0f);
+    o[2] = f32_to_bf16((float)((s >> 16) & 0xFF) / 255.0f);
+    o[3] = f32_to_bf16((float)(t & 0xFF) / 255.0f);
+    o[4] = f32_to_bf16((float)((t >> 8) & 0xFF) / 255.0f);
+    o[5] = f32_to_bf16((float)((t >> 16) & 0xFF) / 255.0f);
+#pragma unroll
+    for (int c = 6; c < 16; ++c) o[c] = 0;
+}
+
+// fp32 network input [H8][W8][6] of one pair from its coarsest pyramid level
+// (same pixels and padding as k_input_from_pyramids, before bf16 rounding)
+__global__ void __launch_bounds__(256)
+k_input_f32_from_pyramid(UNetPairIn P, int H8, int W8, float *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= H8 * W8) return;
+    const int y = min(i / W8, P.h - 1), x = min(i % W8, P.w - 1);
+    const uint32_t s = P.src[(size_t)(y + P.pad) * P.pitch + x + P.pad];
+    const uint32_t t = P.tgt[(size_t)(y + P.pad) * P.pitch + x + P.pad];
+    float *o = out + (size_t)i * 6;
+    o[0] = (float)(s & 0xFF) / 255.0f;
+    o[1] = (float)((s >> 8) & 0xFF) / 255.0f;
+    o[2] = (float)((s >> 16) & 0xFF) / 255.0f;
+    o[3] = (float)(t & 0xFF) / 255.0f;
+    o[4] = (float)((t >> 8) & 0xFF) / 255.0f;
+    o[5] = (float)((t >> 16) & 0xFF) / 255.0f;
+}
+
+// predicted offsets (head output, fp32 [H8][W8][16], channels 0,1) -> int32
+// seed offsets [h][w][2] of each pair, rounded half away from zero
+__global__ void __launch_bounds__(256)
+k_pred_to_seed(const float *__restrict__ pred, int H8, int W8, const UNetPairIn *__restrict__ pairs,
+               int32_t *const *__restrict__ seeds) {
+    const int n = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const UNetPairIn P = pairs[n];
+    if (i >= P.h * P.w) return;
+    const int y = i / P.w, x = i % P.w;
+    const float *q = pred + (((size_t)n * H8 + y) * W8 + x) * 16;
+    seeds[n][2 * i] = (int32_t)roundf(fminf(fmaxf(q[0], -32767.f), 32767.f));
+    seeds[n][2 * i + 1] = (int32_t)roundf(fminf(fmaxf(q[1], -32767.f), 32767.f));
+}
+
+// masked L1 loss over channels 0,1 of pred [n_px][16]; per-block partial
+// sums of (mask * |pred - target|) and mask
+__global__ void __launch_bounds__(256)
+k_loss_partial(const float *__restrict__ pred, const float *__restrict__ target, const float *__restrict__ mask,
+               long n_px, float *__restrict__ partial) {
+    __shared__ float sl[256], sm[256];
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    float l = 0.f, m = 0.f;
+    if (i < n_px) {
+        m = mask[i];
+        l = m * (fabsf(pred[i * 16] - target[2 * i]) + fabsf(pred[i * 16 + 1] - target[2 * i + 1]));
+    }
+    sl[threadIdx.x] = l;
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sl[threadIdx.x] += sl[threadIdx.x + s];
+            sm[threadIdx.x] += sm[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = sl[0];
+        partial[2 * blockIdx.x + 1] = sm[0];
+    }
+}
+
+// one block: totals in block order; totals[0] = loss / max(mask sum, 1), totals[1] = max(mask sum, 1)
+__global__ void __launch_bounds__(256)
+k_loss_total(const float *__restrict__ partial, int n_blocks, float *__restrict__ totals) {
+    __shared__ float sl[256], sm[256];
+    float l = 0.f, m = 0.f;
+    for (int b = threadIdx.x; b < n_blocks; b += 256) {
+        l += partial[2 * b];
+        m += partial[2 * b + 1];
+    }
+    sl[threadIdx.x] = l;
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sl[threadIdx.x] += sl[threadIdx.x + s];
+            sm[threadIdx.x] += sm[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float d = fmaxf(sm[0], 1.f);
+        totals[0] = sl[0] / d;
+        totals[1] = d;
+    }
+}
+
+// d loss / d pred = mask * sign(pred - target) / max(mask sum, 1), bf16 [n_px][16]
+__global__ void __launch_bounds__(256)
+k_loss_grad(const float *__restrict__ pred, const float *__restrict__ target, const float *__restrict__ mask,
+            const float *__restrict__ totals, long n_px, uint16_t *__restrict__ g) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_px * 16) return;
+    const long p = i / 16;
+    const int c = (int)(i % 16);
+    float v = 0.f;
+    if (c < 2) {
+        const float d = pred[p * 16 + c] - target[2 * p + c];
+        v = mask[p] * (float)((d > 0.f) - (d < 0.f)) / totals[1];
+    }
+    g[i] = f32_to_bf16(v);
+}
+
+// Adam on fp32 master weights of one layer (padded layout [9][cout][cin] + bias
+// [cout]); refreshes the bf16 weights [9][cout][cin] and the flipped,
+// transposed bf16 weights [9][cin][cout] used for data gradients.
+__global__ void __launch_bounds__(256)
+k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+       long n_w, long n_total, int cout, int cin, float lr, float b1, float b2, float eps, float c1, float c2,
+       uint16_t *__restrict__ w16, uint16_t *__restrict__ wt16) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_total) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = wi;
+    if (i < n_w) {
+        const uint16_t h = f32_to_bf16(wi);
+        w16[i] = h;
+        const int ci = (int)(i % cin);
+        const int co = (int)((i / cin) % cout);
+        const int tap = (int)(i / ((long)cin * cout));
+        wt16[((size_t)(8 - tap) * cin + ci) * cout + co] = h;
+    }
+}
+
+// bf16 weight copies from fp32 master weights (after loading parameters)
+__global__ void __launch_bounds__(256)
+k_weights_to_bf16(const float *__restrict__ w, long n_w, int cout, int cin, uint16_t *__restrict__ w16,
+                  uint16_t *__restrict__ wt16) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_w) return;
+    const uint16_t h = f32_to_bf16(w[i]);
+    w16[i] = h;
+    const int ci = (int)(i % cin);
+    const int co = (int)((i / cin) % cout);
+    const int tap = (int)(i / ((long)cin * cout));
+    wt16[((size_t)(8 - tap) * cin + ci) * cout + co] = h;
+}
+
+// flat parameters (PyTorch layout: weight [cout_r][cin_r][3][3], bias [cout_r])
+// <-> padded master layout ([9][cout][cin], bias [cout]); to_padded = 1: flat -> padded
+__global__ void __launch_bounds__(256)
+k_param_layout(float *__restrict__ flat, float *__restrict__ padded, int cout_r, int cin_r, int cout, int cin,
+               int to_padded) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long n_w = 9L * cout * cin;
+    if (i >= n_w + cout) return;
+    long f = -1;
+    if (i < n_w) {
+        const int ci = (int)(i % cin);
+        const int co = (int)((i / cin) % cout);
+        const int tap = (int)(i / ((long)cin * cout));
+        if (ci < cin_r && co < cout_r) f = (((long)co * cin_r + ci) * 3 + tap / 3) * 3 + tap % 3;
+    } else {
+        const int co = (int)(i - n_w);
+        if (co < cout_r) f = 9L * cout_r * cin_r + co;
+    }
+    if (to_padded) padded[i] = f >= 0 ? flat[f] : 0.f;
+    else if (f >= 0) flat[f] = padded[i];
+}
+
+__global__ void __launch_bounds__(256) k_fill_zero(float *__restrict__ p, long n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+// channels 0, 1 of the head output [n_px][16] -> offsets [n_px][2]
+__global__ void __launch_bounds__(256)
+k_pred_extract(const float *__restrict__ pred, long n_px, float *__restrict__ out) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_px * 2) return;
+    out[i] = pred[(i / 2) * 16 + (i % 2)];
+}
+
+}  // namespace
+
+static inline dim3 grid1(long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+hipError_t launch_conv3x3(const uint16_t *in, int B, int H, int W, int cin, const uint16_t *wt,
+                          const float *bias, void *out, int cout, bool relu, bool out_f32, hipStream_t s) {
+    const int tiles = (W + 63) / 64 * H * B;
+    const int nb = cout >= 64 ? 4 : cout / 16;
+    dim3 grid(tiles, (cout + 16 * nb - 1) / (16 * nb));
+#define FB_CONV(NB)                                                                                        \
+    if (out_f32) hipLaunchKernelGGL((k_conv3x3<NB, false, true>), grid, dim3(256), 0, s, in, B, H, W, cin, wt, bias, out, cout); \
+    else if (relu) hipLaunchKernelGGL((k_conv3x3<NB, true, false>), grid, dim3(256), 0, s, in, B, H, W, cin, wt, bias, out, cout); \
+    else hipLaunchKernelGGL((k_conv3x3<NB, false, false>), grid, dim3(256), 0, s, in, B, H, W, cin, wt, bias, out, cout);
+    switch (nb) {
+    case 1: FB_CONV(1) break;
+    case 2: FB_CONV(2) break;
+    case 3: FB_CONV(3) break;
+    default: FB_CONV(4) break;
+    }
+#undef FB_CONV
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_wgrad(const uint16_t *in, const uint16_t *g, int B, int H, int W, int cin, int cout,
+                             int chunk_px, float *partial, float *bias_partial, hipStream_t s) {
+    const long total = (long)B * H * W;
+    const int n_chunks = (int)((total + chunk_px - 1) / chunk_px);
+    hipLaunchKernelGGL(k_conv_wgrad, dim3(n_chunks, 9, (cout / 16) * (cin / 16)), dim3(64), 0, s, in, g, B, H,
+                       W, cin, cout, chunk_px, partial);
+    hipLaunchKernelGGL(k_bias_grad, dim3(n_chunks), dim3(256), 0, s, g, total, cout, chunk_px, bias_partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_chunks(const float *partial, int n_chunks, long n, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_chunks, grid1(n), dim3(256), 0, s, partial, n_chunks, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pool2(const uint16_t *in, int B, int H, int W, int C, uint16_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_pool2, grid1((long)B * (H / 2) * (W / 2) * C), dim3(256), 0, s, in, B, H, W, C, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pool2_bwd_add(const uint16_t *gout, int B, int H, int W, int C, uint16_t *gin, hipStream_t s) {
+    hipLaunchKernelGGL(k_pool2_bwd_add, grid1((long)B * H * W * C), dim3(256), 0, s, gout, B, H, W, C, gin);
+    return hipGetLastError();
+}
+
+hipError_t launch_upcat(const uint16_t *deep, const uint16_t *skip, int B, int H, int W, int C1, int C2,
+                        uint16_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_upcat, grid1((long)B * H * W * (C1 + C2)), dim3(256), 0, s, deep, skip, B, H, W, C1, C2, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_upcat_bwd(const uint16_t *gcat, int B, int H, int W, int C1, int C2, uint16_t *gdeep,
+                            uint16_t *gskip, hipStream_t s) {
+    const long n = (long)B * (H / 2) * (W / 2) * C1 + (long)B * H * W * C2;
+    hipLaunchKernelGGL(k_upcat_bwd, grid1(n), dim3(256), 0, s, gcat, B, H, W, C1, C2, gdeep, gskip);
+    return hipGetLastError();
+}
+
+hipError_t launch_relu_mask(uint16_t *g, const uint16_t *y, long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_relu_mask, grid1(n), dim3(256), 0, s, g, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_input_from_f32(const float *x6, long n_px, uint16_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_input_from_f32, grid1(n_px * 16), dim3(256), 0, s, x6, n_px, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_input_from_pyramids(const UNetPairIn *pairs, int n, int H8, int W8, uint16_t *out,
+                                      hipStream_t s) {
+    hipLaunchKernelGGL(k_input_from_pyramids, dim3((H8 * W8 + 255) / 256, n), dim3(256), 0, s, pairs, H8, W8, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_input_f32_from_pyramid(const UNetPairIn &pair, int H8, int W8, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_input_f32_from_pyramid, dim3((H8 * W8 + 255) / 256), dim3(256), 0, s, pair, H8, W8, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pred_to_seed(const float *pred, int H8, int W8, const UNetPairIn *pairs, int32_t *const *seeds,
+                               int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_pred_to_seed, dim3((H8 * W8 + 255) / 256, n), dim3(256), 0, s, pred, H8, W8, pairs, seeds);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss(const float *pred, const float *target, const float *mask, long n_px, float *partial,
+                       float *totals, uint16_t *grad, hipStream_t s) {
+    const int nb = (int)((n_px + 255) / 256);
+    hipLaunchKernelGGL(k_loss_partial, dim3(nb), dim3(256), 0, s, pred, target, mask, n_px, partial);
+    hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(256), 0, s, partial, nb, totals);
+    if (grad) hipLaunchKernelGGL(k_loss_grad, grid1(n_px * 16), dim3(256), 0, s, pred, target, mask, totals, n_px, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, long n_w, long n_total, int cout, int cin,
+                       float lr, float b1, float b2, float eps, float c1, float c2, uint16_t *w16, uint16_t *wt16,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, grid1(n_total), dim3(256), 0, s, w, g, m, v, n_w, n_total, cout, cin, lr, b1, b2,
+                       eps, c1, c2, w16, wt16);
+    return hipGetLastError();
+}
+
+hipError_t launch_weights_to_bf16(const float *w, long n_w, int cout, int cin, uint16_t *w16, uint16_t *wt16,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(k_weights_to_bf16, grid1(n_w), dim3(256), 0, s, w, n_w, cout, cin, w16, wt16);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(float *p, long n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_zero, grid1(n), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pred_extract(const float *pred, long n_px, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_pred_extract, grid1(n_px * 2), dim3(256), 0, s, pred, n_px, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_param_layout(float *flat, float *padded, int cout_r, int cin_r, int cout, int cin, bool to_padded,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_param_layout, grid1(9L * cout * cin + cout), dim3(256), 0, s, flat, padded, cout_r, cin_r,
+                       cout, cin, to_padded ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace fb

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libfastblend.so")
 FB_OK = 0
 FB_USE_GRAPH = 0x1
 FB_NO_AUTOTUNE = 0x2
+FB_LEARNED_SEED = 0x4
 STATUS = {0: "FB_OK", -1: "FB_E_INVALID", -2: "FB_E_SHAPE", -3: "FB_E_UNSUPPORTED",
           -4: "FB_E_ALLOC", -5: "FB_E_HIP"}
 
@@ -44,7 +45,7 @@ class fb_pair_desc(ctypes.Structure):
                 ("nnf", ctypes.c_void_p), ("energy", ctypes.c_void_p)]
 
 
-KERNEL_KINDS = ["pyramid", "pm_start", "pm_iter", "pm_export", "remap", "other"]
+KERNEL_KINDS = ["pyramid", "pm_start", "pm_iter", "pm_export", "remap", "other", "unet"]
 
 
 class fb_profile(ctypes.Structure):
@@ -55,7 +56,8 @@ _lib = None
 _EXPORTS = ["fb_create", "fb_destroy", "fb_last_error", "fb_num_tile_configs", "fb_set_tile_config",
             "fb_pyramid_bytes", "fb_build_pyramid", "fb_nnf_init", "fb_patchmatch_level", "fb_remap",
             "fb_blend_window", "fb_interpolate", "fb_patchmatch_batch", "fb_profile_enable",
-            "fb_profile_read"]
+            "fb_profile_read", "fb_unet_param_count", "fb_unet_forward_flops", "fb_unet_load", "fb_unet_save",
+            "fb_unet_forward", "fb_unet_gradients", "fb_unet_train_step", "fb_unet_pair_input"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -84,6 +86,14 @@ def load_library(path: str = LIB_PATH):
         "fb_patchmatch_batch": (i32, [vp, ctypes.POINTER(fb_pair_desc), i32, P, vp]),
         "fb_profile_enable": (i32, [vp, i32]),
         "fb_profile_read": (i32, [vp, ctypes.POINTER(fb_profile), i32]),
+        "fb_unet_param_count": (ctypes.c_int64, []),
+        "fb_unet_forward_flops": (ctypes.c_double, [i32, i32, i32]),
+        "fb_unet_load": (i32, [vp, vp, vp]),
+        "fb_unet_save": (i32, [vp, vp, vp]),
+        "fb_unet_forward": (i32, [vp, vp, i32, i32, i32, vp, vp]),
+        "fb_unet_gradients": (i32, [vp, vp, vp, vp, i32, i32, i32, vp, vp, vp]),
+        "fb_unet_train_step": (i32, [vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp]),
+        "fb_unet_pair_input": (i32, [vp, vp, vp, i32, i32, i32, i32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -158,6 +168,61 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+    # ---- learned proposal network -----------------------------------------
+    def fb_unet_load(self, params: torch.Tensor):
+        n = load_library().fb_unet_param_count()
+        _check(load_library().fb_unet_load(self.handle, _dev(params, "params", torch.float32, (n,)),
+                                           _stream(params)), "fb_unet_load")
+
+    def fb_unet_save(self) -> torch.Tensor:
+        n = load_library().fb_unet_param_count()
+        out = torch.empty(n, dtype=torch.float32, device=self.device)
+        _check(load_library().fb_unet_save(self.handle, _dev(out, "params"), _stream(out)), "fb_unet_save")
+        return out
+
+    def fb_unet_forward(self, pair6: torch.Tensor) -> torch.Tensor:
+        B, h, w = pair6.shape[:3]
+        out = torch.empty((B, h, w, 2), dtype=torch.float32, device=pair6.device)
+        _check(load_library().fb_unet_forward(self.handle, _dev(pair6, "pair6", torch.float32, (B, h, w, 6)),
+                                              B, h, w, _dev(out, "offsets"), _stream(pair6)), "fb_unet_forward")
+        return out
+
+    def fb_unet_gradients(self, pair6, target, mask):
+        """(flat fp32 gradients, loss) of the masked L1 loss, parameters unchanged."""
+        B, h, w = pair6.shape[:3]
+        n = load_library().fb_unet_param_count()
+        grads = torch.empty(n, dtype=torch.float32, device=pair6.device)
+        loss = torch.empty(1, dtype=torch.float32, device=pair6.device)
+        _check(load_library().fb_unet_gradients(
+            self.handle, _dev(pair6, "pair6", torch.float32, (B, h, w, 6)),
+            _dev(target, "target", torch.float32, (B, h, w, 2)), _dev(mask, "mask", torch.float32, (B, h, w)),
+            B, h, w, _dev(grads, "grads"), _dev(loss, "loss"), _stream(pair6)), "fb_unet_gradients")
+        return grads, loss
+
+    def fb_unet_pair_input(self, src_pyr, tgt_pyr, h: int, w: int, levels: int, patch_radius: int = 2,
+                           out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        hc, wc = level_size(h, w, levels - 1)
+        H8, W8 = -(-hc // 8) * 8, -(-wc // 8) * 8
+        _check_pyr(src_pyr, "src_pyr", h, w, levels, patch_radius)
+        _check_pyr(tgt_pyr, "tgt_pyr", h, w, levels, patch_radius)
+        if out is None:
+            out = torch.empty((H8, W8, 6), dtype=torch.float32, device=src_pyr.device)
+        _check(load_library().fb_unet_pair_input(
+            self.handle, _dev(src_pyr, "src_pyr", torch.uint8), _dev(tgt_pyr, "tgt_pyr", torch.uint8), h, w,
+            levels, patch_radius, _dev(out, "pair6", torch.float32, (H8, W8, 6)), _stream(src_pyr)),
+            "fb_unet_pair_input")
+        return out
+
+    def fb_unet_train_step(self, pair6, target, mask, lr: float) -> torch.Tensor:
+        """One Adam step; returns the loss before the update (device scalar)."""
+        B, h, w = pair6.shape[:3]
+        loss = torch.empty(1, dtype=torch.float32, device=pair6.device)
+        _check(load_library().fb_unet_train_step(
+            self.handle, _dev(pair6, "pair6", torch.float32, (B, h, w, 6)),
+            _dev(target, "target", torch.float32, (B, h, w, 2)), _dev(mask, "mask", torch.float32, (B, h, w)),
+            B, h, w, lr, _dev(loss, "loss"), _stream(pair6)), "fb_unet_train_step")
+        return loss
 
     # ---- measurement ----------------------------------------------------
     def fb_profile_enable(self, on: bool = True):

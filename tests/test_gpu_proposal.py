@@ -1,0 +1,127 @@
+"""GPU tests of the learned proposal network (hand-written bf16 matrix-core
+kernels) against its CPU oracle, and of PatchMatch seeded by it."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import proposal_net as net
+from paper_2311_09265_amd import fastblend as fbm
+from paper_2311_09265_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = fbm.Context(0)
+    yield c
+    c.close()
+
+
+def _batch(B, h, w, seed):
+    g = torch.Generator().manual_seed(seed)
+    x = torch.rand(B, h, w, 6, generator=g)
+    t = (torch.rand(B, h, w, 2, generator=g) - 0.5) * 6
+    m = (torch.rand(B, h, w, generator=g) > 0.25).float()
+    return x, t, m
+
+
+def rel(a, b):
+    a, b = a.double().cpu(), b.double().cpu()
+    return float((a - b).norm() / max(float(b.norm()), 1e-30))
+
+
+def test_param_count(ctx):
+    assert fbm.load_library().fb_unet_param_count() == net.param_count()
+
+
+def test_forward_matches_oracle(ctx):
+    flat = net.init_params(11)
+    ctx.fb_unet_load(flat.cuda())
+    for B, h, w in ((2, 16, 24), (1, 40, 32)):
+        x, _, _ = _batch(B, h, w, B * h)
+        got = ctx.fb_unet_forward(x.cuda())
+        ref, _ = net.forward(flat, x, emulate_bf16=True)
+        assert rel(got, ref) < 1e-2, (B, h, w, rel(got, ref))
+
+
+def test_save_load_round_trip(ctx):
+    flat = net.init_params(12)
+    ctx.fb_unet_load(flat.cuda())
+    back = ctx.fb_unet_save().cpu()
+    assert torch.equal(back, flat)
+
+
+def test_gradients_match_oracle(ctx):
+    flat = net.init_params(13)
+    ctx.fb_unet_load(flat.cuda())
+    x, t, m = _batch(2, 16, 16, 5)
+    grads, loss = ctx.fb_unet_gradients(x.cuda(), t.cuda(), m.cuda())
+    ref_loss, ref = net.loss_and_grads(flat, x, t, m, emulate_bf16=True)
+    assert abs(float(loss.cpu()) - float(ref_loss)) <= 1e-3 * float(ref_loss)
+    g = grads.cpu()
+    for i, (a, b) in enumerate(net.layer_slices()):
+        r = rel(g[a:b], ref[a:b])
+        assert r < 2e-2, (i, r)
+    # parameters are unchanged by a gradient evaluation
+    assert torch.equal(ctx.fb_unet_save().cpu(), flat)
+
+
+def test_training_reduces_loss(ctx):
+    flat = net.init_params(14)
+    ctx.fb_unet_load(flat.cuda())
+    x, t, m = _batch(4, 32, 32, 9)
+    t = t * 0 + torch.tensor([1.5, -2.0])       # a constant offset field is learnable quickly
+    x, t, m = x.cuda(), t.cuda(), m.cuda()
+    losses = [float(ctx.fb_unet_train_step(x, t, m, 2e-3).cpu()) for _ in range(60)]
+    assert losses[-1] < 0.25 * losses[0], losses[::10]
+
+
+def _round_half_away(a):
+    return np.sign(a) * np.floor(np.abs(a) + 0.5)
+
+
+def test_learned_seed_patchmatch(ctx):
+    """PatchMatch seeded by the network: (a) the oracle's seed field drives
+    bit-exact GPU/oracle NNFs through the offset-seed path; (b) the GPU
+    network's rounded offsets agree with the oracle network's almost
+    everywhere; (c) FB_LEARNED_SEED equals seeding with the GPU network's
+    offsets explicitly."""
+    flat = net.init_params(15) * 0.3
+    ctx.fb_unet_load(flat.cuda())
+    N, h, w, K, iters, seed = 3, 64, 96, 3, 2, 77
+    guides = synth.sprite_video(N, h, w, 21, n_sprites=2, side=(10, 24))
+    pairs = [(0, 1), (2, 1)]
+    hc, wc = -(-h // 4), -(-w // 4)
+    pyr = [oracle.pyramid(guides[f], K)[K - 1] for f in range(N)]
+    x6 = torch.stack([torch.from_numpy(np.concatenate([pyr[j], pyr[i]], -1).astype(np.float32) / 255.0)
+                      for j, i in pairs])
+    ref_off, _ = net.forward(flat, x6, emulate_bf16=True)
+    ref_seed = np.clip(_round_half_away(ref_off.numpy()), -32767, 32767).astype(np.int32)
+    gpu_off = ctx.fb_unet_forward(x6.cuda()).cpu().numpy()
+    gpu_seed = np.clip(_round_half_away(gpu_off), -32767, 32767).astype(np.int32)
+    assert (gpu_seed == ref_seed).all(axis=-1).mean() > 0.99
+    prm = fbm.make_params(2, K, iters, seed)
+    g = torch.from_numpy(guides).cuda()
+    pyrs = [ctx.fb_build_pyramid(g[f], K) for f in range(N)]
+
+    def descs(seeds):
+        return [dict(src_pyr=pyrs[j], tgt_pyr=pyrs[i], h=h, w=w, levels=K, pair_id=j * N + i,
+                     **({"seed_offsets": torch.from_numpy(np.ascontiguousarray(seeds[k])).cuda()}
+                        if seeds is not None else {}))
+                for k, (j, i) in enumerate(pairs)]
+
+    # (a) oracle seeds through the explicit offset path: bit-exact with the oracle
+    outs = ctx.fb_patchmatch_batch(descs(ref_seed), prm)
+    for k, (j, i) in enumerate(pairs):
+        F, E = oracle.patchmatch(guides[j], guides[i], 2, K, iters, seed, j * N + i, seed_offsets=ref_seed[k])
+        assert np.array_equal(outs[k][0].cpu().numpy(), F)
+        assert np.array_equal(outs[k][1].cpu().numpy().astype(np.uint32), E)
+    # (c) the learned-seed flag equals explicit seeding with the GPU network's offsets
+    lprm = fbm.make_params(2, K, iters, seed, fbm.FB_LEARNED_SEED)
+    learned = ctx.fb_patchmatch_batch(descs(None), lprm)
+    explicit = ctx.fb_patchmatch_batch(descs(gpu_seed), prm)
+    for (a, ea), (b, eb) in zip(learned, explicit):
+        assert torch.equal(a, b) and torch.equal(ea, eb)
