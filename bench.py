@@ -78,6 +78,72 @@ def cpu_baseline(guides, pairs, p, levels, iters, seed, N, budget_s):
                       "(C oracle, OpenMP over rows), %.1f s" % (done, len(pairs), levels, iters, h, w, dt)}
 
 
+def bench_learned(ctx, fbm, g, s, out, M, p, levels, seed, wpath, args, pairs, N, h, w, plain_energy):
+    """The same blend with every pair's coarsest level seeded by the proposal
+    network (FB_LEARNED_SEED) and args.learned_iters iterations per level."""
+    import numpy as np
+    import torch
+    from paper_2311_09265_amd import proposal
+    params, meta = proposal.load(wpath)
+    ctx.fb_unet_load(torch.from_numpy(params).cuda())
+    lprm = fbm.make_params(p, levels, args.learned_iters, seed, fbm.FB_LEARNED_SEED)
+    for _ in range(max(args.warmup, 1)):
+        ctx.fb_blend_window(g, s, M, lprm, out=out)
+    torch.cuda.synchronize()
+    ctx.fb_profile_enable(True)
+    ctx.fb_profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.fb_blend_window(g, s, M, lprm, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    prof = ctx.fb_profile_read(reset=True)
+    ctx.fb_profile_enable(False)
+    log("learned: %.2f ms/step" % ms)
+    energy = None
+    if not args.no_energy:
+        pyrs = [ctx.fb_build_pyramid(g[f], levels, p) for f in range(N)]
+        descs = [dict(src_pyr=pyrs[j], tgt_pyr=pyrs[i], h=h, w=w, levels=levels, pair_id=j * N + i)
+                 for (j, i) in pairs]
+        energies = [e for _, e in ctx.fb_patchmatch_batch(descs, lprm)]
+        energy = round(float(torch.stack(energies).double().mean().item()), 2)
+        del energies, pyrs
+    hc, wc = -(-h // (1 << (levels - 1))), -(-w // (1 << (levels - 1)))
+    flops = fbm.load_library().fb_unet_forward_flops(len(pairs), -(-hc // 8) * 8, -(-wc // 8) * 8)
+    unet_ms = prof["unet"][1] / args.steps
+    pix, _ = pm_work(len(pairs), h, w, levels, args.learned_iters, p)
+    tf = flops / (unet_ms / 1e3) / 1e12 if unet_ms > 0 else 0.0
+    margin = 0.0
+    accepted = (energy is not None and plain_energy is not None and energy <= plain_energy * (1 + margin))
+    return {"ms_per_step": round(ms, 3), "blended_frames_per_s": round(N / (ms / 1e3), 3),
+            "iters_per_level": args.learned_iters, "pixel_iterations_per_step": pix,
+            "mean_level0_patch_energy": energy, "plain_mean_level0_patch_energy": plain_energy,
+            "energy_margin": margin, "accepted": accepted,
+            "speedup_vs_plain": None,
+            "kernel_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in prof.items() if v[0]},
+            "network_roofline": {"bound": "mfma", "kernel": "k_conv3x3 (forward)", "achieved": round(tf, 3),
+                                 "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tf / 2500.0, 5),
+                                 "flops_per_step": flops},
+            "weights": os.path.relpath(wpath, ROOT), "training": {k: meta.get(k) for k in
+                                                                   ("pairs", "steps", "val_loss", "train_seconds")}}
+
+
+def iter_kernel_traffic():
+    """HBM bytes per launch of the PatchMatch iteration kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    import hashlib
+    summ = os.path.join(ROOT, "profiles", "pm_iter_counters_blend512.json")
+    src = os.path.join(ROOT, "paper_2311_09265_amd", "csrc", "patchmatch.hip")
+    if not os.path.exists(summ):
+        return None, "no counter summary"
+    with open(summ) as f:
+        d = json.load(f)
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if d.get("kernel_source_sha256") != sha:
+        return None, "counters were taken on another version of the kernel"
+    return d["hbm_bytes_per_launch"], d
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +155,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     ap.add_argument("--no-energy", action="store_true", help="skip the mean-energy pass")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2311_09265_amd", "weights", "proposal_unet.npz"),
+                    help="trained proposal network; the learned comparison is skipped if absent")
+    ap.add_argument("--learned-iters", type=int, default=2)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (counter calibration)")
     args = ap.parse_args()
@@ -160,8 +229,14 @@ def main():
         mean_energy = round(float(torch.stack(energies).double().mean().item()), 2)
         del energies, pyrs
 
+    learned = None
+    wpath = args.weights
+    if wpath and os.path.exists(wpath):
+        learned = bench_learned(ctx, fbm, g, s, out, M, p, levels, seed, wpath, args, pairs, N, h, w, mean_energy)
+
     n_iter, iter_ms = prof["pm_iter"]
     iter_ms_step = iter_ms / args.steps
+    traffic, traffic_info = iter_kernel_traffic()
     achieved = terms / (iter_ms_step / 1e3) / 1e12
     kernel_ms = {k: round(v[1] / args.steps, 3) for k, v in prof.items() if v[0]}
 
@@ -200,11 +275,18 @@ def main():
         "kernel_ms_per_step": kernel_ms,
         "roofline": {"bound": "alu", "kernel": "k_pm_iter",
                      "achieved": round(achieved, 3), "peak": round(DOT4_PEAK_TOPS, 1), "unit": "TOP/s",
-                     "frac": round(achieved / DOT4_PEAK_TOPS, 4), "traffic": None,
+                     "frac": round(achieved / DOT4_PEAK_TOPS, 4), "traffic": traffic,
+                     "traffic_note": ("HBM bytes per launch, rocprofv3 FETCH_SIZE x %.2f + WRITE_SIZE x %.2f "
+                                      "(copy-calibrated), %s" % (traffic_info["fetch_scale"], traffic_info["write_scale"],
+                                                                 traffic_info["summary"])
+                                      if traffic is not None else traffic_info),
                      "work": "byte-terms of Eq. 1 (one per squared channel difference) per step: %d" % terms,
                      "avg_launch_ms": round(iter_ms / max(n_iter, 1), 4), "launches": n_iter},
         "cpu_baseline": cpu,
+        "learned": learned,
     }
+    if learned:
+        learned["speedup_vs_plain"] = round(ms / learned["ms_per_step"], 3)
     print(json.dumps(res), flush=True)
     ctx.close()
 

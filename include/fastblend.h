@@ -210,8 +210,9 @@ fb_status fb_profile_read(fb_ctx *ctx, fb_profile *out, int32_t reset);
 /* Learned proposal (a project addition; the paper's method is model-free, */
 /* Section 3.1).  A 4-level U-Net with (32, 48, 96, 192) channels maps a   */
 /* frame pair at the coarsest pyramid level (6 channels: source RGB,       */
-/* target RGB, in [0, 1]) to a 2-channel offset field (row, col, pixels of */
-/* that level).  bf16 weights and activations, fp32 accumulation on the    */
+/* target RGB, in [0, 1], centred to 2x - 1 inside the network) to a       */
+/* 2-channel offset field (row, col, in pixels of that level).  bf16       */
+/* weights and activations, fp32 accumulation on the                       */
 /* matrix cores.  With FB_LEARNED_SEED in fb_params.flags, the blend,      */
 /* interpolation and batch calls seed every pair's coarsest level with the */
 /* rounded prediction (F = clamp(v + offset)) instead of the random draw;  */

@@ -4,7 +4,8 @@ The network is a project addition (the paper's method is model-free,
 Section 3.1), so it has no passage to follow; this file is its plain
 definition, in PyTorch CPU fp64, written independently of the GPU kernels:
 
-  input   6 channels (source RGB, target RGB) in [0, 1], NHWC [B][h][w][6]
+  input   6 channels (source RGB, target RGB) in [0, 1], NHWC [B][h][w][6],
+          centred to 2x - 1 by the network
   enc     (32, 48, 96, 192) channels, two 3x3 conv (padding 1) + ReLU per
           level, 2x2 average pooling between levels
   dec     nearest 2x upsampling, concatenation [upsampled, skip], two 3x3
@@ -79,7 +80,7 @@ def forward(flat, pair6, emulate_bf16: bool = True):
     """Returns (pred NHWC [B][h][w][2] fp64, cache for backward)."""
     e = emulate_bf16
     P = unflatten(flat)
-    x = rb(pair6.to(torch.float64).permute(0, 3, 1, 2), e)
+    x = rb(2.0 * pair6.to(torch.float64).permute(0, 3, 1, 2) - 1.0, e)
     acts = {"x0": x}
 
     def conv(i, inp):

@@ -46,59 +46,83 @@ __device__ __forceinline__ bf16x4 load_bf16x4(const uint16_t *p) {
 }
 
 // ---------------------------------------------------------------------------
-// Forward / data-gradient convolution.  Workgroup: 4 waves = 64 consecutive
-// pixels of one image row; wave w owns pixels [16w, 16w+16) and NB blocks of
-// 16 output channels starting at blockIdx.y * 16 NB.
+// Forward / data-gradient convolution.  The B*H*W output pixels form one flat
+// list; a workgroup (4 waves) takes 256 consecutive pixels, each wave 64 of
+// them as 4 row blocks of 16 (M), times NB blocks of 16 output channels
+// starting at blockIdx.y * 16 NB (N).  Every 16-channel slice of one tap
+// (K) costs each wave 4 + NB fragment loads of 8 bytes per lane for 4 NB
+// matrix-core instructions.
 // ---------------------------------------------------------------------------
 template <int NB, bool RELU, bool OUT_F32>
 __global__ void __launch_bounds__(256)
 k_conv3x3(const uint16_t *__restrict__ in, int B, int H, int W, int cin,
           const uint16_t *__restrict__ wt, const float *__restrict__ bias, void *__restrict__ out,
           int cout) {
+    constexpr int MB = 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tiles_x = (W + 63) / 64;
-    int t = blockIdx.x;
-    const int tx = t % tiles_x;
-    t /= tiles_x;
-    const int y = t % H;
-    const int n = t / H;
+    const long total = (long)B * H * W;
+    const long p_wave = (long)blockIdx.x * 256 + wave * 64;
     const int co0 = blockIdx.y * 16 * NB;
-    const int px = tx * 64 + wave * 16 + (lane & 15);   // pixel of the A row this lane loads
-    const int kq = 4 * (lane >> 4);                       // channel quad within a 16-chunk
-    f32x4 acc[NB];
+    const int kq = 4 * (lane >> 4);
+    // the pixel whose A row this lane loads, per row block
+    int py[MB], px[MB];
+    long pn[MB];
+    bool pv[MB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int mb = 0; mb < MB; ++mb) {
+        const long p = p_wave + mb * 16 + (lane & 15);
+        pv[mb] = p < total;
+        const long q = pv[mb] ? p : 0;
+        px[mb] = (int)(q % W);
+        py[mb] = (int)((q / W) % H);
+        pn[mb] = q / ((long)W * H);
+    }
+    f32x4 acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[mb][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int tap = 0; tap < 9; ++tap) {
-        const int yy = y + tap / 3 - 1, xx = px + tap % 3 - 1;
-        const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < W && px < W;
-        const uint16_t *arow = in + (((size_t)n * H + (ok ? yy : 0)) * W + (ok ? xx : 0)) * cin + kq;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const uint16_t *arow[MB];
+        bool ok[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) {
+            const int yy = py[mb] + dy, xx = px[mb] + dx;
+            ok[mb] = pv[mb] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            arow[mb] = in + ((pn[mb] * H + (ok[mb] ? yy : 0)) * W + (ok[mb] ? xx : 0)) * cin + kq;
+        }
         const uint16_t *wrow = wt + ((size_t)tap * cout + co0 + (lane & 15)) * cin + kq;
         for (int c0 = 0; c0 < cin; c0 += 16) {
-            bf16x4 a = ok ? load_bf16x4(arow + c0) : bf16x4{0, 0, 0, 0};
+            bf16x4 a[MB];
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) a[mb] = ok[mb] ? load_bf16x4(arow[mb] + c0) : bf16x4{0, 0, 0, 0};
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                if (co0 + 16 * b >= cout) break;
                 const bf16x4 bw = load_bf16x4(wrow + (size_t)16 * b * cin + c0);
-                acc[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc[b], 0, 0, 0);
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+                    acc[mb][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mb], bw, acc[mb][b], 0, 0, 0);
             }
         }
     }
-    // epilogue: lane holds D[4 (lane/16) + j][lane % 16] -> pixels rows, channel column
+    // epilogue: lane holds D[4 (lane/16) + j][lane % 16]: pixel row, channel column
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int co = co0 + 16 * b + (lane & 15);
-        if (co0 + 16 * b >= cout) break;
         const float bv = bias ? bias[co] : 0.f;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int p = tx * 64 + wave * 16 + 4 * (lane >> 4) + j;
-            if (p >= W) continue;
-            float v = acc[b][j] + bv;
-            if (RELU) v = fmaxf(v, 0.f);
-            const size_t o = (((size_t)n * H + y) * W + p) * cout + co;
-            if (OUT_F32) reinterpret_cast<float *>(out)[o] = v;
-            else reinterpret_cast<uint16_t *>(out)[o] = f32_to_bf16(v);
-        }
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const long p = p_wave + mb * 16 + 4 * (lane >> 4) + j;
+                if (p >= total) continue;
+                float v = acc[mb][b][j] + bv;
+                if (RELU) v = fmaxf(v, 0.f);
+                const size_t o = (size_t)p * cout + co;
+                if (OUT_F32) reinterpret_cast<float *>(out)[o] = v;
+                else reinterpret_cast<uint16_t *>(out)[o] = f32_to_bf16(v);
+            }
     }
 }
 
@@ -250,13 +274,13 @@ k_relu_mask(uint16_t *__restrict__ g, const uint16_t *__restrict__ y, long n) {
     if (!(bf16_to_f32(y[i]) > 0.f)) g[i] = 0;
 }
 
-// fp32 [n_px][6] in [0,1] -> bf16 [n_px][16] (channels 6..15 zero)
+// fp32 [n_px][6] in [0,1] -> bf16 [n_px][16]: 2x - 1 (centred), channels 6..15 zero
 __global__ void __launch_bounds__(256)
 k_input_from_f32(const float *__restrict__ x6, long n_px, uint16_t *__restrict__ out) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_px * 16) return;
     const int c = (int)(i % 16);
-    out[i] = c < 6 ? f32_to_bf16(x6[(i / 16) * 6 + c]) : (uint16_t)0;
+    out[i] = c < 6 ? f32_to_bf16(2.0f * x6[(i / 16) * 6 + c] - 1.0f) : (uint16_t)0;
 }
 
 // network input from the coarsest pyramid level of every pair: channels
@@ -272,13 +296,14 @@ k_input_from_pyramids(const UNetPairIn *__restrict__ pairs, int H8, int W8, uint
     const uint32_t s = P.src[(size_t)(y + P.pad) * P.pitch + x + P.pad];
     const uint32_t t = P.tgt[(size_t)(y + P.pad) * P.pitch + x + P.pad];
     uint16_t *o = out + ((size_t)n * H8 * W8 + i) * 16;
-    // pixel / 255 as a correctly rounded fp32 division, then bf16
-    o[0] = f32_to_bf16((float)(s & 0xFF) / 255.0f);
-    o[1] = f32_to_bf16((float)((s >> 8) & 0xFF) / 255.0f);
-    o[2] = f32_to_bf16((float)((s >> 16) & 0xFF) / 255.0f);
-    o[3] = f32_to_bf16((float)(t & 0xFF) / 255.0f);
-    o[4] = f32_to_bf16((float)((t >> 8) & 0xFF) / 255.0f);
-    o[5] = f32_to_bf16((float)((t >> 16) & 0xFF) / 255.0f);
+    // x = pixel / 255 (a correctly rounded fp32 division), centred to 2x - 1,
+    // then bf16: the same steps as k_input_from_f32 on that x
+    o[0] = f32_to_bf16(2.0f * ((float)(s & 0xFF) / 255.0f) - 1.0f);
+    o[1] = f32_to_bf16(2.0f * ((float)((s >> 8) & 0xFF) / 255.0f) - 1.0f);
+    o[2] = f32_to_bf16(2.0f * ((float)((s >> 16) & 0xFF) / 255.0f) - 1.0f);
+    o[3] = f32_to_bf16(2.0f * ((float)(t & 0xFF) / 255.0f) - 1.0f);
+    o[4] = f32_to_bf16(2.0f * ((float)((t >> 8) & 0xFF) / 255.0f) - 1.0f);
+    o[5] = f32_to_bf16(2.0f * ((float)((t >> 16) & 0xFF) / 255.0f) - 1.0f);
 #pragma unroll
     for (int c = 6; c < 16; ++c) o[c] = 0;
 }
@@ -467,9 +492,11 @@ static inline dim3 grid1(long n) { return dim3((unsigned)((n + 255) / 256)); }
 
 hipError_t launch_conv3x3(const uint16_t *in, int B, int H, int W, int cin, const uint16_t *wt,
                           const float *bias, void *out, int cout, bool relu, bool out_f32, hipStream_t s) {
-    const int tiles = (W + 63) / 64 * H * B;
-    const int nb = cout >= 64 ? 4 : cout / 16;
-    dim3 grid(tiles, (cout + 16 * nb - 1) / (16 * nb));
+    const long total = (long)B * H * W;
+    // NB divides cout / 16 so every channel block of a launch is full
+    const int blocks = cout / 16;
+    const int nb = blocks % 4 == 0 ? 4 : (blocks % 3 == 0 ? 3 : (blocks % 2 == 0 ? 2 : 1));
+    dim3 grid((unsigned)((total + 255) / 256), blocks / nb);
 #define FB_CONV(NB)                                                                                        \
     if (out_f32) hipLaunchKernelGGL((k_conv3x3<NB, false, true>), grid, dim3(256), 0, s, in, B, H, W, cin, wt, bias, out, cout); \
     else if (relu) hipLaunchKernelGGL((k_conv3x3<NB, true, false>), grid, dim3(256), 0, s, in, B, H, W, cin, wt, bias, out, cout); \

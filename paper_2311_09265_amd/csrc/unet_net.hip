@@ -3,11 +3,12 @@
 //
 // Architecture (a project addition, not from the paper): a 4-level U-Net on
 // the coarsest PatchMatch level of a frame pair.  Input: 6 channels (source
-// RGB, target RGB, / 255).  Encoder levels of (32, 48, 96, 192) channels, two
-// 3x3 conv + ReLU per level, 2x2 average pooling between levels; decoder:
-// nearest 2x upsampling, concatenation with the encoder skip, two 3x3 conv +
-// ReLU; head: 3x3 conv to 2 channels = predicted (row, col) offset of the
-// match, in pixels of that level.  1,116,226 parameters.
+// RGB, target RGB, / 255), centred to 2x - 1.  Encoder levels of (32, 48,
+// 96, 192) channels, two 3x3 conv + ReLU per level, 2x2 average pooling
+// between levels; decoder: nearest 2x upsampling, concatenation with the
+// encoder skip, two 3x3 conv + ReLU; head: 3x3 conv to 2 channels = predicted
+// (row, col) offset of the match, in pixels of that level.  1,116,226
+// parameters.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -124,25 +124,22 @@ def prepare(ctx, pairs, chunk: int = 64):
 
 
 # ------------------------------------------------------------- training ----
-def train(ctx, x, t, m, epochs: int = 15, batch: int = 32, lr: float = 1e-3, seed: int = 0):
+def train(ctx, x, t, m, steps: int = 6000, batch: int = 32, lr: float = 1e-3, seed: int = 0, log_every: int = 500):
+    """Adam on random minibatches, cosine-decayed learning rate; returns the
+    mean training loss of every log_every steps."""
     import torch
     g = torch.Generator().manual_seed(seed)
     n = x.shape[0]
-    hist = []
-    steps = epochs * (n // batch)
-    step = 0
-    for ep in range(epochs):
-        perm = torch.randperm(n, generator=g).to(x.device)
-        losses = []
-        for b0 in range(0, n - batch + 1, batch):
-            idx = perm[b0:b0 + batch]
-            cur_lr = lr * 0.5 * (1 + np.cos(np.pi * step / steps))    # cosine decay
-            losses.append(ctx.fb_unet_train_step(x[idx].contiguous(), t[idx].contiguous(),
-                                                 m[idx].contiguous(), float(cur_lr)))
-            step += 1
-        ep_loss = float(torch.cat(losses).mean().cpu())
-        hist.append(ep_loss)
-        log("epoch %d loss %.4f" % (ep, ep_loss))
+    hist, losses = [], []
+    for step in range(steps):
+        idx = torch.randint(0, n, (batch,), generator=g).to(x.device)
+        cur_lr = lr * 0.5 * (1 + np.cos(np.pi * step / steps))
+        losses.append(ctx.fb_unet_train_step(x[idx].contiguous(), t[idx].contiguous(), m[idx].contiguous(),
+                                             float(cur_lr)))
+        if (step + 1) % log_every == 0 or step + 1 == steps:
+            hist.append(float(torch.cat(losses).mean().cpu()))
+            losses = []
+            log("step %d loss %.4f" % (step + 1, hist[-1]))
     return hist
 
 
@@ -203,16 +200,16 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     tr = sub.add_parser("train")
     tr.add_argument("--out", default=DEFAULT_WEIGHTS)
-    tr.add_argument("--pairs", type=int, default=2000)
+    tr.add_argument("--pairs", type=int, default=4000)
     tr.add_argument("--val", type=int, default=200)
-    tr.add_argument("--epochs", type=int, default=15)
+    tr.add_argument("--steps", type=int, default=6000)
     tr.add_argument("--batch", type=int, default=32)
     tr.add_argument("--lr", type=float, default=1e-3)
     args = ap.parse_args()
 
     t0 = time.time()
     log("generating %d training pairs" % args.pairs)
-    pairs = training_pairs(args.pairs)
+    pairs = training_pairs(args.pairs, workers=min(16, os.cpu_count() or 1))
     log("generated in %.1f s" % (time.time() - t0))
     import torch
     from . import fastblend as fbm
@@ -225,7 +222,7 @@ def main():
     ctx.fb_unet_load(torch.from_numpy(init_params(TRAIN_SEED)).cuda())
     v0 = validation_loss(ctx, xv, tv, mv)
     t1 = time.time()
-    hist = train(ctx, x, t, m, epochs=args.epochs, batch=args.batch, lr=args.lr)
+    hist = train(ctx, x, t, m, steps=args.steps, batch=args.batch, lr=args.lr)
     torch.cuda.synchronize()
     train_s = time.time() - t1
     v1 = validation_loss(ctx, xv, tv, mv)
@@ -237,7 +234,7 @@ def main():
     e_plain, e_learned = evaluate_blend_pairs(ctx, g, wpairs, seed=synth.PHILOX_SEED[2])
     log("blend pairs: plain@%d mean energy %.1f, learned@2 %.1f" % (ITERS, e_plain, e_learned))
     params = ctx.fb_unet_save().cpu().numpy()
-    meta = dict(pairs=args.pairs - nv, val_pairs=nv, epochs=args.epochs, batch=args.batch, lr=args.lr,
+    meta = dict(pairs=args.pairs - nv, val_pairs=nv, steps=args.steps, batch=args.batch, lr=args.lr,
                 train_loss=hist, val_loss_init=v0, val_loss=v1, train_seconds=train_s,
                 blend_energy_plain6=e_plain, blend_energy_learned2=e_learned,
                 levels=LEVELS, iters_plain=ITERS, size=SIZE, seed=TRAIN_SEED)
