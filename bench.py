@@ -100,13 +100,16 @@ def bench_learned(ctx, fbm, g, s, out, M, p, levels, seed, wpath, args, pairs, N
     prof = ctx.fb_profile_read(reset=True)
     ctx.fb_profile_enable(False)
     log("learned: %.2f ms/step" % ms)
-    energy = None
+    energy = plain_same = None
     if not args.no_energy:
         pyrs = [ctx.fb_build_pyramid(g[f], levels, p) for f in range(N)]
         descs = [dict(src_pyr=pyrs[j], tgt_pyr=pyrs[i], h=h, w=w, levels=levels, pair_id=j * N + i)
                  for (j, i) in pairs]
         energies = [e for _, e in ctx.fb_patchmatch_batch(descs, lprm)]
         energy = round(float(torch.stack(energies).double().mean().item()), 2)
+        pprm = fbm.make_params(p, levels, args.learned_iters, seed)
+        energies = [e for _, e in ctx.fb_patchmatch_batch(descs, pprm)]
+        plain_same = round(float(torch.stack(energies).double().mean().item()), 2)
         del energies, pyrs
     hc, wc = -(-h // (1 << (levels - 1))), -(-w // (1 << (levels - 1)))
     flops = fbm.load_library().fb_unet_forward_flops(len(pairs), -(-hc // 8) * 8, -(-wc // 8) * 8)
@@ -118,6 +121,7 @@ def bench_learned(ctx, fbm, g, s, out, M, p, levels, seed, wpath, args, pairs, N
     return {"ms_per_step": round(ms, 3), "blended_frames_per_s": round(N / (ms / 1e3), 3),
             "iters_per_level": args.learned_iters, "pixel_iterations_per_step": pix,
             "mean_level0_patch_energy": energy, "plain_mean_level0_patch_energy": plain_energy,
+            "plain_same_iters_mean_level0_patch_energy": plain_same,
             "energy_margin": margin, "accepted": accepted,
             "speedup_vs_plain": None,
             "kernel_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in prof.items() if v[0]},

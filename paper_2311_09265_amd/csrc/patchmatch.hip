@@ -26,8 +26,9 @@
 // sums t^2 stay in registers for the whole iteration; a source patch row is
 // one 16-byte + one 4-byte load from the padded image (no clamping needed).
 // Random-search candidates are divergent gathers, so the iteration kernel
-// fetches a candidate's first row alone and rejects it when that row's loss
-// already reaches the running best (exact: each row's loss is >= 0).
+// fetches a candidate's patch piece by piece (the first four pixels of row
+// 0, then each complete row) and drops it as soon as the part fetched
+// already reaches the running best (exact: every pixel's loss is >= 0).
 //
 // Random draws: Philox4x32-10 (Salmon et al., SC'11), key = seed, counter =
 // (pixel index r*w + c, pair id, level << 16 | iteration, m >> 2); word m & 3
@@ -118,16 +119,15 @@ struct TargetPatch {
     static constexpr int K = 2 * P + 1;
     static constexpr int S1 = K < 4 ? K : 4;  // pixels of the first-row test
     uint32_t px[K][K];
-    uint32_t row_tt[K];  // sum t^2 of every row
     uint32_t head_tt;    // sum t^2 of the first S1 pixels of row 0
-    uint32_t tt;         // sum t^2 of the patch
+    uint32_t cum_tt[K];  // sum t^2 of rows 0..i; cum_tt[K - 1] is the patch's
 };
 
 template <int P>
 __device__ __forceinline__ void load_target_patch(const uint32_t *tp, uint32_t off, uint32_t pitch_b,
                                                   TargetPatch<P> &t) {
     constexpr int K = 2 * P + 1;
-    t.tt = 0;
+    uint32_t tt = 0;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const PixRow<K> row = load_pixrow<K>(tp, off + (uint32_t)i * pitch_b);
@@ -138,8 +138,8 @@ __device__ __forceinline__ void load_target_patch(const uint32_t *tp, uint32_t o
             acc = __builtin_amdgcn_udot4(row.v[j], row.v[j], acc, false);
             if (i == 0 && j == TargetPatch<P>::S1 - 1) t.head_tt = acc;
         }
-        t.row_tt[i] = acc;
-        t.tt += acc;
+        tt += acc;
+        t.cum_tt[i] = tt;
     }
 }
 
@@ -162,7 +162,7 @@ template <int P>
 __device__ __forceinline__ uint32_t patch_loss(const uint32_t *sp, uint32_t off, uint32_t pitch_b,
                                                const TargetPatch<P> &t) {
     constexpr int K = 2 * P + 1;
-    uint32_t e = t.tt;
+    uint32_t e = t.cum_tt[K - 1];
 #pragma unroll
     for (int i = 0; i < K; ++i) e += seg_loss<P, 0, K>(sp, off + (uint32_t)i * pitch_b, t, i);
     return e;
@@ -260,19 +260,25 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     int br = (int)(f0 >> 16), bc = (int)(f0 & 0xFFFFu);
     uint32_t be = gload<uint32_t>(J.e_in, 4u * v);
 
-    // Every pixel's share of the loss is a square, so once the first S1
-    // pixels of row 0 alone reach the running best the candidate cannot pass
-    // '<': the rest of its patch is never fetched.  Far random-search
-    // candidates, divergent gathers, usually stop after that one load.
+    // Every pixel's share of the loss is a square, so any part of the patch
+    // whose loss alone reaches the running best rules the candidate out of
+    // '<'.  The first S1 pixels of row 0 are tested first (far random-search
+    // candidates, divergent gathers, usually stop after that one load), then
+    // every complete row: a row is fetched only by lanes still in the race.
+    // The sum of s^2 - 2 s t wraps in uint32, but with the t^2 sums added
+    // back every partial loss is the exact nonnegative value.
     auto consider = [&](int cr, int cc) {
         if (cr == br && cc == bc) return;
         const uint32_t off = 4u * (uint32_t)(cr * pitch + cc);
-        uint32_t e = t.head_tt + seg_loss<P, 0, S1>(src_px, off, t, 0);
-        if (e >= be) return;
-        if constexpr (S1 < K)
-            e += (t.row_tt[0] - t.head_tt) + seg_loss<P, S1, K - S1>(src_px, off + 4u * S1, t, 0);
+        uint32_t acc = seg_loss<P, 0, S1>(src_px, off, t, 0);
+        if (t.head_tt + acc >= be) return;
+        if constexpr (S1 < K) acc += seg_loss<P, S1, K - S1>(src_px, off + 4u * S1, t, 0);
 #pragma unroll
-        for (int i = 1; i < K; ++i) e += t.row_tt[i] + seg_loss<P, 0, K>(src_px, off + (uint32_t)i * pitch_b, t, i);
+        for (int i = 0; i < K; ++i) {
+            if (i > 0) acc += seg_loss<P, 0, K>(src_px, off + (uint32_t)i * pitch_b, t, i);
+            if (i < K - 1 && t.cum_tt[i] + acc >= be) return;
+        }
+        const uint32_t e = t.cum_tt[K - 1] + acc;
         if (e < be) { br = cr; bc = cc; be = e; }
     };
 
