@@ -50,6 +50,34 @@ def pair_images(h, w, seed, kind="sprites"):
     return v[0], v[2]
 
 
+def _pyramid_layout(h, w, levels, p):
+    """Byte layout of a pyramid buffer: per level its padded 4-byte pixels,
+    (h_l + 2p) rows of pitch = w_l + 2p rounded up to 16, 256-byte aligned."""
+    out, off = [], 0
+    for l in range(levels):
+        hl, wl = -(-h // (1 << l)), -(-w // (1 << l))
+        pitch = -(-(wl + 2 * p) // 16) * 16
+        out.append((hl, wl, pitch, off))
+        off = -(-(off + (hl + 2 * p) * pitch * 4) // 256) * 256
+    return out, off
+
+
+@pytest.mark.parametrize("h,w,levels,p", [(37, 53, 3, 1), (40, 33, 2, 2), (19, 70, 2, 3), (11, 9, 2, 4)])
+def test_pyramid_buffer_matches_oracle(ctx, h, w, levels, p):
+    """Every level of the pyramid buffer byte for byte: the oracle's level with
+    a replicated p-pixel border, as (R, G, B, 0) words."""
+    img = pair_images(h, w, h * w + p, "noise")[0]
+    buf = host(ctx.fb_build_pyramid(dev(img), levels, p))
+    ref = oracle.pyramid(img, levels)
+    lay, total = _pyramid_layout(h, w, levels, p)
+    assert buf.size == total
+    for l, (hl, wl, pitch, px_off) in enumerate(lay):
+        padded = np.pad(ref[l], ((p, p), (p, p), (0, 0)), mode="edge")
+        px = buf[px_off:px_off + (hl + 2 * p) * pitch * 4].reshape(hl + 2 * p, pitch, 4)
+        assert np.array_equal(px[:, :wl + 2 * p, :3], padded), l
+        assert not px[:, :wl + 2 * p, 3].any(), l
+
+
 def test_config1_translation_pair(ctx):
     """64x64 value-noise pair shifted by (3,-2) + noise, 1 level, 5 iterations."""
     A, B, _ = synth.translation_pair(synth.CONFIG_SEED[1])
