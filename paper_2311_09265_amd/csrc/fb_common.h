@@ -124,6 +124,22 @@ struct UNetPairIn {
     int32_t h, w, pitch, pad;
 };
 
+// Input of a 3x3 convolution: channels [0, ca) from a ([H][W][ca], or
+// [H/2][W/2][ca] upsampled 2x nearest when a_half), channels [ca, cin) from
+// b ([H][W][cin - ca]); all channel counts multiples of 16.
+struct ConvIn {
+    const uint16_t *a;
+    const uint16_t *b;
+    int32_t ca;
+    int32_t a_half;
+};
+constexpr int kConvTile = 256;     // output pixels per workgroup of the LDS kernel
+constexpr int kConvHaloMax = 1024; // input pixels (with border) one workgroup may stage
+// whether the LDS kernel takes images of this shape (else a single-tensor
+// input goes to the direct kernel and a split input is refused)
+bool conv_lds_fits(int B, int H, int W);
+hipError_t launch_conv3x3_in(const ConvIn &X, int B, int H, int W, int cin, const uint16_t *wt,
+                             const float *bias, void *out, int cout, bool relu, bool out_f32, hipStream_t s);
 hipError_t launch_conv3x3(const uint16_t *in, int B, int H, int W, int cin, const uint16_t *wt,
                           const float *bias, void *out, int cout, bool relu, bool out_f32, hipStream_t s);
 hipError_t launch_conv_wgrad(const uint16_t *in, const uint16_t *g, int B, int H, int W, int cin, int cout,
@@ -170,7 +186,9 @@ uint16_t *unet_input_buffer(UNet *u);
 float *unet_pred_buffer(UNet *u);
 float *unet_loss_buffer(UNet *u);
 hipError_t unet_input_from_f32(UNet *u, const float *x6, hipStream_t s);
-hipError_t unet_forward(UNet *u, hipStream_t s);
+// keep_cat: also materialise the decoder's concatenated inputs (needed by a
+// following backward pass; the forward convolutions read them in place)
+hipError_t unet_forward(UNet *u, hipStream_t s, bool keep_cat);
 hipError_t unet_loss_backward(UNet *u, const float *target, const float *mask, bool backward, hipStream_t s);
 hipError_t unet_adam(UNet *u, float lr, hipStream_t s);
 double unet_forward_flops(int B, int H, int W);

@@ -519,7 +519,7 @@ fb_status plan_learned_seeds(fb_ctx *ctx, Plan &P, std::vector<PairSpec> &pairs)
             if (e != hipSuccess) return e;
             const UNetPairIn *pin = reinterpret_cast<const UNetPairIn *>(tab + in_off);
             if ((e = launch_input_from_pyramids(pin, B, H8, W8, unet_input_buffer(u), s)) != hipSuccess) return e;
-            if ((e = unet_forward(u, s)) != hipSuccess) return e;
+            if ((e = unet_forward(u, s, false)) != hipSuccess) return e;
             return launch_pred_to_seed(unet_pred_buffer(u), H8, W8, pin,
                                        reinterpret_cast<int32_t *const *>(tab + dst_off), B, s);
         }});
@@ -1014,7 +1014,7 @@ fb_status fb_unet_forward(fb_ctx *ctx, const float *pair6, int32_t B, int32_t h,
     UNet *u = ctx->unet;
     FB_HIP(unet_reserve(u, B, h, w, false));
     FB_HIP(unet_input_from_f32(u, pair6, s));
-    FB_HIP(unet_forward(u, s));
+    FB_HIP(unet_forward(u, s, false));
     FB_HIP(launch_pred_extract(unet_pred_buffer(u), (long)B * h * w, offsets, s));
     return FB_OK;
 }
@@ -1029,7 +1029,7 @@ static fb_status unet_backward_common(fb_ctx *ctx, const float *pair6, const flo
     UNet *u = ctx->unet;
     FB_HIP(unet_reserve(u, B, h, w, true));
     FB_HIP(unet_input_from_f32(u, pair6, s));
-    FB_HIP(unet_forward(u, s));
+    FB_HIP(unet_forward(u, s, true));
     FB_HIP(unet_loss_backward(u, target, mask, true, s));
     if (loss) FB_HIP(hipMemcpyAsync(loss, unet_loss_buffer(u), sizeof(float), hipMemcpyDeviceToDevice, s));
     return FB_OK;

@@ -18,6 +18,8 @@
 //   A (16 x 16, M x K): lane l holds A[l % 16][4 (l / 16) + j], j = 0..3
 //   B (16 x 16, K x N): lane l holds B[4 (l / 16) + j][l % 16]
 //   D (16 x 16):        lane l holds D[4 (l / 16) + j][l % 16]
+#include <algorithm>
+
 #include "fb_common.h"
 
 namespace fb {
@@ -120,6 +122,176 @@ k_conv3x3(const uint16_t *__restrict__ in, int B, int H, int W, int cin,
                 float v = acc[mb][b][j] + bv;
                 if (RELU) v = fmaxf(v, 0.f);
                 const size_t o = (size_t)p * cout + co;
+                if (OUT_F32) reinterpret_cast<float *>(out)[o] = v;
+                else reinterpret_cast<uint16_t *>(out)[o] = f32_to_bf16(v);
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward / data-gradient convolution on v_mfma_f32_32x32x16_bf16, staged
+// through LDS.  A workgroup takes kConvTile consecutive pixels of one image
+// (4 waves x 2 row blocks of 32 pixels: M) and 32 NBW output channels (N).
+// For every 16-channel slice of the input (K) it stages in LDS the input rows
+// the tile touches, with a zero border (the halo), and the slice's weights of
+// all 9 taps; every tap then reads its A and B fragments from LDS as
+// contiguous 1 KB blocks, so each input element is fetched from memory once
+// per slice instead of once per tap.  Input channels [0, ca) may come from a
+// half-resolution tensor upsampled 2x (nearest): the decoder's
+// upsample-and-concatenate is read in place instead of materialised.
+//
+// 32x32x16 bf16 lane layout (wave64):
+//   A (32 x 16): lane l holds A[l % 32][8 (l / 32) + j], j = 0..7
+//   B (16 x 32): lane l holds B[8 (l / 32) + j][l % 32]
+//   D (32 x 32): lane l holds D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32], i = 0..15
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) {
+    union {
+        uint4 u;
+        bf16x8 b;
+    } c;
+    c.u = u;
+    return c.b;
+}
+
+template <int NBW, bool RELU, bool OUT_F32>
+__global__ void __launch_bounds__(256)
+k_conv3x3_lds(ConvIn X, int H, int W, int cin, int tiles_per_img, const uint16_t *__restrict__ wt,
+              const float *__restrict__ bias, void *__restrict__ out, int cout) {
+    constexpr int NT = 32 * NBW;
+    constexpr int WE = (9 * NT + 255) / 256;  // weight rows staged per thread
+    constexpr int HE = kConvHaloMax / 256;    // halo pixels staged per thread (at most)
+    extern __shared__ uint4 lds[];
+    uint4 *s_w = lds;               // [9][NT][2]: 16 channels of one weight row
+    uint4 *s_in = lds + 9 * NT * 2; // [halo pixels][2]: 16 channels of one pixel
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int img = blockIdx.x / tiles_per_img;
+    const int HW = H * W, WP = W + 2;
+    const int p0 = (blockIdx.x - img * tiles_per_img) * kConvTile;
+    const int p1 = min(p0 + kConvTile, HW);
+    const int ya = p0 / W - 1;                           // first halo row
+    const int halo = ((p1 - 1) / W + 1 - ya + 1) * WP;  // <= kConvHaloMax (checked by the host)
+    const int co0 = blockIdx.y * NT;
+    const int half = lane >> 5;
+    const int cb = cin - X.ca;
+
+    // what this thread stages: halo pixels tid + 256 k (source pixel index in
+    // a and in b, or -1 for the zero border) and weight rows tid + 256 k
+    int src_a[HE], src_b[HE];
+#pragma unroll
+    for (int k = 0; k < HE; ++k) {
+        const int i = tid + 256 * k;
+        src_a[k] = src_b[k] = -1;
+        if (i < halo) {
+            const int hy = i / WP, hx = i - hy * WP;
+            const int y = ya + hy, x = hx - 1;
+            if (y >= 0 && y < H && x >= 0 && x < W) {
+                src_b[k] = (img * H + y) * W + x;
+                src_a[k] = X.a_half ? (img * (H >> 1) + (y >> 1)) * (W >> 1) + (x >> 1) : src_b[k];
+            }
+        }
+    }
+    int w_row[WE];
+#pragma unroll
+    for (int k = 0; k < WE; ++k) {
+        const int i = tid + 256 * k;
+        const int tap = i / NT, co = co0 + (i - tap * NT);
+        w_row[k] = (i < 9 * NT && co < cout) ? tap * cout + co : -1;
+    }
+    uint4 r_in[HE][2], r_w[WE][2];
+    auto fetch = [&](int c0) {
+        const bool in_a = c0 < X.ca;
+        const uint16_t *base = in_a ? X.a + c0 : X.b + (c0 - X.ca);
+        const int stride = in_a ? X.ca : cb;
+#pragma unroll
+        for (int k = 0; k < HE; ++k) {
+            const int sp = in_a ? src_a[k] : src_b[k];
+            r_in[k][0] = r_in[k][1] = make_uint4(0, 0, 0, 0);
+            if (sp >= 0) {
+                const uint4 *q = reinterpret_cast<const uint4 *>(base + (size_t)sp * stride);
+                r_in[k][0] = q[0];
+                r_in[k][1] = q[1];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < WE; ++k) {
+            r_w[k][0] = r_w[k][1] = make_uint4(0, 0, 0, 0);
+            if (w_row[k] >= 0) {
+                const uint4 *q = reinterpret_cast<const uint4 *>(wt + (size_t)w_row[k] * cin + c0);
+                r_w[k][0] = q[0];
+                r_w[k][1] = q[1];
+            }
+        }
+    };
+
+    int hidx[2];  // halo index of this lane's pixel in each of its row blocks
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+        const int p = min(p0 + 64 * wave + 32 * mb + (lane & 31), p1 - 1);
+        const int y = p / W;
+        hidx[mb] = (y - ya) * WP + (p - y * W) + 1;
+    }
+    f32x16 acc[2][NBW];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[mb][nb][i] = 0.f;
+
+    fetch(0);
+    for (int c0 = 0; c0 < cin; c0 += 16) {
+        __syncthreads();  // the previous slice's fragments have been read
+#pragma unroll
+        for (int k = 0; k < HE; ++k) {
+            const int i = tid + 256 * k;
+            if (i < halo) {
+                s_in[2 * i] = r_in[k][0];
+                s_in[2 * i + 1] = r_in[k][1];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < WE; ++k) {
+            const int i = tid + 256 * k;
+            if (i < 9 * NT) {
+                s_w[2 * i] = r_w[k][0];
+                s_w[2 * i + 1] = r_w[k][1];
+            }
+        }
+        __syncthreads();
+        if (c0 + 16 < cin) fetch(c0 + 16);  // in flight while the matrix cores work
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int toff = (tap / 3 - 1) * WP + (tap % 3 - 1);
+            bf16x8 a[2], b[NBW];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) a[mb] = as_bf16x8(s_in[2 * (hidx[mb] + toff) + half]);
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb) b[nb] = as_bf16x8(s_w[2 * (tap * NT + 32 * nb + (lane & 31)) + half]);
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NBW; ++nb)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NBW; ++nb) {
+        const int co = co0 + 32 * nb + (lane & 31);
+        if (co >= cout) continue;
+        const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int p = p0 + 64 * wave + 32 * mb + 8 * (i >> 2) + 4 * half + (i & 3);
+                if (p >= p1) continue;
+                float v = acc[mb][nb][i] + bv;
+                if (RELU) v = fmaxf(v, 0.f);
+                const size_t o = ((size_t)img * HW + p) * cout + co;
                 if (OUT_F32) reinterpret_cast<float *>(out)[o] = v;
                 else reinterpret_cast<uint16_t *>(out)[o] = f32_to_bf16(v);
             }
@@ -489,6 +661,48 @@ k_pred_extract(const float *__restrict__ pred, long n_px, float *__restrict__ ou
 }  // namespace
 
 static inline dim3 grid1(long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+// largest halo (pixels) of a kConvTile-pixel tile of a W-wide image of HW pixels
+static int conv_halo_px(int H, int W) {
+    const int HW = H * W;
+    int best = 0;
+    for (int p0 = 0; p0 < HW; p0 += kConvTile) {
+        const int p1 = std::min(p0 + kConvTile, HW);
+        best = std::max(best, ((p1 - 1) / W - p0 / W + 3) * (W + 2));
+    }
+    return best;
+}
+
+bool conv_lds_fits(int B, int H, int W) {
+    return conv_halo_px(H, W) <= kConvHaloMax && (long)B * H * W < (1L << 31);
+}
+
+hipError_t launch_conv3x3_in(const ConvIn &X, int B, int H, int W, int cin, const uint16_t *wt,
+                             const float *bias, void *out, int cout, bool relu, bool out_f32, hipStream_t s) {
+    if (cin % 16 || cout % 16 || X.ca % 16 || X.ca > cin || (X.ca < cin && !X.b) || (X.a_half && (H % 2 || W % 2)))
+        return hipErrorInvalidValue;
+    const int nbw = cout <= 32 ? 1 : (cout <= 64 ? 2 : 3);
+    const int halo = conv_halo_px(H, W);
+    const size_t lds = ((size_t)9 * 32 * nbw + halo) * 2 * sizeof(uint4);
+    if (!conv_lds_fits(B, H, W)) {
+        // wide images: the direct kernel, which needs the input in one tensor
+        if (X.ca != cin || X.a_half) return hipErrorInvalidValue;
+        return launch_conv3x3(X.a, B, H, W, cin, wt, bias, out, cout, relu, out_f32, s);
+    }
+    const int tiles = (H * W + kConvTile - 1) / kConvTile;
+    dim3 grid((unsigned)(B * tiles), (unsigned)((cout + 32 * nbw - 1) / (32 * nbw)));
+#define FB_CONVL(NB)                                                                                            \
+    if (out_f32) hipLaunchKernelGGL((k_conv3x3_lds<NB, false, true>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, out, cout); \
+    else if (relu) hipLaunchKernelGGL((k_conv3x3_lds<NB, true, false>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, out, cout); \
+    else hipLaunchKernelGGL((k_conv3x3_lds<NB, false, false>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, out, cout);
+    switch (nbw) {
+    case 1: FB_CONVL(1) break;
+    case 2: FB_CONVL(2) break;
+    default: FB_CONVL(3) break;
+    }
+#undef FB_CONVL
+    return hipGetLastError();
+}
 
 hipError_t launch_conv3x3(const uint16_t *in, int B, int H, int W, int cin, const uint16_t *wt,
                           const float *bias, void *out, int cout, bool relu, bool out_f32, hipStream_t s) {

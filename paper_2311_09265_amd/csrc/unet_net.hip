@@ -219,38 +219,57 @@ float *unet_loss_buffer(UNet *u) { return u->totals; }
         if (e_ != hipSuccess) return e_;         \
     } while (0)
 
-static hipError_t conv_fwd(UNet *u, int i, hipStream_t s) {
-    const LayerDef &l = kLayers[i];
-    const int sh = kTShift[kLIn[i]];
-    const float *bias = u->w32 + u->w_off[i] + 9 * (size_t)l.cout * l.cin;
-    void *out = kLOut[i] >= 0 ? (void *)u->act[kLOut[i]] : (void *)u->pred;
-    return launch_conv3x3(u->act[kLIn[i]], u->B, u->H >> sh, u->W >> sh, l.cin, u->w16 + u->w16_off[i], bias,
-                          out, l.cout, l.relu, kLOut[i] < 0, s);
+// decoder layers that read [upsampled deeper tensor, skip] in place
+static bool upcat_input(int i, int *deep, int *skip) {
+    switch (i) {
+    case 8: *deep = BT; *skip = E3; return true;
+    case 10: *deep = D3; *skip = E2; return true;
+    case 12: *deep = D2; *skip = E1; return true;
+    default: return false;
+    }
 }
 
-hipError_t unet_forward(UNet *u, hipStream_t s) {
+// keep_cat: the decoder's concatenated input is materialised anyway
+static hipError_t conv_fwd(UNet *u, int i, bool keep_cat, hipStream_t s) {
+    const LayerDef &l = kLayers[i];
+    const int sh = kTShift[kLIn[i]], H = u->H >> sh, W = u->W >> sh;
+    const float *bias = u->w32 + u->w_off[i] + 9 * (size_t)l.cout * l.cin;
+    void *out = kLOut[i] >= 0 ? (void *)u->act[kLOut[i]] : (void *)u->pred;
+    int deep, skip;
+    ConvIn X{u->act[kLIn[i]], nullptr, l.cin, 0};
+    if (upcat_input(i, &deep, &skip)) {
+        if (conv_lds_fits(u->B, H, W)) {
+            X = ConvIn{u->act[deep], u->act[skip], kTCh[deep], 1};
+        } else if (!keep_cat) {
+            FB_TRY(launch_upcat(u->act[deep], u->act[skip], u->B, H, W, kTCh[deep], kTCh[skip], u->act[kLIn[i]], s));
+        }
+    }
+    return launch_conv3x3_in(X, u->B, H, W, l.cin, u->w16 + u->w16_off[i], bias, out, l.cout, l.relu, kLOut[i] < 0, s);
+}
+
+hipError_t unet_forward(UNet *u, hipStream_t s, bool keep_cat) {
     const int B = u->B, H = u->H, W = u->W;
-    FB_TRY(conv_fwd(u, 0, s));
-    FB_TRY(conv_fwd(u, 1, s));
+    FB_TRY(conv_fwd(u, 0, keep_cat, s));
+    FB_TRY(conv_fwd(u, 1, keep_cat, s));
     FB_TRY(launch_pool2(u->act[E1], B, H, W, 32, u->act[P1], s));
-    FB_TRY(conv_fwd(u, 2, s));
-    FB_TRY(conv_fwd(u, 3, s));
+    FB_TRY(conv_fwd(u, 2, keep_cat, s));
+    FB_TRY(conv_fwd(u, 3, keep_cat, s));
     FB_TRY(launch_pool2(u->act[E2], B, H / 2, W / 2, 48, u->act[P2], s));
-    FB_TRY(conv_fwd(u, 4, s));
-    FB_TRY(conv_fwd(u, 5, s));
+    FB_TRY(conv_fwd(u, 4, keep_cat, s));
+    FB_TRY(conv_fwd(u, 5, keep_cat, s));
     FB_TRY(launch_pool2(u->act[E3], B, H / 4, W / 4, 96, u->act[P3], s));
-    FB_TRY(conv_fwd(u, 6, s));
-    FB_TRY(conv_fwd(u, 7, s));
-    FB_TRY(launch_upcat(u->act[BT], u->act[E3], B, H / 4, W / 4, 192, 96, u->act[C3], s));
-    FB_TRY(conv_fwd(u, 8, s));
-    FB_TRY(conv_fwd(u, 9, s));
-    FB_TRY(launch_upcat(u->act[D3], u->act[E2], B, H / 2, W / 2, 96, 48, u->act[C2], s));
-    FB_TRY(conv_fwd(u, 10, s));
-    FB_TRY(conv_fwd(u, 11, s));
-    FB_TRY(launch_upcat(u->act[D2], u->act[E1], B, H, W, 48, 32, u->act[C1], s));
-    FB_TRY(conv_fwd(u, 12, s));
-    FB_TRY(conv_fwd(u, 13, s));
-    return conv_fwd(u, 14, s);
+    FB_TRY(conv_fwd(u, 6, keep_cat, s));
+    FB_TRY(conv_fwd(u, 7, keep_cat, s));
+    if (keep_cat) FB_TRY(launch_upcat(u->act[BT], u->act[E3], B, H / 4, W / 4, 192, 96, u->act[C3], s));
+    FB_TRY(conv_fwd(u, 8, keep_cat, s));
+    FB_TRY(conv_fwd(u, 9, keep_cat, s));
+    if (keep_cat) FB_TRY(launch_upcat(u->act[D3], u->act[E2], B, H / 2, W / 2, 96, 48, u->act[C2], s));
+    FB_TRY(conv_fwd(u, 10, keep_cat, s));
+    FB_TRY(conv_fwd(u, 11, keep_cat, s));
+    if (keep_cat) FB_TRY(launch_upcat(u->act[D2], u->act[E1], B, H, W, 48, 32, u->act[C1], s));
+    FB_TRY(conv_fwd(u, 12, keep_cat, s));
+    FB_TRY(conv_fwd(u, 13, keep_cat, s));
+    return conv_fwd(u, 14, keep_cat, s);
 }
 
 // weight and bias gradients of layer i from the gradient g of its output
@@ -271,8 +290,8 @@ static hipError_t conv_wgrad(UNet *u, int i, const uint16_t *g, hipStream_t s) {
 static hipError_t conv_dgrad(UNet *u, int i, const uint16_t *g, uint16_t *gin, hipStream_t s) {
     const LayerDef &l = kLayers[i];
     const int sh = kTShift[kLIn[i]];
-    return launch_conv3x3(g, u->B, u->H >> sh, u->W >> sh, l.cout, u->wt16 + u->w16_off[i], nullptr, gin, l.cin,
-                          false, false, s);
+    return launch_conv3x3_in(ConvIn{g, nullptr, l.cout, 0}, u->B, u->H >> sh, u->W >> sh, l.cout,
+                             u->wt16 + u->w16_off[i], nullptr, gin, l.cin, false, false, s);
 }
 
 static long elems(UNet *u, int t) { return (long)u->B * (u->H >> kTShift[t]) * (u->W >> kTShift[t]) * kTCh[t]; }

@@ -38,9 +38,12 @@ def test_param_count(ctx):
 
 
 def test_forward_matches_oracle(ctx):
+    """Ragged tiles (16x24), several tiles per image (40x32), and an image
+    wide enough (16x400) for the convolutions to take the direct kernel with
+    the decoder's concatenations materialised."""
     flat = net.init_params(11)
     ctx.fb_unet_load(flat.cuda())
-    for B, h, w in ((2, 16, 24), (1, 40, 32)):
+    for B, h, w in ((2, 16, 24), (1, 40, 32), (1, 16, 400)):
         x, _, _ = _batch(B, h, w, B * h)
         got = ctx.fb_unet_forward(x.cuda())
         ref, _ = net.forward(flat, x, emulate_bf16=True)
