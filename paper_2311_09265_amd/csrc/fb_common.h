@@ -138,10 +138,16 @@ constexpr int kConvHaloMax = 1024; // input pixels (with border) one workgroup m
 // whether the LDS kernel takes images of this shape (else a single-tensor
 // input goes to the direct kernel and a split input is refused)
 bool conv_lds_fits(int B, int H, int W);
+// out: [px][ostride], channels [0, ostride) of the cout computed ones
 hipError_t launch_conv3x3_in(const ConvIn &X, int B, int H, int W, int cin, const uint16_t *wt,
-                             const float *bias, void *out, int cout, bool relu, bool out_f32, hipStream_t s);
+                             const float *bias, void *out, int cout, int ostride, bool relu, bool out_f32,
+                             hipStream_t s);
 hipError_t launch_conv3x3(const uint16_t *in, int B, int H, int W, int cin, const uint16_t *wt,
-                          const float *bias, void *out, int cout, bool relu, bool out_f32, hipStream_t s);
+                          const float *bias, void *out, int cout, int ostride, bool relu, bool out_f32,
+                          hipStream_t s);
+// the offset head: 32 channels -> fp32 [px][2] (weights [9][cout_pad][32])
+hipError_t launch_head3x3(const uint16_t *in, int B, int H, int W, int cin, const uint16_t *wt, int cout_pad,
+                          const float *bias, float *out, hipStream_t s);
 hipError_t launch_conv_wgrad(const uint16_t *in, const uint16_t *g, int B, int H, int W, int cin, int cout,
                              int chunk_px, float *partial, float *bias_partial, hipStream_t s);
 hipError_t launch_reduce_chunks(const float *partial, int n_chunks, long n, float *out, hipStream_t s);

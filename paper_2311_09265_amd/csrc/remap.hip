@@ -10,56 +10,75 @@
 // divisor = their count; the keyframe combination of Eq. 9 has two terms
 // with weights (r-i)/(r-l), (i-l)/(r-l) and divisor 1.
 //
-// One thread per output pixel of one output frame.  Per remapped term a
-// thread reads (2p+1)^2 packed NNF entries (coalesced along rows, shared
-// through L1 with the neighbouring threads) and gathers the same number of
-// 4-byte style pixels from the padded frame (so F(v+d) - d needs no clamp).
-// Channel sums are integers (R and B in the two halves of one register, G in
-// another); each term costs one fp32 division per channel.  HBM traffic per
-// output frame: its fields and style frames once (L2-resident gathers) plus
-// 12 B per output pixel.
+// One thread per output pixel of one output frame; a workgroup is a tile of
+// one frame.  Per remapped term the workgroup stages the tile's NNF entries
+// with a p-pixel border in LDS (one coalesced pass), so each thread reads its
+// (2p+1)^2 field entries from LDS, then gathers as many 4-byte style pixels
+// from the padded frame (so F(v+d) - d needs no clamp) through global
+// address space with 32-bit offsets.  Channel sums are integers (R and B in
+// the two halves of one register, G in another); each term costs one fp32
+// division per channel.  HBM traffic per output frame: its fields and style
+// frames once (L2-resident gathers) plus 12 B per output pixel.
 #include "fb_common.h"
 
 namespace fb {
 
 namespace {
 
-constexpr int kRTW = 64, kRTH = 4;
+constexpr int kRTW = 32, kRTH = 8;
+
+template <class T>
+__device__ __forceinline__ T gload(const void *base, uint32_t byte_off) {
+    return *(const __attribute__((address_space(1))) T *)((const __attribute__((address_space(1))) char *)base +
+                                                          byte_off);
+}
 
 template <int P>
 __global__ void __launch_bounds__(kRTW *kRTH)
 k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__ terms, int h,
             int w, int pitch, int tiles_x) {
+    constexpr int SW = kRTW + 2 * P, SH = kRTH + 2 * P;
+    __shared__ uint32_t sf[SH * SW];  // the tile's field entries with a P-pixel border
     const RemapFrame fr = frames[blockIdx.y];
     const int ty = (int)blockIdx.x / tiles_x, tx = (int)blockIdx.x - ty * tiles_x;
-    const int r = ty * kRTH + (int)threadIdx.y, c = tx * kRTW + (int)threadIdx.x;
-    if (r >= h || c >= w) return;
+    const int rt = ty * kRTH, ct = tx * kRTW;
+    const int r = rt + (int)threadIdx.y, c = ct + (int)threadIdx.x;
+    const int tid = (int)threadIdx.y * kRTW + (int)threadIdx.x;
+    const bool active = r < h && c < w;  // no early exit: the term loop has barriers
     const int r0 = max(-P, -r), r1 = min(P, h - 1 - r);
     const int c0 = max(-P, -c), c1 = min(P, w - 1 - c);
     const float denom = (float)(255 * (r1 - r0 + 1) * (c1 - c0 + 1));
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
     for (int k = 0; k < fr.n_terms; ++k) {
         const RemapTerm T = terms[fr.term_base + k];
-        const uint32_t *__restrict__ sp = T.style_px;
+        const uint32_t *sp = T.style_px;
         if (T.f == nullptr) {
-            const uint32_t px = sp[(size_t)(r + P) * pitch + (c + P)];
-            a0 += T.weight * ((float)(px & 0xFFu) / 255.0f);
-            a1 += T.weight * ((float)((px >> 8) & 0xFFu) / 255.0f);
-            a2 += T.weight * ((float)((px >> 16) & 0xFFu) / 255.0f);
+            if (active) {
+                const uint32_t px = gload<uint32_t>(sp, 4u * (uint32_t)((r + P) * pitch + (c + P)));
+                a0 += T.weight * ((float)(px & 0xFFu) / 255.0f);
+                a1 += T.weight * ((float)((px >> 8) & 0xFFu) / 255.0f);
+                a2 += T.weight * ((float)((px >> 16) & 0xFFu) / 255.0f);
+            }
             continue;
         }
-        const uint32_t *__restrict__ f = T.f;
+        __syncthreads();  // the previous term's field entries have been read
+        for (int i = tid; i < SH * SW; i += kRTW * kRTH) {
+            const int yy = rt - P + i / SW, xx = ct - P + i % SW;
+            sf[i] = (yy >= 0 && yy < h && xx >= 0 && xx < w) ? gload<uint32_t>(T.f, 4u * (uint32_t)(yy * w + xx)) : 0u;
+        }
+        __syncthreads();
+        if (!active) continue;
         uint32_t rb = 0, g = 0;
 #pragma unroll
         for (int dr = -P; dr <= P; ++dr) {
             if (dr < r0 || dr > r1) continue;
-            const uint32_t *frow = f + (size_t)(r + dr) * w + c;
+            const uint32_t *srow = sf + ((int)threadIdx.y + P + dr) * SW + (int)threadIdx.x + P;
 #pragma unroll
             for (int dc = -P; dc <= P; ++dc) {
                 if (dc < c0 || dc > c1) continue;
-                const uint32_t q = frow[dc];
+                const uint32_t q = srow[dc];
                 const int sr = (int)(q >> 16) - dr + P, sc = (int)(q & 0xFFFFu) - dc + P;
-                const uint32_t px = sp[(size_t)sr * pitch + sc];
+                const uint32_t px = gload<uint32_t>(sp, 4u * (uint32_t)(sr * pitch + sc));
                 rb += px & 0x00FF00FFu;
                 g += (px >> 8) & 0xFFu;
             }
@@ -68,6 +87,7 @@ k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__
         a1 += T.weight * ((float)g / denom);
         a2 += T.weight * ((float)(rb >> 16) / denom);
     }
+    if (!active) return;
     float *o = fr.out + ((size_t)r * w + c) * 3;
     o[0] = a0 / fr.divisor;
     o[1] = a1 / fr.divisor;

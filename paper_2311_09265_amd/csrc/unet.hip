@@ -59,7 +59,7 @@ template <int NB, bool RELU, bool OUT_F32>
 __global__ void __launch_bounds__(256)
 k_conv3x3(const uint16_t *__restrict__ in, int B, int H, int W, int cin,
           const uint16_t *__restrict__ wt, const float *__restrict__ bias, void *__restrict__ out,
-          int cout) {
+          int cout, int ostride) {
     constexpr int MB = 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const long total = (long)B * H * W;
@@ -112,6 +112,7 @@ k_conv3x3(const uint16_t *__restrict__ in, int B, int H, int W, int cin,
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int co = co0 + 16 * b + (lane & 15);
+        if (co >= ostride) continue;
         const float bv = bias ? bias[co] : 0.f;
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
@@ -121,7 +122,7 @@ k_conv3x3(const uint16_t *__restrict__ in, int B, int H, int W, int cin,
                 if (p >= total) continue;
                 float v = acc[mb][b][j] + bv;
                 if (RELU) v = fmaxf(v, 0.f);
-                const size_t o = (size_t)p * cout + co;
+                const size_t o = (size_t)p * ostride + co;
                 if (OUT_F32) reinterpret_cast<float *>(out)[o] = v;
                 else reinterpret_cast<uint16_t *>(out)[o] = f32_to_bf16(v);
             }
@@ -160,7 +161,7 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) {
 template <int NBW, bool RELU, bool OUT_F32>
 __global__ void __launch_bounds__(256)
 k_conv3x3_lds(ConvIn X, int H, int W, int cin, int tiles_per_img, const uint16_t *__restrict__ wt,
-              const float *__restrict__ bias, void *__restrict__ out, int cout) {
+              const float *__restrict__ bias, void *__restrict__ out, int cout, int ostride) {
     constexpr int NT = 32 * NBW;
     constexpr int WE = (9 * NT + 255) / 256;  // weight rows staged per thread
     constexpr int HE = kConvHaloMax / 256;    // halo pixels staged per thread (at most)
@@ -281,7 +282,7 @@ k_conv3x3_lds(ConvIn X, int H, int W, int cin, int tiles_per_img, const uint16_t
 #pragma unroll
     for (int nb = 0; nb < NBW; ++nb) {
         const int co = co0 + 32 * nb + (lane & 31);
-        if (co >= cout) continue;
+        if (co >= ostride) continue;
         const float bv = bias ? bias[co] : 0.f;
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
@@ -291,9 +292,95 @@ k_conv3x3_lds(ConvIn X, int H, int W, int cin, int tiles_per_img, const uint16_t
                 if (p >= p1) continue;
                 float v = acc[mb][nb][i] + bv;
                 if (RELU) v = fmaxf(v, 0.f);
-                const size_t o = ((size_t)img * HW + p) * cout + co;
+                const size_t o = ((size_t)img * HW + p) * ostride + co;
                 if (OUT_F32) reinterpret_cast<float *>(out)[o] = v;
                 else reinterpret_cast<uint16_t *>(out)[o] = f32_to_bf16(v);
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Offset head: 3x3 convolution from 32 bf16 channels to the 2 offset channels,
+// fp32 out [px][2].  v_mfma_f32_16x16x32_bf16 covers all 32 input channels of
+// one tap for 16 pixels (M) and 16 output channels (N, the first 2 real), so
+// a tap is one matrix-core instruction per 16 pixels.  The tile's input rows
+// with a zero border are staged in LDS once (all 32 channels); the weights of
+// all taps stay in registers.
+//
+// 16x16x32 bf16 lane layout (wave64):
+//   A (16 x 32): lane l holds A[l % 16][8 (l / 16) + j], j = 0..7
+//   B (32 x 16): lane l holds B[8 (l / 16) + j][l % 16]
+//   D (16 x 16): lane l holds D[4 (l / 16) + j][l % 16], j = 0..3
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_head3x3(const uint16_t *__restrict__ in, int H, int W, int tiles_per_img, const uint16_t *__restrict__ wt,
+          int cout_pad, const float *__restrict__ bias, float *__restrict__ out) {
+    constexpr int CIN = 32, HE = kConvHaloMax / 256;
+    extern __shared__ uint4 lds[];  // [halo pixels][4]: 32 channels of one pixel
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int img = blockIdx.x / tiles_per_img;
+    const int HW = H * W, WP = W + 2;
+    const int p0 = (blockIdx.x - img * tiles_per_img) * kConvTile;
+    const int p1 = min(p0 + kConvTile, HW);
+    const int ya = p0 / W - 1;
+    const int halo = ((p1 - 1) / W + 1 - ya + 1) * WP;
+    // all loads first, then all LDS stores
+    uint4 v[HE][4];
+#pragma unroll
+    for (int k = 0; k < HE; ++k) {
+        const int i = tid + 256 * k;
+        const int hy = i / WP, hx = i - hy * WP;
+        const int y = ya + hy, x = hx - 1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[k][j] = make_uint4(0, 0, 0, 0);
+        if (i < halo && y >= 0 && y < H && x >= 0 && x < W) {
+            const uint4 *q = reinterpret_cast<const uint4 *>(in + (((size_t)img * H + y) * W + x) * CIN);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[k][j] = q[j];
+        }
+    }
+    // B fragments of all taps: output channel lane % 16, input channels 8 (lane / 16) + j
+    bf16x8 b[9];
+    const int co = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+        b[tap] = as_bf16x8(*reinterpret_cast<const uint4 *>(wt + ((size_t)tap * cout_pad + co) * CIN + 8 * kq));
+#pragma unroll
+    for (int k = 0; k < HE; ++k) {
+        const int i = tid + 256 * k;
+        if (i < halo) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) lds[4 * i + j] = v[k][j];
+        }
+    }
+    __syncthreads();
+    // each wave: 4 blocks of 16 pixels, their tap chains interleaved
+    int hc[4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+        const int pa = min(p0 + 64 * wave + 16 * mb + (lane & 15), p1 - 1);  // this lane's A row
+        const int y = pa / W;
+        hc[mb] = (y - ya) * WP + (pa - y * W) + 1;
+    }
+    f32x4 acc[4];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int toff = (tap / 3 - 1) * WP + (tap % 3 - 1);
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(lds[4 * (hc[mb] + toff) + kq]), b[tap],
+                                                              acc[mb], 0, 0, 0);
+    }
+    if (co < 2) {
+        const float bv = bias[co];
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int p = p0 + 64 * wave + 16 * mb + 4 * kq + j;
+                if (p < p1) out[((size_t)img * HW + p) * 2 + co] = acc[mb][j] + bv;
             }
     }
 }
@@ -508,12 +595,12 @@ k_pred_to_seed(const float *__restrict__ pred, int H8, int W8, const UNetPairIn 
     const UNetPairIn P = pairs[n];
     if (i >= P.h * P.w) return;
     const int y = i / P.w, x = i % P.w;
-    const float *q = pred + (((size_t)n * H8 + y) * W8 + x) * 16;
+    const float *q = pred + (((size_t)n * H8 + y) * W8 + x) * 2;
     seeds[n][2 * i] = (int32_t)roundf(fminf(fmaxf(q[0], -32767.f), 32767.f));
     seeds[n][2 * i + 1] = (int32_t)roundf(fminf(fmaxf(q[1], -32767.f), 32767.f));
 }
 
-// masked L1 loss over channels 0,1 of pred [n_px][16]; per-block partial
+// masked L1 loss of pred [n_px][2]; per-block partial
 // sums of (mask * |pred - target|) and mask
 __global__ void __launch_bounds__(256)
 k_loss_partial(const float *__restrict__ pred, const float *__restrict__ target, const float *__restrict__ mask,
@@ -523,7 +610,7 @@ k_loss_partial(const float *__restrict__ pred, const float *__restrict__ target,
     float l = 0.f, m = 0.f;
     if (i < n_px) {
         m = mask[i];
-        l = m * (fabsf(pred[i * 16] - target[2 * i]) + fabsf(pred[i * 16 + 1] - target[2 * i + 1]));
+        l = m * (fabsf(pred[2 * i] - target[2 * i]) + fabsf(pred[2 * i + 1] - target[2 * i + 1]));
     }
     sl[threadIdx.x] = l;
     sm[threadIdx.x] = m;
@@ -577,7 +664,7 @@ k_loss_grad(const float *__restrict__ pred, const float *__restrict__ target, co
     const int c = (int)(i % 16);
     float v = 0.f;
     if (c < 2) {
-        const float d = pred[p * 16 + c] - target[2 * p + c];
+        const float d = pred[2 * p + c] - target[2 * p + c];
         v = mask[p] * (float)((d > 0.f) - (d < 0.f)) / totals[1];
     }
     g[i] = f32_to_bf16(v);
@@ -650,12 +737,12 @@ __global__ void __launch_bounds__(256) k_fill_zero(float *__restrict__ p, long n
     if (i < n) p[i] = 0.f;
 }
 
-// channels 0, 1 of the head output [n_px][16] -> offsets [n_px][2]
+// head output [n_px][2] -> the caller's offsets [n_px][2]
 __global__ void __launch_bounds__(256)
 k_pred_extract(const float *__restrict__ pred, long n_px, float *__restrict__ out) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_px * 2) return;
-    out[i] = pred[(i / 2) * 16 + (i % 2)];
+    out[i] = pred[i];
 }
 
 }  // namespace
@@ -673,13 +760,25 @@ static int conv_halo_px(int H, int W) {
     return best;
 }
 
+hipError_t launch_head3x3(const uint16_t *in, int B, int H, int W, int cin, const uint16_t *wt, int cout_pad,
+                          const float *bias, float *out, hipStream_t s) {
+    const int halo = conv_halo_px(H, W);
+    if (cin != 32 || cout_pad < 16 || halo > kConvHaloMax || (long)B * H * W >= (1L << 31))
+        return hipErrorInvalidValue;
+    const int tiles = (H * W + kConvTile - 1) / kConvTile;
+    hipLaunchKernelGGL(k_head3x3, dim3((unsigned)(B * tiles)), dim3(256), (size_t)halo * 4 * sizeof(uint4), s, in,
+                       H, W, tiles, wt, cout_pad, bias, out);
+    return hipGetLastError();
+}
+
 bool conv_lds_fits(int B, int H, int W) {
     return conv_halo_px(H, W) <= kConvHaloMax && (long)B * H * W < (1L << 31);
 }
 
 hipError_t launch_conv3x3_in(const ConvIn &X, int B, int H, int W, int cin, const uint16_t *wt,
-                             const float *bias, void *out, int cout, bool relu, bool out_f32, hipStream_t s) {
-    if (cin % 16 || cout % 16 || X.ca % 16 || X.ca > cin || (X.ca < cin && !X.b) || (X.a_half && (H % 2 || W % 2)))
+                             const float *bias, void *out, int cout, int ostride, bool relu, bool out_f32,
+                             hipStream_t s) {
+    if (cin % 16 || cout % 16 || ostride < 1 || ostride > cout || X.ca % 16 || X.ca > cin || (X.ca < cin && !X.b) || (X.a_half && (H % 2 || W % 2)))
         return hipErrorInvalidValue;
     const int nbw = cout <= 32 ? 1 : (cout <= 64 ? 2 : 3);
     const int halo = conv_halo_px(H, W);
@@ -687,14 +786,14 @@ hipError_t launch_conv3x3_in(const ConvIn &X, int B, int H, int W, int cin, cons
     if (!conv_lds_fits(B, H, W)) {
         // wide images: the direct kernel, which needs the input in one tensor
         if (X.ca != cin || X.a_half) return hipErrorInvalidValue;
-        return launch_conv3x3(X.a, B, H, W, cin, wt, bias, out, cout, relu, out_f32, s);
+        return launch_conv3x3(X.a, B, H, W, cin, wt, bias, out, cout, ostride, relu, out_f32, s);
     }
     const int tiles = (H * W + kConvTile - 1) / kConvTile;
     dim3 grid((unsigned)(B * tiles), (unsigned)((cout + 32 * nbw - 1) / (32 * nbw)));
 #define FB_CONVL(NB)                                                                                            \
-    if (out_f32) hipLaunchKernelGGL((k_conv3x3_lds<NB, false, true>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, out, cout); \
-    else if (relu) hipLaunchKernelGGL((k_conv3x3_lds<NB, true, false>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, out, cout); \
-    else hipLaunchKernelGGL((k_conv3x3_lds<NB, false, false>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, out, cout);
+    if (out_f32) hipLaunchKernelGGL((k_conv3x3_lds<NB, false, true>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, out, cout, ostride); \
+    else if (relu) hipLaunchKernelGGL((k_conv3x3_lds<NB, true, false>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, out, cout, ostride); \
+    else hipLaunchKernelGGL((k_conv3x3_lds<NB, false, false>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, out, cout, ostride);
     switch (nbw) {
     case 1: FB_CONVL(1) break;
     case 2: FB_CONVL(2) break;
@@ -705,16 +804,17 @@ hipError_t launch_conv3x3_in(const ConvIn &X, int B, int H, int W, int cin, cons
 }
 
 hipError_t launch_conv3x3(const uint16_t *in, int B, int H, int W, int cin, const uint16_t *wt,
-                          const float *bias, void *out, int cout, bool relu, bool out_f32, hipStream_t s) {
+                          const float *bias, void *out, int cout, int ostride, bool relu, bool out_f32,
+                          hipStream_t s) {
     const long total = (long)B * H * W;
     // NB divides cout / 16 so every channel block of a launch is full
     const int blocks = cout / 16;
     const int nb = blocks % 4 == 0 ? 4 : (blocks % 3 == 0 ? 3 : (blocks % 2 == 0 ? 2 : 1));
     dim3 grid((unsigned)((total + 255) / 256), blocks / nb);
 #define FB_CONV(NB)                                                                                        \
-    if (out_f32) hipLaunchKernelGGL((k_conv3x3<NB, false, true>), grid, dim3(256), 0, s, in, B, H, W, cin, wt, bias, out, cout); \
-    else if (relu) hipLaunchKernelGGL((k_conv3x3<NB, true, false>), grid, dim3(256), 0, s, in, B, H, W, cin, wt, bias, out, cout); \
-    else hipLaunchKernelGGL((k_conv3x3<NB, false, false>), grid, dim3(256), 0, s, in, B, H, W, cin, wt, bias, out, cout);
+    if (out_f32) hipLaunchKernelGGL((k_conv3x3<NB, false, true>), grid, dim3(256), 0, s, in, B, H, W, cin, wt, bias, out, cout, ostride); \
+    else if (relu) hipLaunchKernelGGL((k_conv3x3<NB, true, false>), grid, dim3(256), 0, s, in, B, H, W, cin, wt, bias, out, cout, ostride); \
+    else hipLaunchKernelGGL((k_conv3x3<NB, false, false>), grid, dim3(256), 0, s, in, B, H, W, cin, wt, bias, out, cout, ostride);
     switch (nb) {
     case 1: FB_CONV(1) break;
     case 2: FB_CONV(2) break;

@@ -163,7 +163,7 @@ static hipError_t carve(UNet *u, int B, int H, int W, bool training, bool alloca
     size_t a_off[kNT], g_off[kNT] = {};
     for (int t = 0; t < kNT; ++t) a_off[t] = take(tensor_elems(t) * 2);
     const size_t px = (size_t)B * H * W;
-    const size_t pred_off = take(px * 16 * 4);
+    const size_t pred_off = take(px * 2 * 4);
     size_t part_off = 0, bpart_off = 0, lpart_off = 0, tot_off = 0;
     if (training) {
         for (int t = 0; t < kNT; ++t) g_off[t] = take(tensor_elems(t) * 2);
@@ -244,7 +244,14 @@ static hipError_t conv_fwd(UNet *u, int i, bool keep_cat, hipStream_t s) {
             FB_TRY(launch_upcat(u->act[deep], u->act[skip], u->B, H, W, kTCh[deep], kTCh[skip], u->act[kLIn[i]], s));
         }
     }
-    return launch_conv3x3_in(X, u->B, H, W, l.cin, u->w16 + u->w16_off[i], bias, out, l.cout, l.relu, kLOut[i] < 0, s);
+    if (kLOut[i] < 0) {  // the offset head: fp32 [px][2]
+        if (conv_lds_fits(u->B, H, W))
+            return launch_head3x3(X.a, u->B, H, W, l.cin, u->w16 + u->w16_off[i], l.cout, bias, u->pred, s);
+        return launch_conv3x3_in(X, u->B, H, W, l.cin, u->w16 + u->w16_off[i], bias, out, l.cout, l.cout_r, false,
+                                 true, s);
+    }
+    return launch_conv3x3_in(X, u->B, H, W, l.cin, u->w16 + u->w16_off[i], bias, out, l.cout, l.cout, l.relu, false,
+                             s);
 }
 
 hipError_t unet_forward(UNet *u, hipStream_t s, bool keep_cat) {
@@ -291,7 +298,7 @@ static hipError_t conv_dgrad(UNet *u, int i, const uint16_t *g, uint16_t *gin, h
     const LayerDef &l = kLayers[i];
     const int sh = kTShift[kLIn[i]];
     return launch_conv3x3_in(ConvIn{g, nullptr, l.cout, 0}, u->B, u->H >> sh, u->W >> sh, l.cout,
-                             u->wt16 + u->w16_off[i], nullptr, gin, l.cin, false, false, s);
+                             u->wt16 + u->w16_off[i], nullptr, gin, l.cin, l.cin, false, false, s);
 }
 
 static long elems(UNet *u, int t) { return (long)u->B * (u->H >> kTShift[t]) * (u->W >> kTShift[t]) * kTCh[t]; }
