@@ -452,7 +452,7 @@ fb_status drain_marks(fb_ctx *ctx) {
 
 bool valid_p(int p) { return p >= 1 && p <= kMaxP; }
 
-constexpr int kUNetChunk = 64;  // pairs per network launch sequence
+constexpr int kUNetChunk = 512;  // pairs per network launch sequence (about 9 MB of activations per pair at 128x128)
 
 // Learned proposal: the network predicts each pair's offset field at its
 // coarsest level from the two coarsest pyramid levels; the rounded offsets

@@ -158,13 +158,13 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) {
     return c.b;
 }
 
-template <int NBW, bool RELU, bool OUT_F32>
+template <int NBW, int HE, bool RELU>
 __global__ void __launch_bounds__(256)
 k_conv3x3_lds(ConvIn X, int H, int W, int cin, int tiles_per_img, const uint16_t *__restrict__ wt,
-              const float *__restrict__ bias, void *__restrict__ out, int cout, int ostride) {
+              const float *__restrict__ bias, uint16_t *__restrict__ out, int cout, int ostride) {
+    // HE: halo pixels staged per thread (the halo has at most 256 HE pixels)
     constexpr int NT = 32 * NBW;
     constexpr int WE = (9 * NT + 255) / 256;  // weight rows staged per thread
-    constexpr int HE = kConvHaloMax / 256;    // halo pixels staged per thread (at most)
     extern __shared__ uint4 lds[];
     uint4 *s_w = lds;               // [9][NT][2]: 16 channels of one weight row
     uint4 *s_in = lds + 9 * NT * 2; // [halo pixels][2]: 16 channels of one pixel
@@ -174,7 +174,7 @@ k_conv3x3_lds(ConvIn X, int H, int W, int cin, int tiles_per_img, const uint16_t
     const int p0 = (blockIdx.x - img * tiles_per_img) * kConvTile;
     const int p1 = min(p0 + kConvTile, HW);
     const int ya = p0 / W - 1;                           // first halo row
-    const int halo = ((p1 - 1) / W + 1 - ya + 1) * WP;  // <= kConvHaloMax (checked by the host)
+    const int halo = ((p1 - 1) / W + 1 - ya + 1) * WP;  // <= 256 HE (checked by the host)
     const int co0 = blockIdx.y * NT;
     const int half = lane >> 5;
     const int cb = cin - X.ca;
@@ -292,9 +292,7 @@ k_conv3x3_lds(ConvIn X, int H, int W, int cin, int tiles_per_img, const uint16_t
                 if (p >= p1) continue;
                 float v = acc[mb][nb][i] + bv;
                 if (RELU) v = fmaxf(v, 0.f);
-                const size_t o = ((size_t)img * HW + p) * ostride + co;
-                if (OUT_F32) reinterpret_cast<float *>(out)[o] = v;
-                else reinterpret_cast<uint16_t *>(out)[o] = f32_to_bf16(v);
+                out[((size_t)img * HW + p) * ostride + co] = f32_to_bf16(v);
             }
     }
 }
@@ -783,22 +781,26 @@ hipError_t launch_conv3x3_in(const ConvIn &X, int B, int H, int W, int cin, cons
     const int nbw = cout <= 32 ? 1 : (cout <= 64 ? 2 : 3);
     const int halo = conv_halo_px(H, W);
     const size_t lds = ((size_t)9 * 32 * nbw + halo) * 2 * sizeof(uint4);
-    if (!conv_lds_fits(B, H, W)) {
-        // wide images: the direct kernel, which needs the input in one tensor
+    if (!conv_lds_fits(B, H, W) || out_f32) {
+        // wide images (and fp32 output): the direct kernel, which needs the input in one tensor
         if (X.ca != cin || X.a_half) return hipErrorInvalidValue;
         return launch_conv3x3(X.a, B, H, W, cin, wt, bias, out, cout, ostride, relu, out_f32, s);
     }
     const int tiles = (H * W + kConvTile - 1) / kConvTile;
+    const int he = std::max(2, (halo + 255) / 256);
     dim3 grid((unsigned)(B * tiles), (unsigned)((cout + 32 * nbw - 1) / (32 * nbw)));
-#define FB_CONVL(NB)                                                                                            \
-    if (out_f32) hipLaunchKernelGGL((k_conv3x3_lds<NB, false, true>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, out, cout, ostride); \
-    else if (relu) hipLaunchKernelGGL((k_conv3x3_lds<NB, true, false>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, out, cout, ostride); \
-    else hipLaunchKernelGGL((k_conv3x3_lds<NB, false, false>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, out, cout, ostride);
+    uint16_t *o = static_cast<uint16_t *>(out);
+#define FB_CONVL(NB, HE)                                                                                        \
+    if (relu) hipLaunchKernelGGL((k_conv3x3_lds<NB, HE, true>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, o, cout, ostride); \
+    else hipLaunchKernelGGL((k_conv3x3_lds<NB, HE, false>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, o, cout, ostride);
+#define FB_CONVL_HE(NB) \
+    if (he == 2) { FB_CONVL(NB, 2) } else if (he == 3) { FB_CONVL(NB, 3) } else { FB_CONVL(NB, 4) }
     switch (nbw) {
-    case 1: FB_CONVL(1) break;
-    case 2: FB_CONVL(2) break;
-    default: FB_CONVL(3) break;
+    case 1: FB_CONVL_HE(1) break;
+    case 2: FB_CONVL_HE(2) break;
+    default: FB_CONVL_HE(3) break;
     }
+#undef FB_CONVL_HE
 #undef FB_CONVL
     return hipGetLastError();
 }
