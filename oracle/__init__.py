@@ -69,6 +69,17 @@ def lib():
         L.fbo_blend_window.restype = I
         L.fbo_interpolate.argtypes = [u8p, I, I, I, i32p, u8p, I, I, I, I, U64, f64p]
         L.fbo_interpolate.restype = I
+        L.fbo_remap_u8.argtypes = [u8p, i32p, I, I, I, u8p]
+        L.fbo_remap_u8.restype = None
+        L.fbo_style_loss.argtypes = [u8p, u8p, u8p, u8p, I, I, I, I, I, I, I, I]
+        L.fbo_style_loss.restype = U32
+        L.fbo_pm_iteration_style.argtypes = [u8p, u8p, u8p, I, I, I, I, I, I, U64, U32, i32p, i32p, u32p, u8p]
+        L.fbo_pm_iteration_style.restype = None
+        L.fbo_patchmatch_style.argtypes = [u8p, u8p, u8p, I, I, I, I, I, U64, U32, I, i32p, u32p,
+                                           ctypes.c_void_p]
+        L.fbo_patchmatch_style.restype = I
+        L.fbo_blend_window_style.argtypes = [u8p, u8p, I, I, I, I, I, I, I, U64, I, f64p]
+        L.fbo_blend_window_style.restype = I
         L.fbo_set_threads.argtypes = [I]
         L.fbo_set_threads.restype = None
         L.fbo_get_threads.argtypes = []
@@ -212,6 +223,62 @@ def blend_window(guides, styles, M: int, p: int, levels: int, iters: int, seed: 
     st = lib().fbo_blend_window(guides, styles, N, h, w, M, p, levels, iters, seed, out)
     if st != 0:
         raise RuntimeError("fbo_blend_window failed: %d" % st)
+    return out
+
+
+def remap_u8(style, F, p: int) -> np.ndarray:
+    """S^ of Eq. (3): the Alg. 2 remap of `style` through F as a uint8 image
+    (each channel's average rounded half up)."""
+    style = _img(style)
+    h, w = style.shape[:2]
+    out = np.zeros((h, w, 3), np.uint8)
+    lib().fbo_remap_u8(style, np.ascontiguousarray(F, np.int32), h, w, p, out)
+    return out
+
+
+def style_loss(Gs, Gt, Ss, Sh, p: int, alpha16: int, u, v) -> int:
+    """Eq. (3) for one match, scaled by 16: alpha16 SSD(G) + 16 SSD(S, S^)."""
+    Gs, Gt, Ss, Sh = _img(Gs), _img(Gt), _img(Ss), _img(Sh)
+    h, w = Gs.shape[:2]
+    return int(lib().fbo_style_loss(Gs, Gt, Ss, Sh, h, w, p, alpha16, int(u[0]), int(u[1]), int(v[0]), int(v[1])))
+
+
+def pm_iteration_style(Gs, Gt, Ss, p: int, alpha16: int, level: int, it: int, seed: int, pair_id: int, F):
+    """One iteration under the Eq. (3) loss; returns (F, E, S^ of its refresh)."""
+    Gs, Gt, Ss = _img(Gs), _img(Gt), _img(Ss)
+    h, w = Gs.shape[:2]
+    Fn = np.zeros((h, w, 2), np.int32)
+    En = np.zeros((h, w), np.uint32)
+    Sh = np.zeros((h, w, 3), np.uint8)
+    lib().fbo_pm_iteration_style(Gs, Gt, Ss, h, w, p, alpha16, level, it, seed, pair_id,
+                                 np.ascontiguousarray(F, np.int32), Fn, En, Sh)
+    return Fn, En, Sh
+
+
+def patchmatch_style(Gs, Gt, Ss, p: int, levels: int, iters: int, seed: int, pair_id: int, alpha16: int):
+    """NNF(G_j, G_i) under the Eq. (3) loss; returns level-0 F, E and the last S^."""
+    Gs, Gt, Ss = _img(Gs), _img(Gt), _img(Ss)
+    h, w = Gs.shape[:2]
+    F = np.zeros((h, w, 2), np.int32)
+    E = np.zeros((h, w), np.uint32)
+    Sh = np.zeros((h, w, 3), np.uint8)
+    st = lib().fbo_patchmatch_style(Gs, Gt, Ss, h, w, p, levels, iters, seed, pair_id, alpha16, F, E,
+                                    Sh.ctypes.data_as(ctypes.c_void_p))
+    if st != 0:
+        raise RuntimeError("fbo_patchmatch_style failed: %d" % st)
+    return F, E, Sh
+
+
+def blend_window_style(guides, styles, M: int, p: int, levels: int, iters: int, seed: int,
+                       alpha16: int) -> np.ndarray:
+    """Eq. (2) with every NNF under the Eq. (3) loss, fp64 [N][h][w][3]."""
+    guides = np.ascontiguousarray(guides, np.uint8)
+    styles = np.ascontiguousarray(styles, np.uint8)
+    N, h, w = guides.shape[:3]
+    out = np.zeros((N, h, w, 3), np.float64)
+    st = lib().fbo_blend_window_style(guides, styles, N, h, w, M, p, levels, iters, seed, alpha16, out)
+    if st != 0:
+        raise RuntimeError("fbo_blend_window_style failed: %d" % st)
     return out
 
 

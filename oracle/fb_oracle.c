@@ -30,6 +30,10 @@
  *                 average of Section 3.3).
  *   window ends   the blending window is truncated to [0, N-1] and divided by
  *                 its length; the j == i term is the style frame itself.
+ *   Eq. (3)       S^ is a uint8 image (the remap average rounded half up),
+ *                 alpha = alpha16 / 16, the loss is scaled by 16 to stay an
+ *                 integer; S^ is refreshed at the start of every iteration
+ *                 and the incumbent's loss recomputed under it.
  *
  * Images are uint8 [h][w][3] row-major; NNFs are int32 [h][w][2] (row, col);
  * energies are uint32 [h][w].  Floating-point outputs are fp64.
@@ -337,13 +341,163 @@ void fbo_remap(const uint8_t *style, const int32_t *F, int h, int w, int p, doub
 }
 
 /* ------------------------------------------------------------------------ */
-/* Sliding-window blending, Eq. (2), balanced mode with the guide-only loss: */
+/* Guide + style loss, Eq. (3) (Section 3.4, after Ebsynth).  For the pair   */
+/* (source frame j, target frame i) the loss of target patch v matched to    */
+/* source patch u is                                                        */
+/*     alpha ||G_j[u] - G_i[v]||^2 + ||S_j[u] - S^_i[v]||^2,                 */
+/* where S^_i is the source style S_j remapped through the current field     */
+/* (Alg. 2) and is refreshed once at the start of every iteration.          */
+/* Readings (the paper gives no precision for S^_i or alpha):               */
+/*   S^_i     a uint8 image: each channel of the Alg. 2 average rounded      */
+/*            half up, (2 sum + count) / (2 count) in integers;            */
+/*   alpha    fixed point, alpha = alpha16 / 16 with 0 <= alpha16 <= 512,   */
+/*            and the loss is scaled by 16 so that it stays an exact        */
+/*            integer: L = alpha16 SSD(G_j, G_i) + 16 SSD(S_j, S^_i).       */
+/* ------------------------------------------------------------------------ */
+
+/* S^ = Alg. 2 remap of `style` through F, as a uint8 image (rounded). */
+void fbo_remap_u8(const uint8_t *style, const int32_t *F, int h, int w, int p, uint8_t *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < h; ++r)
+        for (int c = 0; c < w; ++c) {
+            long sum[3] = { 0, 0, 0 };
+            long cnt = 0;
+            for (int dr = -p; dr <= p; ++dr)
+                for (int dc = -p; dc <= p; ++dc) {
+                    int qr = r + dr, qc = c + dc;
+                    if (qr < 0 || qr >= h || qc < 0 || qc >= w) continue;
+                    int sr = clampi(F[2 * (qr * w + qc)] - dr, 0, h - 1);
+                    int sc = clampi(F[2 * (qr * w + qc) + 1] - dc, 0, w - 1);
+                    for (int ch = 0; ch < 3; ++ch) sum[ch] += style[(sr * w + sc) * 3 + ch];
+                    ++cnt;
+                }
+            for (int ch = 0; ch < 3; ++ch)
+                out[(r * w + c) * 3 + ch] = (uint8_t)((2 * sum[ch] + cnt) / (2 * cnt));
+        }
+}
+
+/* Eq. (3) for one match, scaled by 16 (see above). */
+uint32_t fbo_style_loss(const uint8_t *Gs, const uint8_t *Gt, const uint8_t *Ss, const uint8_t *Sh,
+                        int h, int w, int p, int alpha16, int ur, int uc, int vr, int vc)
+{
+    return (uint32_t)alpha16 * fbo_patch_ssd(Gs, Gt, h, w, p, ur, uc, vr, vc) +
+           16u * fbo_patch_ssd(Ss, Sh, h, w, p, ur, uc, vr, vc);
+}
+
+/* One iteration under the Eq. (3) loss: S^ is refreshed from the previous   */
+/* field Fo (written to Sh), every incumbent's loss is recomputed under it,  */
+/* then each pixel tries the same candidate sequence as fbo_pm_iteration.    */
+void fbo_pm_iteration_style(const uint8_t *Gs, const uint8_t *Gt, const uint8_t *Ss, int h, int w,
+                            int p, int alpha16, int level, int iter, uint64_t seed, uint32_t pair_id,
+                            const int32_t *Fo, int32_t *Fn, uint32_t *En, uint8_t *Sh)
+{
+    static const int D[4][2] = { { -1, 0 }, { 1, 0 }, { 0, -1 }, { 0, 1 } };
+    const int R = maxi(h, w);
+    fbo_remap_u8(Ss, Fo, h, w, p, Sh);
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < h; ++r)
+        for (int c = 0; c < w; ++c) {
+            int br = Fo[2 * (r * w + c)], bc = Fo[2 * (r * w + c) + 1];
+            uint32_t be = fbo_style_loss(Gs, Gt, Ss, Sh, h, w, p, alpha16, br, bc, r, c);
+            for (int k = 0; k < 4; ++k) {
+                int qr = r + D[k][0], qc = c + D[k][1];
+                if (qr < 0 || qr >= h || qc < 0 || qc >= w) continue;
+                int cr = clampi(Fo[2 * (qr * w + qc)] - D[k][0], 0, h - 1);
+                int cc = clampi(Fo[2 * (qr * w + qc) + 1] - D[k][1], 0, w - 1);
+                uint32_t e = fbo_style_loss(Gs, Gt, Ss, Sh, h, w, p, alpha16, cr, cc, r, c);
+                if (e < be) { br = cr; bc = cc; be = e; }
+            }
+            uint32_t x[4] = { 0, 0, 0, 0 };
+            for (int m = 0; (R >> m) >= 1; ++m) {
+                int rho = R >> m;
+                if ((m & 3) == 0)
+                    draw_words(seed, (uint32_t)(r * w + c), pair_id, (uint32_t)level,
+                               (uint32_t)iter, (uint32_t)(m >> 2), x);
+                uint32_t word = x[m & 3];
+                int dr = (int)fbo_uniform16(word & 0xFFFFu, (uint32_t)(2 * rho + 1)) - rho;
+                int dc = (int)fbo_uniform16(word >> 16, (uint32_t)(2 * rho + 1)) - rho;
+                int cr = clampi(br + dr, 0, h - 1), cc = clampi(bc + dc, 0, w - 1);
+                uint32_t e = fbo_style_loss(Gs, Gt, Ss, Sh, h, w, p, alpha16, cr, cc, r, c);
+                if (e < be) { br = cr; bc = cc; be = e; }
+            }
+            Fn[2 * (r * w + c)] = br;
+            Fn[2 * (r * w + c) + 1] = bc;
+            En[r * w + c] = be;
+        }
+}
+
+/* NNF(G_j, G_i) under the Eq. (3) loss: Alg. 1 with guide and style         */
+/* pyramids (the same 2x2 filter), the same initialisation and upsampling,   */
+/* and `iters` >= 1 iterations of fbo_pm_iteration_style per level.  E is    */
+/* the loss under the S^ of the last refresh; Sh0 (optional) receives the    */
+/* last level-0 S^.                                                          */
+int fbo_patchmatch_style(const uint8_t *G0s, const uint8_t *G0t, const uint8_t *S0s, int h, int w,
+                         int p, int levels, int iters, uint64_t seed, uint32_t pair_id, int alpha16,
+                         int32_t *F, uint32_t *E, uint8_t *Sh0)
+{
+    if (levels < 1 || levels > 16 || h < 1 || w < 1 || p < 0 || iters < 1 || alpha16 < 0 || alpha16 > 512)
+        return FBO_E_INVALID;
+    int hs[16], ws[16];
+    const uint8_t *Gs[16], *Gt[16], *Ss[16];
+    uint8_t *own[48];
+    int n_own = 0;
+    hs[0] = h; ws[0] = w; Gs[0] = G0s; Gt[0] = G0t; Ss[0] = S0s;
+    for (int l = 1; l < levels; ++l) {
+        hs[l] = (hs[l - 1] + 1) / 2;
+        ws[l] = (ws[l - 1] + 1) / 2;
+        const uint8_t *prev[3] = { Gs[l - 1], Gt[l - 1], Ss[l - 1] };
+        uint8_t *next[3];
+        for (int k = 0; k < 3; ++k) {
+            next[k] = (uint8_t *)malloc((size_t)hs[l] * ws[l] * 3);
+            if (!next[k]) { for (int q = 0; q < k; ++q) free(next[q]); for (int i = 0; i < n_own; ++i) free(own[i]); return FBO_E_ALLOC; }
+            fbo_downsample(prev[k], hs[l - 1], ws[l - 1], next[k]);
+        }
+        for (int k = 0; k < 3; ++k) own[n_own++] = next[k];
+        Gs[l] = next[0]; Gt[l] = next[1]; Ss[l] = next[2];
+    }
+    size_t n0 = (size_t)h * w;
+    int32_t *Fa = (int32_t *)malloc(n0 * 2 * sizeof(int32_t));
+    int32_t *Fb = (int32_t *)malloc(n0 * 2 * sizeof(int32_t));
+    uint32_t *Ea = (uint32_t *)malloc(n0 * sizeof(uint32_t));
+    uint32_t *Eb = (uint32_t *)malloc(n0 * sizeof(uint32_t));
+    uint8_t *Sh = (uint8_t *)malloc(n0 * 3);
+    int status = FBO_OK;
+    if (!Fa || !Fb || !Ea || !Eb || !Sh) { status = FBO_E_ALLOC; goto done; }
+    for (int l = levels - 1; l >= 0; --l) {
+        int hl = hs[l], wl = ws[l];
+        /* the start of the level (its energies are recomputed by the first iteration) */
+        if (l == levels - 1) {
+            fbo_nnf_init_random(Gs[l], Gt[l], hl, wl, p, l, seed, pair_id, Fa, Ea);
+        } else {
+            fbo_nnf_upsample(Fa, hs[l + 1], ws[l + 1], Gs[l], Gt[l], hl, wl, p, Fb, Eb);
+            int32_t *tf = Fa; Fa = Fb; Fb = tf;
+            uint32_t *te = Ea; Ea = Eb; Eb = te;
+        }
+        for (int it = 0; it < iters; ++it) {
+            fbo_pm_iteration_style(Gs[l], Gt[l], Ss[l], hl, wl, p, alpha16, l, it, seed, pair_id, Fa, Fb, Eb, Sh);
+            int32_t *tf = Fa; Fa = Fb; Fb = tf;
+            uint32_t *te = Ea; Ea = Eb; Eb = te;
+        }
+    }
+    memcpy(F, Fa, n0 * 2 * sizeof(int32_t));
+    memcpy(E, Ea, n0 * sizeof(uint32_t));
+    if (Sh0) memcpy(Sh0, Sh, n0 * 3);
+done:
+    free(Fa); free(Fb); free(Ea); free(Eb); free(Sh);
+    for (int i = 0; i < n_own; ++i) free(own[i]);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sliding-window blending, Eq. (2), balanced mode with the guide-only loss  */
+/* (alpha16 < 0) or the Eq. (3) loss:                                        */
 /* out_i = mean over j in [max(0,i-M), min(N-1,i+M)] of (S_j -> S_i), where  */
 /* S_j -> S_i remaps style frame j with NNF(G_j, G_i) (pair id j*N + i) and  */
 /* the j == i term is S_i itself.  Sum in ascending j.                       */
 /* ------------------------------------------------------------------------ */
-int fbo_blend_window(const uint8_t *guides, const uint8_t *styles, int N, int h, int w, int M,
-                     int p, int levels, int iters, uint64_t seed, double *out)
+static int blend_window(const uint8_t *guides, const uint8_t *styles, int N, int h, int w, int M,
+                        int p, int levels, int iters, uint64_t seed, int alpha16, double *out)
 {
     size_t fpix = (size_t)h * w;
     int32_t *F = (int32_t *)malloc(fpix * 2 * sizeof(int32_t));
@@ -360,8 +514,13 @@ int fbo_blend_window(const uint8_t *guides, const uint8_t *styles, int N, int h,
                 for (size_t k = 0; k < fpix * 3; ++k) acc[k] += styles[(size_t)i * fpix * 3 + k] / 255.0;
                 continue;
             }
-            status = fbo_patchmatch(guides + (size_t)j * fpix * 3, guides + (size_t)i * fpix * 3,
-                                    h, w, p, levels, iters, seed, (uint32_t)(j * N + i), NULL, F, E);
+            if (alpha16 < 0)
+                status = fbo_patchmatch(guides + (size_t)j * fpix * 3, guides + (size_t)i * fpix * 3,
+                                        h, w, p, levels, iters, seed, (uint32_t)(j * N + i), NULL, F, E);
+            else
+                status = fbo_patchmatch_style(guides + (size_t)j * fpix * 3, guides + (size_t)i * fpix * 3,
+                                              styles + (size_t)j * fpix * 3, h, w, p, levels, iters, seed,
+                                              (uint32_t)(j * N + i), alpha16, F, E, NULL);
             if (status) goto done;
             fbo_remap(styles + (size_t)j * fpix * 3, F, h, w, p, tmp);
             for (size_t k = 0; k < fpix * 3; ++k) acc[k] += tmp[k];
@@ -371,6 +530,21 @@ int fbo_blend_window(const uint8_t *guides, const uint8_t *styles, int N, int h,
 done:
     free(F); free(E); free(tmp);
     return status;
+}
+
+int fbo_blend_window(const uint8_t *guides, const uint8_t *styles, int N, int h, int w, int M,
+                     int p, int levels, int iters, uint64_t seed, double *out)
+{
+    return blend_window(guides, styles, N, h, w, M, p, levels, iters, seed, -1, out);
+}
+
+/* Eq. (2) with every NNF(G_j, G_i) estimated under the Eq. (3) loss (the    */
+/* paper's balanced mode with its improved loss).                            */
+int fbo_blend_window_style(const uint8_t *guides, const uint8_t *styles, int N, int h, int w, int M,
+                           int p, int levels, int iters, uint64_t seed, int alpha16, double *out)
+{
+    if (alpha16 < 0) return FBO_E_INVALID;
+    return blend_window(guides, styles, N, h, w, M, p, levels, iters, seed, alpha16, out);
 }
 
 /* ------------------------------------------------------------------------ */
