@@ -16,6 +16,8 @@ Prints one JSON line:
              squared channel difference of Eq. 1) / summed HIP-event time of
              its launches in the timed region
   cpu_baseline  the CPU oracle on a bounded sample of the same pairs
+  learned    the same blend with the proposal network seeding PatchMatch
+  style_loss the same blend with every NNF under the guide + style loss (Eq. 3)
 """
 from __future__ import annotations
 
@@ -132,6 +134,47 @@ def bench_learned(ctx, fbm, g, s, out, M, p, levels, seed, wpath, args, pairs, N
                                                                    ("pairs", "steps", "val_loss", "train_seconds")}}
 
 
+def bench_style(ctx, fbm, g, s, out, M, p, levels, iters, seed, args, pairs, N, h, w):
+    """The same blend with every NNF estimated under the guide + style loss of
+    Eq. 3 (FB_STYLE_LOSS, alpha = 1): a refresh of the remapped style before
+    each iteration launch, and twice the byte-terms per candidate."""
+    import torch
+    sprm = fbm.make_params(p, levels, iters, seed, fbm.FB_STYLE_LOSS, 16)
+    for _ in range(max(args.warmup, 1)):
+        ctx.fb_blend_window(g, s, M, sprm, out=out)
+    torch.cuda.synchronize()
+    ctx.fb_profile_enable(True)
+    ctx.fb_profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.fb_blend_window(g, s, M, sprm, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    prof = ctx.fb_profile_read(reset=True)
+    ctx.fb_profile_enable(False)
+    log("style loss: %.2f ms/step" % ms)
+    pix, terms = pm_work(len(pairs), h, w, levels, iters, p)
+    terms *= 2  # guide and style patches
+    iter_ms = prof["pm_iter"][1] / args.steps
+    tf = terms / (iter_ms / 1e3) / 1e12 if iter_ms > 0 else 0.0
+    loss = None
+    if not args.no_energy:
+        pyrs = [ctx.fb_build_pyramid(g[f], levels, p) for f in range(N)]
+        spyrs = [ctx.fb_build_pyramid(s[f], levels, p) for f in range(N)]
+        descs = [dict(src_pyr=pyrs[j], tgt_pyr=pyrs[i], src_style_pyr=spyrs[j], h=h, w=w, levels=levels,
+                      pair_id=j * N + i) for (j, i) in pairs]
+        energies = [e for _, e in ctx.fb_patchmatch_batch(descs, sprm)]
+        loss = round(float(torch.stack(energies).double().mean().item()) / 16.0, 2)
+        del energies, pyrs, spyrs
+    return {"alpha": 1.0, "ms_per_step": round(ms, 3), "blended_frames_per_s": round(N / (ms / 1e3), 3),
+            "mpix_iter_per_s": round(pix / (ms / 1e3) / 1e6, 3),
+            "kernel_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in prof.items() if v[0]},
+            "iteration_roofline": {"bound": "alu", "kernel": "k_pm_iter (Eq. 3)", "achieved": round(tf, 3),
+                                   "peak": round(DOT4_PEAK_TOPS, 1), "unit": "TOP/s",
+                                   "frac": round(tf / DOT4_PEAK_TOPS, 4)},
+            "mean_level0_eq3_loss": loss}
+
+
 def iter_kernel_traffic():
     """HBM bytes per launch of the PatchMatch iteration kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
@@ -162,6 +205,7 @@ def main():
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2311_09265_amd", "weights", "proposal_unet.npz"),
                     help="trained proposal network; the learned comparison is skipped if absent")
     ap.add_argument("--learned-iters", type=int, default=2)
+    ap.add_argument("--no-style", action="store_true", help="skip the Eq. 3 (guide + style loss) comparison")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (counter calibration)")
     args = ap.parse_args()
@@ -233,6 +277,10 @@ def main():
         mean_energy = round(float(torch.stack(energies).double().mean().item()), 2)
         del energies, pyrs
 
+    style = None
+    if not args.no_style:
+        style = bench_style(ctx, fbm, g, s, out, M, p, levels, iters, seed, args, pairs, N, h, w)
+
     learned = None
     wpath = args.weights
     if wpath and os.path.exists(wpath):
@@ -288,6 +336,7 @@ def main():
                      "avg_launch_ms": round(iter_ms / max(n_iter, 1), 4), "launches": n_iter},
         "cpu_baseline": cpu,
         "learned": learned,
+        "style_loss": style,
     }
     if learned:
         learned["speedup_vs_plain"] = round(ms / learned["ms_per_step"], 3)

@@ -54,6 +54,17 @@ typedef enum {
 #define FB_USE_GRAPH   0x1u  /* replay the batched launch sequence as a HIP graph */
 #define FB_NO_AUTOTUNE 0x2u  /* use the default tile shape, skip the autotuner    */
 #define FB_LEARNED_SEED 0x4u /* seed the coarsest level with the proposal network */
+/* Guide + style loss, Eq. 3 (Section 3.4): alpha ||G_j[u] - G_i[v]||^2 +
+ * ||S_j[u] - S^_i[v]||^2, where S^_i is the source style S_j remapped (Alg. 2)
+ * through the current field, refreshed at the start of every iteration (the
+ * incumbent is re-scored under it).  S^_i is kept as a uint8 image (each
+ * channel's average rounded half up); alpha = alpha16 / 16 and the energies
+ * are the loss scaled by 16, alpha16 SSD(G) + 16 SSD(S, S^), exact in
+ * uint32.  Needs iters >= 1 and 0 <= alpha16 <= 512.  Taken by
+ * fb_blend_window (the styles are the sources' S_j) and fb_patchmatch_batch
+ * (each descriptor's src_style_pyr); the per-level calls and
+ * fb_interpolate return FB_E_UNSUPPORTED with it. */
+#define FB_STYLE_LOSS 0x8u
 
 /* PatchMatch parameters (Algorithm 1).  The paper names p, n and the pyramid
  * but gives no values; 2 / 3 / 6 are the values of the 512x512 blending
@@ -62,8 +73,10 @@ typedef struct {
     int32_t patch_radius;  /* p: patches are (2p+1) x (2p+1) x 3; 1 <= p <= 4  */
     int32_t levels;        /* pyramid levels K >= 1                            */
     int32_t iters;         /* iterations n per level, >= 0                     */
-    uint32_t flags;        /* FB_USE_GRAPH | FB_NO_AUTOTUNE                    */
+    uint32_t flags;        /* FB_USE_GRAPH | FB_NO_AUTOTUNE | FB_LEARNED_SEED | FB_STYLE_LOSS */
     uint64_t seed;         /* key of the Philox4x32-10 draws                   */
+    int32_t alpha16;       /* FB_STYLE_LOSS: guide weight alpha = alpha16 / 16 */
+    int32_t reserved;      /* must be 0                                        */
 } fb_params;
 
 typedef struct fb_ctx fb_ctx;
@@ -173,6 +186,9 @@ typedef struct {
     const int32_t *seed_offsets;  /* optional int32 offsets at level levels-1   */
     int32_t *nnf;                 /* out: int32 [h][w][2] level-0 field          */
     uint32_t *energy;             /* out: uint32 [h][w]                          */
+    const void *src_style_pyr;    /* FB_STYLE_LOSS: fb_build_pyramid of the      */
+                                  /* source's style frame S_j (same h, w, p,     */
+                                  /* >= levels levels); else ignored             */
 } fb_pair_desc;
 
 /* pairs (host) holds n_pairs descriptors; params->levels is ignored (each
@@ -196,6 +212,7 @@ enum {
     FB_KERNEL_REMAP = 4,     /* remap-sum (Alg. 2 + Eq. 2 / Eq. 9)            */
     FB_KERNEL_OTHER = 5,
     FB_KERNEL_UNET = 6,      /* proposal network forward for a group of pairs */
+    FB_KERNEL_STYLE = 7,     /* FB_STYLE_LOSS: refresh of the remapped styles  */
     FB_KERNEL_KINDS = 8
 };
 typedef struct {

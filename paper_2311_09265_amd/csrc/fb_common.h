@@ -63,6 +63,8 @@ struct PMJob {
     const uint32_t *e_abi;     // ABI energies (start mode 4)
     int32_t *nnf_abi;          // export destinations
     uint32_t *energy_abi;
+    const uint32_t *src_sty;   // Eq. 3 loss: padded pixels of the source style level
+    uint32_t *sty_hat;         // Eq. 3 loss: the remapped style S^, padded like the level
     int32_t h, w, pitch;       // level size; row pitch in pixels
     int32_t hc, wc;            // coarse size for upsampling
     uint32_t pair_id;
@@ -70,7 +72,8 @@ struct PMJob {
     int32_t mode;
     int32_t tile_base;         // first flat tile of this job in the launch
     int32_t tiles_x;           // tiles along w
-    int32_t pad_[2];
+    int32_t alpha16;           // Eq. 3 loss: guide weight alpha = alpha16 / 16
+    int32_t pad_;
 };
 static_assert(sizeof(PMJob) % 8 == 0, "PMJob is copied as an array");
 
@@ -107,8 +110,13 @@ hipError_t launch_downsample(const uint8_t *base, size_t stride, int n, const Le
 
 hipError_t launch_pm_start(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
                            TileCfg cfg, int p, uint64_t seed, hipStream_t s);
+// style: the Eq. 3 loss (guide + style against sty_hat), which re-scores the
+// incumbent instead of reading e_in
 hipError_t launch_pm_iter(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
-                          TileCfg cfg, int p, int iter, uint64_t seed, hipStream_t s);
+                          TileCfg cfg, int p, int iter, uint64_t seed, bool style, hipStream_t s);
+// S^ = Alg. 2 remap of src_sty through f_in, rounded, into sty_hat (border replicated)
+hipError_t launch_style_refresh(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
+                                TileCfg cfg, int p, hipStream_t s);
 hipError_t launch_pm_export(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
                             TileCfg cfg, hipStream_t s);
 

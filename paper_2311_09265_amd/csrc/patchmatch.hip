@@ -239,7 +239,12 @@ k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unif
     gstore<uint32_t>(J.e_out, 4u * v, patch_loss<P>(J.src_px, 4u * (uint32_t)(fr * J.pitch + fc), pitch_b, t));
 }
 
-template <int P, int TW, int TH>
+// STYLE: the guide + style loss of Eq. 3, scaled by 16 to stay an integer,
+//   alpha16 SSD(G_j[u], G_i[v]) + 16 SSD(S_j[u], S^[v]),
+// with S^ the remapped style of the current field (refreshed by
+// k_style_refresh before every iteration launch).  The incumbent is re-scored
+// under that S^ instead of taking e_in.
+template <int P, int TW, int TH, bool STYLE>
 __global__ void __launch_bounds__(TW *TH)
 k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles, int iter,
           uint32_t k0, uint32_t k1) {
@@ -253,12 +258,21 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     const uint32_t *src_px = J.src_px;
     constexpr int K = 2 * P + 1, S1 = TargetPatch<P>::S1;
 
-    TargetPatch<P> t;
+    TargetPatch<P> t, ts;  // ts: the patch of S^ (Eq. 3 loss only)
     load_target_patch<P>(J.tgt_px, 4u * (uint32_t)(r * pitch + c), pitch_b, t);
+    const uint32_t *src_sty = J.src_sty;
+    const uint32_t a16 = STYLE ? (uint32_t)J.alpha16 : 1u;
+    if constexpr (STYLE) load_target_patch<P>(J.sty_hat, 4u * (uint32_t)(r * pitch + c), pitch_b, ts);
 
     const uint32_t f0 = gload<uint32_t>(f_in, 4u * v);
     int br = (int)(f0 >> 16), bc = (int)(f0 & 0xFFFFu);
-    uint32_t be = gload<uint32_t>(J.e_in, 4u * v);
+    uint32_t be;
+    if constexpr (STYLE) {
+        const uint32_t off = 4u * (uint32_t)(br * pitch + bc);
+        be = a16 * patch_loss<P>(src_px, off, pitch_b, t) + 16u * patch_loss<P>(src_sty, off, pitch_b, ts);
+    } else {
+        be = gload<uint32_t>(J.e_in, 4u * v);
+    }
 
     // Every pixel's share of the loss is a square, so any part of the patch
     // whose loss alone reaches the running best rules the candidate out of
@@ -267,18 +281,40 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     // every complete row: a row is fetched only by lanes still in the race.
     // The sum of s^2 - 2 s t wraps in uint32, but with the t^2 sums added
     // back every partial loss is the exact nonnegative value.
+    // (Eq. 3: both terms are sums of squares, so the weighted partial sums
+    // are lower bounds in the same way; the weighted total stays below 2^32
+    // for alpha16 <= 512.)
     auto consider = [&](int cr, int cc) {
         if (cr == br && cc == bc) return;
         const uint32_t off = 4u * (uint32_t)(cr * pitch + cc);
-        uint32_t acc = seg_loss<P, 0, S1>(src_px, off, t, 0);
-        if (t.head_tt + acc >= be) return;
-        if constexpr (S1 < K) acc += seg_loss<P, S1, K - S1>(src_px, off + 4u * S1, t, 0);
+        uint32_t acc = seg_loss<P, 0, S1>(src_px, off, t, 0), accs = 0;
+        if constexpr (STYLE) {
+            accs = seg_loss<P, 0, S1>(src_sty, off, ts, 0);
+            if (a16 * (t.head_tt + acc) + 16u * (ts.head_tt + accs) >= be) return;
+        } else {
+            if (t.head_tt + acc >= be) return;
+        }
+        if constexpr (S1 < K) {
+            acc += seg_loss<P, S1, K - S1>(src_px, off + 4u * S1, t, 0);
+            if constexpr (STYLE) accs += seg_loss<P, S1, K - S1>(src_sty, off + 4u * S1, ts, 0);
+        }
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            if (i > 0) acc += seg_loss<P, 0, K>(src_px, off + (uint32_t)i * pitch_b, t, i);
-            if (i < K - 1 && t.cum_tt[i] + acc >= be) return;
+            if (i > 0) {
+                acc += seg_loss<P, 0, K>(src_px, off + (uint32_t)i * pitch_b, t, i);
+                if constexpr (STYLE) accs += seg_loss<P, 0, K>(src_sty, off + (uint32_t)i * pitch_b, ts, i);
+            }
+            if (i < K - 1) {
+                if constexpr (STYLE) {
+                    if (a16 * (t.cum_tt[i] + acc) + 16u * (ts.cum_tt[i] + accs) >= be) return;
+                } else {
+                    if (t.cum_tt[i] + acc >= be) return;
+                }
+            }
         }
-        const uint32_t e = t.cum_tt[K - 1] + acc;
+        uint32_t e;
+        if constexpr (STYLE) e = a16 * (t.cum_tt[K - 1] + acc) + 16u * (ts.cum_tt[K - 1] + accs);
+        else e = t.cum_tt[K - 1] + acc;
         if (e < be) { br = cr; bc = cc; be = e; }
     };
 
@@ -316,6 +352,54 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     }
     gstore<uint32_t>(J.f_out, 4u * v, ((uint32_t)br << 16) | (uint32_t)bc);
     gstore<uint32_t>(J.e_out, 4u * v, be);
+}
+
+// S^ of Eq. 3 for one iteration: the Alg. 2 remap of the source style level
+// through the field f_in, each channel's average rounded half up
+// ((2 sum + count) / (2 count)), as (R,G,B,0) pixels written into the padded
+// sty_hat together with its replicated border, so the loss never clamps.
+// The tile's field entries with a P-pixel border are staged in LDS once.
+template <int P, int TW, int TH>
+__global__ void __launch_bounds__(TW *TH)
+k_style_refresh(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles) {
+    constexpr int SW = TW + 2 * P, SH = TH + 2 * P;
+    __shared__ uint32_t sf[SH * SW];
+    const TileCoord tc = locate<TW, TH>(jobs, n_jobs, total_tiles, uniform_tiles);
+    const PMJob &J = jobs[tc.job];
+    const int h = J.h, w = J.w, pitch = J.pitch, r = tc.r, c = tc.c;
+    const int rt = r - (int)threadIdx.y, ct = c - (int)threadIdx.x;  // tile origin
+    for (int i = (int)(threadIdx.y * TW + threadIdx.x); i < SH * SW; i += TW * TH) {
+        const int yy = rt - P + i / SW, xx = ct - P + i % SW;
+        sf[i] = (yy >= 0 && yy < h && xx >= 0 && xx < w) ? gload<uint32_t>(J.f_in, 4u * (uint32_t)(yy * w + xx)) : 0u;
+    }
+    __syncthreads();
+    if (!tc.active) return;
+    uint32_t rb = 0, g = 0, cnt = 0;  // R and B sums in 16-bit halves; G alone
+#pragma unroll
+    for (int dr = -P; dr <= P; ++dr) {
+        if (r + dr < 0 || r + dr >= h) continue;
+#pragma unroll
+        for (int dc = -P; dc <= P; ++dc) {
+            if (c + dc < 0 || c + dc >= w) continue;
+            const uint32_t q = sf[((int)threadIdx.y + P + dr) * SW + (int)threadIdx.x + P + dc];
+            // source pixel clamp(F(v + d) - d), read from the padded style level
+            const int sr = (int)(q >> 16) - dr + P, sc = (int)(q & 0xFFFFu) - dc + P;
+            const uint32_t px = gload<uint32_t>(J.src_sty, 4u * (uint32_t)(sr * pitch + sc));
+            rb += px & 0x00FF00FFu;
+            g += (px >> 8) & 0xFFu;
+            ++cnt;
+        }
+    }
+    const uint32_t vr = (2u * (rb & 0xFFFFu) + cnt) / (2u * cnt);
+    const uint32_t vg = (2u * g + cnt) / (2u * cnt);
+    const uint32_t vb = (2u * (rb >> 16) + cnt) / (2u * cnt);
+    const uint32_t px = vr | (vg << 8) | (vb << 16);
+    // this pixel, and the border copies it stands for at the image edges
+    const int r0 = r == 0 ? -P : 0, r1 = r == h - 1 ? P : 0;
+    const int c0 = c == 0 ? -P : 0, c1 = c == w - 1 ? P : 0;
+    for (int a = r0; a <= r1; ++a)
+        for (int b = c0; b <= c1; ++b)
+            gstore<uint32_t>(J.sty_hat, 4u * (uint32_t)((r + P + a) * pitch + (c + P + b)), px);
 }
 
 template <int TW, int TH>
@@ -378,16 +462,31 @@ hipError_t launch_pm_start(const PMJob *jobs, int n_jobs, int total_tiles, int u
 }
 
 hipError_t launch_pm_iter(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
-                          TileCfg cfg, int p, int iter, uint64_t seed, hipStream_t s) {
+                          TileCfg cfg, int p, int iter, uint64_t seed, bool style, hipStream_t s) {
     if (total_tiles <= 0) return hipSuccess;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-#define FB_ITER2(P_, TW, TH)                                                                  \
-    hipLaunchKernelGGL((k_pm_iter<P_, TW, TH>), dim3(total_tiles), dim3(TW, TH), 0, s, jobs,  \
-                       n_jobs, total_tiles, uniform_tiles, iter, k0, k1)
+#define FB_ITER2(P_, TW, TH)                                                                           \
+    if (style) hipLaunchKernelGGL((k_pm_iter<P_, TW, TH, true>), dim3(total_tiles), dim3(TW, TH), 0, s, \
+                                  jobs, n_jobs, total_tiles, uniform_tiles, iter, k0, k1);             \
+    else hipLaunchKernelGGL((k_pm_iter<P_, TW, TH, false>), dim3(total_tiles), dim3(TW, TH), 0, s,     \
+                            jobs, n_jobs, total_tiles, uniform_tiles, iter, k0, k1)
 #define FB_ITER(TW, TH) FB_P_SWITCH(p, FB_ITER2, TW, TH)
     FB_TILE_SWITCH(cfg, FB_ITER)
 #undef FB_ITER
 #undef FB_ITER2
+    return hipGetLastError();
+}
+
+hipError_t launch_style_refresh(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
+                                TileCfg cfg, int p, hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+#define FB_REFRESH2(P_, TW, TH)                                                                      \
+    hipLaunchKernelGGL((k_style_refresh<P_, TW, TH>), dim3(total_tiles), dim3(TW, TH), 0, s, jobs, \
+                       n_jobs, total_tiles, uniform_tiles)
+#define FB_REFRESH(TW, TH) FB_P_SWITCH(p, FB_REFRESH2, TW, TH)
+    FB_TILE_SWITCH(cfg, FB_REFRESH)
+#undef FB_REFRESH
+#undef FB_REFRESH2
     return hipGetLastError();
 }
 

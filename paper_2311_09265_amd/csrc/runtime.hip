@@ -59,6 +59,7 @@ struct Plan {
     bool has_tune = false;
     std::vector<PMJob> tune_jobs;
     int tune_iter = 0;
+    bool tune_style = false;
     std::string tune_key;
 };
 
@@ -91,7 +92,7 @@ void assign_tiles(std::vector<PMJob> &jobs, TileCfg cfg, int *total, int *unifor
     *uniform = uni > 0 ? uni : 0;
 }
 
-enum LaunchKind { kLaunchStart, kLaunchIter, kLaunchExport };
+enum LaunchKind { kLaunchStart, kLaunchIter, kLaunchStyleIter, kLaunchStyleRefresh, kLaunchExport };
 
 void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cfg, int p,
                    uint64_t seed, int iter) {
@@ -101,6 +102,7 @@ void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cf
     const size_t off = table_append(P, jobs.data(), jobs.size());
     const int n = (int)jobs.size();
     sig_add(P, "pm", kind, (long long)off, n, ((long long)iter << 32) | (cfg.tw << 8) | cfg.th);
+    const bool style = kind == kLaunchStyleIter;
     switch (kind) {
     case kLaunchStart:
         P.ops.push_back({FB_KERNEL_PM_START, [=](hipStream_t s, const uint8_t *tab) {
@@ -109,9 +111,16 @@ void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cf
         }});
         break;
     case kLaunchIter:
+    case kLaunchStyleIter:
         P.ops.push_back({FB_KERNEL_PM_ITER, [=](hipStream_t s, const uint8_t *tab) {
             return launch_pm_iter(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform,
-                                  cfg, p, iter, seed, s);
+                                  cfg, p, iter, seed, style, s);
+        }});
+        break;
+    case kLaunchStyleRefresh:
+        P.ops.push_back({FB_KERNEL_STYLE, [=](hipStream_t s, const uint8_t *tab) {
+            return launch_style_refresh(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform,
+                                        cfg, p, s);
         }});
         break;
     case kLaunchExport:
@@ -158,6 +167,8 @@ struct PairSpec {
     uint32_t *f[2], *e[2];     // ping-pong buffers (level-0 capacity)
     int32_t *nnf_abi;          // optional export of the final field
     uint32_t *energy_abi;
+    const uint8_t *src_sty_pyr;  // Eq. 3 loss: pyramid of the source style frame
+    uint32_t *sty_hat;         // Eq. 3 loss: padded S^ buffer (level-0 capacity)
     int final_buf;             // filled by the planner
 };
 
@@ -172,6 +183,10 @@ PMJob job_geom(const PairSpec &ps, int l) {
     j.pitch = g.pitch;
     j.pair_id = ps.pair_id;
     j.level = l;
+    if (ps.src_sty_pyr) {
+        j.src_sty = reinterpret_cast<const uint32_t *>(ps.src_sty_pyr + g.px_off);
+        j.sty_hat = ps.sty_hat;
+    }
     return j;
 }
 
@@ -196,9 +211,11 @@ std::string tune_key_of(const std::vector<PairSpec> &pairs, int p) {
 
 // The whole coarse-to-fine PatchMatch of every pair (Algorithm 1), grouped by
 // level: a pair with K levels joins at pass Kmax - K, so at every pass all
-// active pairs sit at the same level number.
+// active pairs sit at the same level number.  With the Eq. 3 loss (style),
+// every iteration launch is preceded by the refresh of the pairs' S^ from the
+// field the iteration starts from.
 void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, uint64_t seed,
-                     TileCfg cfg) {
+                     TileCfg cfg, bool style = false, int alpha16 = 0) {
     int kmax = 0;
     for (const PairSpec &ps : pairs) kmax = std::max(kmax, ps.L.levels);
     std::vector<int> cur(pairs.size(), 0);
@@ -231,6 +248,15 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
         }
         add_pm_launch(P, kLaunchStart, js, cfg, p, seed, 0);
         for (int it = 0; it < iters; ++it) {
+            if (style) {
+                js.clear();
+                for (size_t k : active) {
+                    PMJob j = job_geom(pairs[k], l);
+                    j.f_in = pairs[k].f[cur[k]];
+                    js.push_back(j);
+                }
+                add_pm_launch(P, kLaunchStyleRefresh, js, cfg, p, seed, it);
+            }
             js.clear();
             for (size_t k : active) {
                 PairSpec &ps = pairs[k];
@@ -239,6 +265,7 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
                 j.e_in = ps.e[cur[k]];
                 j.f_out = ps.f[cur[k] ^ 1];
                 j.e_out = ps.e[cur[k] ^ 1];
+                j.alpha16 = alpha16;
                 cur[k] ^= 1;
                 js.push_back(j);
             }
@@ -246,8 +273,9 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
                 P.has_tune = true;
                 P.tune_jobs = js;
                 P.tune_iter = it;
+                P.tune_style = style;
             }
-            add_pm_launch(P, kLaunchIter, js, cfg, p, seed, it);
+            add_pm_launch(P, style ? kLaunchStyleIter : kLaunchIter, js, cfg, p, seed, it);
         }
     }
     std::vector<PMJob> ex;
@@ -284,7 +312,7 @@ struct fb_ctx {
     Buf table;
     std::vector<uint8_t> table_host;  // bytes currently in `table`
     uint64_t table_gen = 0;
-    Buf pyr, style, fe, tune_table;
+    Buf pyr, style, fe, tune_table, shat;
     std::map<std::string, int> tuned;
     int forced_cfg = -1;
     std::string graph_sig;
@@ -349,10 +377,13 @@ fb_status autotune(fb_ctx *ctx, Plan &P, hipStream_t s, int p, uint64_t seed) {
         FB_HIP(hipMemcpy(ctx->tune_table.p, jobs.data(), jobs.size() * sizeof(PMJob),
                          hipMemcpyHostToDevice));
         const PMJob *dj = reinterpret_cast<const PMJob *>(ctx->tune_table.p);
-        FB_HIP(launch_pm_iter(dj, (int)jobs.size(), total, uniform, tile_cfg(c), p, P.tune_iter, seed, s));
+        // reruns of the last iteration read what it read and write what it wrote
+        FB_HIP(launch_pm_iter(dj, (int)jobs.size(), total, uniform, tile_cfg(c), p, P.tune_iter, seed,
+                              P.tune_style, s));
         FB_HIP(hipEventRecord(e0, s));
         for (int rep = 0; rep < 3; ++rep)
-            FB_HIP(launch_pm_iter(dj, (int)jobs.size(), total, uniform, tile_cfg(c), p, P.tune_iter, seed, s));
+            FB_HIP(launch_pm_iter(dj, (int)jobs.size(), total, uniform, tile_cfg(c), p, P.tune_iter, seed,
+                                  P.tune_style, s));
         FB_HIP(hipEventRecord(e1, s));
         FB_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -541,6 +572,11 @@ fb_status check_params(const fb_params *prm, bool need_levels) {
     if (need_levels && (prm->levels < 1 || prm->levels > kMaxLevels))
         return fail(FB_E_INVALID, "levels must be in [1, 16]");
     if (prm->iters < 0 || prm->iters > 0xFFFE) return fail(FB_E_INVALID, "iters must be in [0, 65534]");
+    if (prm->reserved != 0) return fail(FB_E_INVALID, "params->reserved must be 0");
+    if (prm->flags & FB_STYLE_LOSS) {
+        if (prm->iters < 1) return fail(FB_E_INVALID, "FB_STYLE_LOSS needs iters >= 1");
+        if (prm->alpha16 < 0 || prm->alpha16 > 512) return fail(FB_E_INVALID, "alpha16 must be in [0, 512]");
+    }
     return FB_OK;
 }
 
@@ -655,6 +691,8 @@ fb_status fb_nnf_init(fb_ctx *ctx, const void *src_pyr, const void *tgt_pyr, int
     if (st) return st;
     if (!src_pyr || !tgt_pyr || !nnf || !energy) return fail(FB_E_INVALID, "null pointer");
     if ((st = check_size(h, w)) || (st = check_params(params, false))) return st;
+    if (params->flags & FB_STYLE_LOSS)
+        return fail(FB_E_UNSUPPORTED, "FB_STYLE_LOSS is taken by fb_blend_window and fb_patchmatch_batch only");
     if (level < 0 || level >= kMaxLevels) return fail(FB_E_INVALID, "level must be in [0, 15]");
     const int p = params->patch_radius;
     const PyrLayout L = pyr_layout(h, w, level + 1, p);
@@ -691,6 +729,8 @@ fb_status fb_patchmatch_level(fb_ctx *ctx, const void *src_pyr, const void *tgt_
     if (st) return st;
     if (!src_pyr || !tgt_pyr || !nnf || !energy) return fail(FB_E_INVALID, "null pointer");
     if ((st = check_size(h, w)) || (st = check_params(params, false))) return st;
+    if (params->flags & FB_STYLE_LOSS)
+        return fail(FB_E_UNSUPPORTED, "FB_STYLE_LOSS is taken by fb_blend_window and fb_patchmatch_batch only");
     if (level < 0 || level >= kMaxLevels - 1) return fail(FB_E_INVALID, "level must be in [0, 14]");
     const int p = params->patch_radius;
     const PyrLayout L = pyr_layout(h, w, level + 2, p);  // level + 1 for the coarse size only
@@ -780,21 +820,28 @@ fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *sty
     if ((uint64_t)N * (uint64_t)N > 0xFFFFFFFFull) return fail(FB_E_UNSUPPORTED, "pair ids j*N+i must fit in 32 bits");
     const PyrLayout L = pyr_layout(h, w, K, p);
     int32_t pitch = 0;
-    const size_t sbytes = padded_image_bytes(h, w, p, &pitch);
+    const size_t pbytes = padded_image_bytes(h, w, p, &pitch);
+    // with the Eq. 3 loss the styles get whole pyramids (level 0 of a pyramid
+    // is laid out as a padded frame)
+    const bool style = params->flags & FB_STYLE_LOSS;
+    const size_t sbytes = style ? L.bytes : pbytes;
     const size_t npx = (size_t)h * w;
     size_t n_pairs = 0;
     for (int i = 0; i < N; ++i) n_pairs += (size_t)(std::min(N - 1, i + M) - std::max(0, i - M));
     if ((st = ensure(ctx, ctx->pyr, (size_t)N * L.bytes)) ||
         (st = ensure(ctx, ctx->style, (size_t)N * sbytes)) ||
-        (st = ensure(ctx, ctx->fe, std::max<size_t>(n_pairs, 1) * npx * 16)))
+        (st = ensure(ctx, ctx->fe, std::max<size_t>(n_pairs, 1) * npx * 16)) ||
+        (style && (st = ensure(ctx, ctx->shat, std::max<size_t>(n_pairs, 1) * pbytes))))
         return st;
     uint8_t *pyr = static_cast<uint8_t *>(ctx->pyr.p);
     uint8_t *sty = static_cast<uint8_t *>(ctx->style.p);
     uint32_t *fe = static_cast<uint32_t *>(ctx->fe.p);
+    uint8_t *shat = static_cast<uint8_t *>(ctx->shat.p);
 
     Plan P;
     plan_pyramids(P, guides, N, h, w, L, pyr, L.bytes);
-    plan_style_pack(P, styles, N, h, w, p, sty, sbytes, pitch);
+    if (style) plan_pyramids(P, styles, N, h, w, L, sty, L.bytes);
+    else plan_style_pack(P, styles, N, h, w, p, sty, sbytes, pitch);
     std::vector<PairSpec> pairs;
     pairs.reserve(n_pairs);
     for (int i = 0; i < N; ++i)
@@ -810,12 +857,16 @@ fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *sty
             ps.f[1] = fe + (n_pairs + k) * npx;
             ps.e[0] = fe + (2 * n_pairs + k) * npx;
             ps.e[1] = fe + (3 * n_pairs + k) * npx;
+            if (style) {
+                ps.src_sty_pyr = sty + (size_t)j * sbytes;
+                ps.sty_hat = reinterpret_cast<uint32_t *>(shat + k * pbytes);
+            }
             pairs.push_back(ps);
         }
     if (params->flags & FB_LEARNED_SEED)
         if ((st = plan_learned_seeds(ctx, P, pairs))) return st;
     const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
-    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg);
+    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg, style, params->alpha16);
 
     std::vector<RemapTerm> terms;
     std::vector<RemapFrame> frames;
@@ -846,6 +897,8 @@ fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, i
     if (st) return st;
     if (!guides || !key_idx || !key_styles || !out) return fail(FB_E_INVALID, "null pointer");
     if ((st = check_size(h, w)) || (st = check_params(params, true))) return st;
+    if (params->flags & FB_STYLE_LOSS)
+        return fail(FB_E_UNSUPPORTED, "FB_STYLE_LOSS is taken by fb_blend_window and fb_patchmatch_batch only");
     if (n_frames < 1 || n_keys < 1) return fail(FB_E_INVALID, "need n_frames >= 1 and n_keys >= 1");
     for (int k = 0; k < n_keys; ++k) {
         if (key_idx[k] < 0 || key_idx[k] >= n_frames) return fail(FB_E_INVALID, "key index out of range");
@@ -940,16 +993,22 @@ fb_status fb_patchmatch_batch(fb_ctx *ctx, const fb_pair_desc *pairs_in, int32_t
     if (!pairs_in || n_pairs < 1) return fail(FB_E_INVALID, "need n_pairs >= 1 descriptors");
     if ((st = check_params(params, false))) return st;
     const int p = params->patch_radius;
-    size_t total_px = 0;
+    const bool style = params->flags & FB_STYLE_LOSS;
+    size_t total_px = 0, shat_bytes = 0;
     for (int k = 0; k < n_pairs; ++k) {
         const fb_pair_desc &d = pairs_in[k];
         if (!d.src_pyr || !d.tgt_pyr || !d.nnf || !d.energy) return fail(FB_E_INVALID, "null pointer in pair descriptor");
         if ((st = check_size(d.h, d.w))) return st;
         if (d.levels < 1 || d.levels > kMaxLevels) return fail(FB_E_INVALID, "levels must be in [1, 16]");
+        if (style && !d.src_style_pyr) return fail(FB_E_INVALID, "FB_STYLE_LOSS needs src_style_pyr in every descriptor");
         total_px += (size_t)d.h * d.w;
+        if (style) shat_bytes += padded_image_bytes(d.h, d.w, p, nullptr);
     }
-    if ((st = ensure(ctx, ctx->fe, total_px * 16))) return st;
+    if ((st = ensure(ctx, ctx->fe, total_px * 16)) || (style && (st = ensure(ctx, ctx->shat, shat_bytes))))
+        return st;
     uint32_t *fe = static_cast<uint32_t *>(ctx->fe.p);
+    uint8_t *shat = static_cast<uint8_t *>(ctx->shat.p);
+    size_t shat_off = 0;
     std::vector<PairSpec> pairs;
     size_t off = 0;
     for (int k = 0; k < n_pairs; ++k) {
@@ -966,6 +1025,11 @@ fb_status fb_patchmatch_batch(fb_ctx *ctx, const fb_pair_desc *pairs_in, int32_t
         ps.e[1] = fe + 3 * total_px + off;
         ps.nnf_abi = d.nnf;
         ps.energy_abi = d.energy;
+        if (style) {
+            ps.src_sty_pyr = static_cast<const uint8_t *>(d.src_style_pyr);
+            ps.sty_hat = reinterpret_cast<uint32_t *>(shat + shat_off);
+            shat_off += padded_image_bytes(d.h, d.w, p, nullptr);
+        }
         off += (size_t)d.h * d.w;
         pairs.push_back(ps);
     }
@@ -973,7 +1037,7 @@ fb_status fb_patchmatch_batch(fb_ctx *ctx, const fb_pair_desc *pairs_in, int32_t
     if (params->flags & FB_LEARNED_SEED)
         if ((st = plan_learned_seeds(ctx, P, pairs))) return st;
     const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
-    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg);
+    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg, style, params->alpha16);
     return run_plan(ctx, P, params->flags, static_cast<hipStream_t>(stream), p, params->seed);
 }
 

@@ -23,6 +23,7 @@ FB_OK = 0
 FB_USE_GRAPH = 0x1
 FB_NO_AUTOTUNE = 0x2
 FB_LEARNED_SEED = 0x4
+FB_STYLE_LOSS = 0x8
 STATUS = {0: "FB_OK", -1: "FB_E_INVALID", -2: "FB_E_SHAPE", -3: "FB_E_UNSUPPORTED",
           -4: "FB_E_ALLOC", -5: "FB_E_HIP"}
 
@@ -35,17 +36,19 @@ class FastBlendError(RuntimeError):
 
 class fb_params(ctypes.Structure):
     _fields_ = [("patch_radius", ctypes.c_int32), ("levels", ctypes.c_int32),
-                ("iters", ctypes.c_int32), ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+                ("iters", ctypes.c_int32), ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+                ("alpha16", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class fb_pair_desc(ctypes.Structure):
     _fields_ = [("src_pyr", ctypes.c_void_p), ("tgt_pyr", ctypes.c_void_p),
                 ("h", ctypes.c_int32), ("w", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("pair_id", ctypes.c_uint32), ("seed_offsets", ctypes.c_void_p),
-                ("nnf", ctypes.c_void_p), ("energy", ctypes.c_void_p)]
+                ("nnf", ctypes.c_void_p), ("energy", ctypes.c_void_p),
+                ("src_style_pyr", ctypes.c_void_p)]
 
 
-KERNEL_KINDS = ["pyramid", "pm_start", "pm_iter", "pm_export", "remap", "other", "unet"]
+KERNEL_KINDS = ["pyramid", "pm_start", "pm_iter", "pm_export", "remap", "other", "unet", "style"]
 
 
 class fb_profile(ctypes.Structure):
@@ -135,8 +138,9 @@ def _check_pyr(pyr: torch.Tensor, name: str, h: int, w: int, levels: int, patch_
 
 
 def make_params(patch_radius: int = 2, levels: int = 3, iters: int = 6, seed: int = 0,
-                flags: int = 0) -> fb_params:
-    return fb_params(patch_radius, levels, iters, flags, seed & 0xFFFFFFFFFFFFFFFF)
+                flags: int = 0, alpha16: int = 16) -> fb_params:
+    """alpha16: the guide weight of the Eq. 3 loss (FB_STYLE_LOSS), alpha = alpha16 / 16."""
+    return fb_params(patch_radius, levels, iters, flags, seed & 0xFFFFFFFFFFFFFFFF, alpha16, 0)
 
 
 def level_size(h: int, w: int, level: int):
@@ -323,7 +327,8 @@ class Context:
         return out
 
     def fb_patchmatch_batch(self, pairs: Sequence[dict], params: fb_params):
-        """pairs: dicts with src_pyr, tgt_pyr, h, w, levels, pair_id[, seed_offsets].
+        """pairs: dicts with src_pyr, tgt_pyr, h, w, levels, pair_id[, seed_offsets]
+        [, src_style_pyr (FB_STYLE_LOSS)].
         Returns a list of (nnf int32 [h][w][2], energy int32 [h][w])."""
         descs = (fb_pair_desc * len(pairs))()
         outs, keep = [], []
@@ -335,11 +340,15 @@ class Context:
             nnf = torch.empty((h, w, 2), dtype=torch.int32, device=dev)
             energy = torch.empty((h, w), dtype=torch.int32, device=dev)
             so = d.get("seed_offsets")
+            ss = d.get("src_style_pyr")
+            if ss is not None:
+                _check_pyr(ss, "src_style_pyr", h, w, d["levels"], params.patch_radius)
             hc, wc = level_size(h, w, d["levels"] - 1)
             descs[k] = fb_pair_desc(_dev(d["src_pyr"], "src_pyr", torch.uint8),
                                     _dev(d["tgt_pyr"], "tgt_pyr", torch.uint8), h, w, d["levels"],
                                     d["pair_id"], _dev(so, "seed_offsets", torch.int32, (hc, wc, 2)),
-                                    _dev(nnf, "nnf"), _dev(energy, "energy"))
+                                    _dev(nnf, "nnf"), _dev(energy, "energy"),
+                                    _dev(ss, "src_style_pyr", torch.uint8))
             outs.append((nnf, energy))
             keep.append(so)
         _check(load_library().fb_patchmatch_batch(self.handle, descs, len(pairs), ctypes.byref(params),

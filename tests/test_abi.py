@@ -65,3 +65,30 @@ def test_null_context_is_rejected_without_gpu(lib):
     assert b"ctx" in lib.fb_last_error()
     assert lib.fb_num_tile_configs() >= 2
     assert lib.fb_set_tile_config(None, 0) == -1
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Field offsets and sizes of the ctypes structs equal the C header's
+    (compiled with gcc here), so the binding cannot drift from the ABI."""
+    import shutil
+    import subprocess
+    from paper_2311_09265_amd import fastblend
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"fb_params": fastblend.fb_params, "fb_pair_desc": fastblend.fb_pair_desc,
+               "fb_profile": fastblend.fb_profile}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "fastblend.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (name, name))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (name, f, name, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(got["%s.%s" % (name, f)]) == getattr(cls, f).offset, (name, f)
