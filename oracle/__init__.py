@@ -80,6 +80,10 @@ def lib():
         L.fbo_patchmatch_style.restype = I
         L.fbo_blend_window_style.argtypes = [u8p, u8p, I, I, I, I, I, I, I, U64, I, f64p]
         L.fbo_blend_window_style.restype = I
+        L.fbo_remap_f64.argtypes = [f64p, i32p, I, I, I, f64p]
+        L.fbo_remap_f64.restype = None
+        L.fbo_blend_window_fast.argtypes = [u8p, u8p, I, I, I, I, I, I, I, U64, I, f64p]
+        L.fbo_blend_window_fast.restype = I
         L.fbo_set_threads.argtypes = [I]
         L.fbo_set_threads.restype = None
         L.fbo_get_threads.argtypes = []
@@ -279,6 +283,29 @@ def blend_window_style(guides, styles, M: int, p: int, levels: int, iters: int, 
     st = lib().fbo_blend_window_style(guides, styles, N, h, w, M, p, levels, iters, seed, alpha16, out)
     if st != 0:
         raise RuntimeError("fbo_blend_window_style failed: %d" % st)
+    return out
+
+
+def remap_f64(X, F, p: int) -> np.ndarray:
+    """Alg. 2 on a floating-point image X [h][w][3] (fast mode, Eq. 4-5)."""
+    X = np.ascontiguousarray(X, np.float64)
+    h, w = X.shape[:2]
+    out = np.zeros((h, w, 3), np.float64)
+    lib().fbo_remap_f64(X, np.ascontiguousarray(F, np.int32), h, w, p, out)
+    return out
+
+
+def blend_window_fast(guides, styles, M: int, p: int, levels: int, iters: int, seed: int,
+                      identity_nnf: bool = False) -> np.ndarray:
+    """Fast mode (Alg. 3-5 with Eq. 6) over a whole video, fp64 [N][h][w][3].
+    identity_nnf replaces every NNF by the identity (a test hook)."""
+    guides = np.ascontiguousarray(guides, np.uint8)
+    styles = np.ascontiguousarray(styles, np.uint8)
+    N, h, w = guides.shape[:3]
+    out = np.zeros((N, h, w, 3), np.float64)
+    st = lib().fbo_blend_window_fast(guides, styles, N, h, w, M, p, levels, iters, seed, int(identity_nnf), out)
+    if st != 0:
+        raise RuntimeError("fbo_blend_window_fast failed: %d" % st)
     return out
 
 

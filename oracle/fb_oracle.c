@@ -548,6 +548,176 @@ int fbo_blend_window_style(const uint8_t *guides, const uint8_t *styles, int N, 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Alg. 2 on a floating-point image X [h][w][3] (a sum of remapped frames,   */
+/* as the fast mode remaps them again, Eq. 4-5): out(v) = sum over in-image  */
+/* v + d of X(clamp(F(v + d) - d)) / count.                                  */
+/* ------------------------------------------------------------------------ */
+void fbo_remap_f64(const double *X, const int32_t *F, int h, int w, int p, double *out)
+{
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < h; ++r)
+        for (int c = 0; c < w; ++c) {
+            double sum[3] = { 0, 0, 0 };
+            int cnt = 0;
+            for (int dr = -p; dr <= p; ++dr)
+                for (int dc = -p; dc <= p; ++dc) {
+                    int qr = r + dr, qc = c + dc;
+                    if (qr < 0 || qr >= h || qc < 0 || qc >= w) continue;
+                    int sr = clampi(F[2 * (qr * w + qc)] - dr, 0, h - 1);
+                    int sc = clampi(F[2 * (qr * w + qc) + 1] - dc, 0, w - 1);
+                    for (int ch = 0; ch < 3; ++ch) sum[ch] += X[(sr * w + sc) * 3 + ch];
+                    ++cnt;
+                }
+            for (int ch = 0; ch < 3; ++ch) out[(r * w + c) * 3 + ch] = sum[ch] / (double)cnt;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Fast mode (Section 3.4, "Efficiency Improvement"): the remapping table   */
+/* (Alg. 3), the blending table of its column prefix sums (Alg. 4), the     */
+/* interval query (Alg. 5) and the sliding window as a forward and a        */
+/* mirrored query (Eq. 6).  Readings where the listings are garbled:        */
+/*  - the query steps back by the block it used, i <- i - 2^L, and remaps   */
+/*    to S_r (the listing never decrements i and writes S_j);               */
+/*  - the block ending at r itself is added without a remap (NNF(G_r, G_r)  */
+/*    is the identity; R13's j == i convention);                            */
+/*  - blending-table columns run to L = ceil(log2 N) inclusive, the widest  */
+/*    block the query can ask for;                                          */
+/*  - the mirrored ("symmetric") tables index frames as N - 1 - i;          */
+/*  - NNF(G_i, G_j) is the whole coarse-to-fine estimation with pair id     */
+/*    i N + j, as everywhere else;                                          */
+/*  - identity_nnf != 0 replaces every NNF by the identity field (a test    */
+/*    hook: the result must then be the exact window mean).                 */
+/* Values are fp64 in [0,1] units (styles / 255); the window sum of Eq. 6   */
+/* is divided by the truncated window's length.                             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const uint8_t *guides, *styles;
+    int N, h, w, p, levels, iters, identity_nnf;
+    uint64_t seed;
+    int32_t *F;
+    uint32_t *E;
+} fast_ctx;
+
+static int fast_nnf(fast_ctx *fc, int src, int tgt)
+{
+    size_t fpix = (size_t)fc->h * fc->w;
+    if (fc->identity_nnf) {
+        for (int r = 0; r < fc->h; ++r)
+            for (int c = 0; c < fc->w; ++c) {
+                fc->F[2 * (r * fc->w + c)] = r;
+                fc->F[2 * (r * fc->w + c) + 1] = c;
+            }
+        return FBO_OK;
+    }
+    return fbo_patchmatch(fc->guides + (size_t)src * fpix * 3, fc->guides + (size_t)tgt * fpix * 3, fc->h, fc->w,
+                          fc->p, fc->levels, fc->iters, fc->seed, (uint32_t)(src * fc->N + tgt), NULL, fc->F, fc->E);
+}
+
+/* Blending table BT[k][L] (k in table order, frame = map(k)), L = 0..Lmax. */
+static int build_blending_table(fast_ctx *fc, int mirrored, int Lmax, double **BT, double *tmp)
+{
+    const int N = fc->N;
+    size_t n3 = (size_t)fc->h * fc->w * 3;
+#define FRAME(k) (mirrored ? N - 1 - (k) : (k))
+    /* Alg. 3: RemappingTable(j, L + 1) collects (S_i -> S_j); kept in BT[j][L + 1] */
+    for (int j = 0; j < N; ++j)
+        for (int L = 0; L <= Lmax; ++L) memset(BT[j * (Lmax + 1) + L], 0, n3 * sizeof(double));
+    for (int i = 0; i < N; ++i) {
+        int j = i;
+        for (int L = 0; L < Lmax; ++L) {
+            if (i & (1 << L)) continue;
+            j |= 1 << L;
+            if (j < N) {
+                int st = fast_nnf(fc, FRAME(i), FRAME(j));
+                if (st) return st;
+                fbo_remap(fc->styles + (size_t)FRAME(i) * n3, fc->F, fc->h, fc->w, fc->p, tmp);
+                double *dst = BT[j * (Lmax + 1) + L + 1];
+                for (size_t q = 0; q < n3; ++q) dst[q] += tmp[q];
+            }
+        }
+    }
+    /* Alg. 4: BlendingTable(i, 0) = S_i, BlendingTable(i, L) = BlendingTable(i, L - 1) + RemappingTable(i, L) */
+    for (int i = 0; i < N; ++i) {
+        double *b0 = BT[i * (Lmax + 1)];
+        const uint8_t *s = fc->styles + (size_t)FRAME(i) * n3;
+        for (size_t q = 0; q < n3; ++q) b0[q] = s[q] / 255.0;
+        for (int L = 1; L <= Lmax; ++L) {
+            double *b = BT[i * (Lmax + 1) + L], *prev = BT[i * (Lmax + 1) + L - 1];
+            for (size_t q = 0; q < n3; ++q) b[q] += prev[q];
+        }
+    }
+#undef FRAME
+    return FBO_OK;
+}
+
+/* Alg. 5 without the final division: A = sum_{i=l}^{r} (S_i -> S_r), in table order. */
+static int query_blending_table(fast_ctx *fc, int mirrored, int Lmax, double **BT, int l, int r, double *A,
+                                double *tmp)
+{
+    const int N = fc->N;
+    size_t n3 = (size_t)fc->h * fc->w * 3;
+    for (size_t q = 0; q < n3; ++q) A[q] = 0.0;
+    int i = r;
+    while (i >= l) {
+        int L = 0;
+        while ((i & (1 << L)) && i - (1 << (L + 1)) + 1 >= l) ++L;
+        const double *X = BT[i * (Lmax + 1) + L];
+        if (i == r) {
+            for (size_t q = 0; q < n3; ++q) A[q] += X[q];
+        } else {
+            int src = mirrored ? N - 1 - i : i, tgt = mirrored ? N - 1 - r : r;
+            int st = fast_nnf(fc, src, tgt);
+            if (st) return st;
+            fbo_remap_f64(X, fc->F, fc->h, fc->w, fc->p, tmp);
+            for (size_t q = 0; q < n3; ++q) A[q] += tmp[q];
+        }
+        i -= 1 << L;
+    }
+    return FBO_OK;
+}
+
+int fbo_blend_window_fast(const uint8_t *guides, const uint8_t *styles, int N, int h, int w, int M, int p,
+                          int levels, int iters, uint64_t seed, int identity_nnf, double *out)
+{
+    if (N < 1 || M < 0 || h < 1 || w < 1) return FBO_E_INVALID;
+    int Lmax = 0;
+    while ((1 << Lmax) < N) ++Lmax;
+    size_t fpix = (size_t)h * w, n3 = fpix * 3;
+    fast_ctx fc = { guides, styles, N, h, w, p, levels, iters, identity_nnf, seed, NULL, NULL };
+    int status = FBO_OK;
+    size_t nbt = (size_t)N * (Lmax + 1);
+    double **BT[2] = { (double **)calloc(nbt, sizeof(double *)), (double **)calloc(nbt, sizeof(double *)) };
+    double *tmp = (double *)malloc(n3 * sizeof(double));
+    double *left = (double *)malloc(n3 * sizeof(double));
+    double *right = (double *)malloc(n3 * sizeof(double));
+    fc.F = (int32_t *)malloc(fpix * 2 * sizeof(int32_t));
+    fc.E = (uint32_t *)malloc(fpix * sizeof(uint32_t));
+    if (!BT[0] || !BT[1] || !tmp || !left || !right || !fc.F || !fc.E) { status = FBO_E_ALLOC; goto done; }
+    for (int d = 0; d < 2; ++d)
+        for (size_t k = 0; k < nbt; ++k)
+            if (!(BT[d][k] = (double *)malloc(n3 * sizeof(double)))) { status = FBO_E_ALLOC; goto done; }
+    for (int d = 0; d < 2; ++d)
+        if ((status = build_blending_table(&fc, d, Lmax, BT[d], tmp))) goto done;
+    /* Eq. (6): left half on the forward table, right half on the mirrored one */
+    for (int i = 0; i < N; ++i) {
+        int lo = maxi(0, i - M), hi = (i + M < N - 1) ? i + M : N - 1;
+        if ((status = query_blending_table(&fc, 0, Lmax, BT[0], lo, i, left, tmp))) goto done;
+        if ((status = query_blending_table(&fc, 1, Lmax, BT[1], N - 1 - hi, N - 1 - i, right, tmp))) goto done;
+        double *o = out + (size_t)i * n3;
+        const uint8_t *s = styles + (size_t)i * n3;
+        for (size_t q = 0; q < n3; ++q) o[q] = (left[q] + right[q] - s[q] / 255.0) / (double)(hi - lo + 1);
+    }
+done:
+    for (int d = 0; d < 2; ++d) {
+        if (BT[d]) for (size_t k = 0; k < nbt; ++k) free(BT[d][k]);
+        free(BT[d]);
+    }
+    free(tmp); free(left); free(right); free(fc.F); free(fc.E);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Keyframe interpolation, Eq. (9): for l < i < r (l, r the bracketing keys) */
 /* out_i = (r-i)/(r-l) (S_l -> S_i) + (i-l)/(r-l) (S_r -> S_i); keyframes    */
 /* are passed through unchanged (Section 3.5).  Reading for frames before    */
