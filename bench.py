@@ -18,6 +18,8 @@ Prints one JSON line:
   cpu_baseline  the CPU oracle on a bounded sample of the same pairs
   learned    the same blend with the proposal network seeding PatchMatch
   style_loss the same blend with every NNF under the guide + style loss (Eq. 3)
+  fast_mode  the fast-mode blend (tables and queries, Alg. 3-5) against the
+             balanced one at window radius 5 and 15
 """
 from __future__ import annotations
 
@@ -175,6 +177,60 @@ def bench_style(ctx, fbm, g, s, out, M, p, levels, iters, seed, args, pairs, N, 
             "mean_level0_eq3_loss": loss}
 
 
+def fast_mode_nnfs(N, M):
+    """Distinct NNFs the fast mode estimates (tables of Alg. 3 in both frame
+    orders, plus the remaps of Alg. 5's queries)."""
+    Lmax = max(0, (N - 1).bit_length())
+    need = set()
+    frame = lambda d, k: N - 1 - k if d else k
+    for d in (0, 1):
+        for i in range(N):
+            j = i
+            for L in range(Lmax):
+                if (i >> L) & 1:
+                    continue
+                j |= 1 << L
+                if j < N:
+                    need.add((frame(d, i), frame(d, j)))
+    for i in range(N):
+        lo, hi = max(0, i - M), min(N - 1, i + M)
+        for d, (l, r) in ((0, (lo, i)), (1, (N - 1 - hi, N - 1 - i))):
+            k = r
+            while k >= l:
+                L = 0
+                while (k >> L) & 1 and k - (1 << (L + 1)) + 1 >= l:
+                    L += 1
+                if k != r:
+                    need.add((frame(d, k), i))
+                k -= 1 << L
+    return len(need)
+
+
+def bench_fast(ctx, fbm, g, s, out, p, levels, iters, seed, args, N, h, w):
+    """Fast mode (FB_FAST_BLEND, Alg. 3-5 with Eq. 6) against the balanced
+    window blend, at window radius 5 and 15."""
+    import torch
+    res = {}
+    for M in (5, 15):
+        row = {}
+        for name, flags in (("fast", fbm.FB_FAST_BLEND), ("balanced", 0)):
+            prm = fbm.make_params(p, levels, iters, seed, flags)
+            ctx.fb_blend_window(g, s, M, prm, out=out)
+            torch.cuda.synchronize()
+            steps = max(1, args.steps // 2)
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ctx.fb_blend_window(g, s, M, prm, out=out)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / steps * 1e3
+            nnfs = fast_mode_nnfs(N, M) if flags else len(window_pairs(N, M))
+            row[name] = {"ms_per_step": round(ms, 3), "blended_frames_per_s": round(N / (ms / 1e3), 3), "nnfs": nnfs}
+            log("window radius %d, %s: %.2f ms/step, %d NNFs" % (M, name, ms, nnfs))
+        row["speedup_fast_vs_balanced"] = round(row["balanced"]["ms_per_step"] / row["fast"]["ms_per_step"], 3)
+        res["M=%d" % M] = row
+    return res
+
+
 def iter_kernel_traffic():
     """HBM bytes per launch of the PatchMatch iteration kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
@@ -206,6 +262,7 @@ def main():
                     help="trained proposal network; the learned comparison is skipped if absent")
     ap.add_argument("--learned-iters", type=int, default=2)
     ap.add_argument("--no-style", action="store_true", help="skip the Eq. 3 (guide + style loss) comparison")
+    ap.add_argument("--no-fast", action="store_true", help="skip the fast-mode comparison")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (counter calibration)")
     args = ap.parse_args()
@@ -277,6 +334,10 @@ def main():
         mean_energy = round(float(torch.stack(energies).double().mean().item()), 2)
         del energies, pyrs
 
+    fast = None
+    if not args.no_fast:
+        fast = bench_fast(ctx, fbm, g, s, out, p, levels, iters, seed, args, N, h, w)
+
     style = None
     if not args.no_style:
         style = bench_style(ctx, fbm, g, s, out, M, p, levels, iters, seed, args, pairs, N, h, w)
@@ -337,6 +398,7 @@ def main():
         "cpu_baseline": cpu,
         "learned": learned,
         "style_loss": style,
+        "fast_mode": fast,
     }
     if learned:
         learned["speedup_vs_plain"] = round(ms / learned["ms_per_step"], 3)

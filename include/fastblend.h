@@ -65,6 +65,13 @@ typedef enum {
  * (each descriptor's src_style_pyr); the per-level calls and
  * fb_interpolate return FB_E_UNSUPPORTED with it. */
 #define FB_STYLE_LOSS 0x8u
+/* Fast mode of the window blend (Section 3.4, Alg. 3-5, Eq. 4-6): instead of
+ * the 2M NNFs of every frame, a remapping table of O(N log N) NNFs, its
+ * column prefix sums (the blending table) and a mirrored twin; each frame's
+ * window is then a forward and a mirrored interval query, O(log M) further
+ * remaps of table entries (Eq. 4-5 approximations), minus the frame itself
+ * (Eq. 6).  Taken by fb_blend_window only; not with FB_STYLE_LOSS. */
+#define FB_FAST_BLEND 0x10u
 
 /* PatchMatch parameters (Algorithm 1).  The paper names p, n and the pyramid
  * but gives no values; 2 / 3 / 6 are the values of the 512x512 blending

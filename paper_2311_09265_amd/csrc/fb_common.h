@@ -84,21 +84,26 @@ struct TileCfg {
 int n_tile_cfgs();
 TileCfg tile_cfg(int i);
 
-// One term of a remap sum: weight * (style remapped through f) or, with
-// f == nullptr, weight * style / 255 (the frame itself).
+// One term of a remap sum: weight * (source remapped through f), or with
+// f == nullptr weight * the source itself.  kind 0: the source is a style
+// frame, padded level-0 (R,G,B,0) uint8 pixels, in [0,1] units (/ 255);
+// kind 1: an fp32 image [h][w][4] (x, y, z, unused), unpadded, read with
+// clamped coordinates (the fast mode's tables, Eq. 4-5).
+enum RemapKind : int32_t { kRemapStyle = 0, kRemapFloat = 1 };
 struct RemapTerm {
-    const uint32_t *style_px;  // padded level-0 pixels of the style frame
+    const uint32_t *style_px;  // source (kind 0: padded uint8 pixels; kind 1: float4 pixels)
     const uint32_t *f;         // packed field [h][w] or nullptr
     float weight;
-    int32_t pad_;
+    int32_t kind;
 };
 
-// Output frame of a remap sum: out = (sum of its terms) / divisor.
+// Output frame of a remap sum: out = (sum of its terms) / divisor, written as
+// fp32 [h][w][3] (out_kind 0) or [h][w][4] with the 4th channel 0 (out_kind 1).
 struct RemapFrame {
-    float *out;                // fp32 [h][w][3]
+    float *out;
     int32_t term_base, n_terms;
     float divisor;
-    int32_t pad_;
+    int32_t out_kind;
 };
 
 // ---- launchers (stream-ordered, no synchronisation) ----

@@ -27,6 +27,10 @@ namespace {
 
 constexpr int kRTW = 32, kRTH = 8;
 
+// 16-byte float pixels are loaded as a vector type (address-space casts do
+// not copy structs)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 template <class T>
 __device__ __forceinline__ T gload(const void *base, uint32_t byte_off) {
     return *(const __attribute__((address_space(1))) T *)((const __attribute__((address_space(1))) char *)base +
@@ -52,12 +56,20 @@ k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__
     for (int k = 0; k < fr.n_terms; ++k) {
         const RemapTerm T = terms[fr.term_base + k];
         const uint32_t *sp = T.style_px;
+        const bool flt = T.kind == kRemapFloat;
         if (T.f == nullptr) {
             if (active) {
-                const uint32_t px = gload<uint32_t>(sp, 4u * (uint32_t)((r + P) * pitch + (c + P)));
-                a0 += T.weight * ((float)(px & 0xFFu) / 255.0f);
-                a1 += T.weight * ((float)((px >> 8) & 0xFFu) / 255.0f);
-                a2 += T.weight * ((float)((px >> 16) & 0xFFu) / 255.0f);
+                if (flt) {
+                    const f32x4 x = gload<f32x4>(sp, 16u * (uint32_t)(r * w + c));
+                    a0 += T.weight * x.x;
+                    a1 += T.weight * x.y;
+                    a2 += T.weight * x.z;
+                } else {
+                    const uint32_t px = gload<uint32_t>(sp, 4u * (uint32_t)((r + P) * pitch + (c + P)));
+                    a0 += T.weight * ((float)(px & 0xFFu) / 255.0f);
+                    a1 += T.weight * ((float)((px >> 8) & 0xFFu) / 255.0f);
+                    a2 += T.weight * ((float)((px >> 16) & 0xFFu) / 255.0f);
+                }
             }
             continue;
         }
@@ -68,6 +80,30 @@ k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__
         }
         __syncthreads();
         if (!active) continue;
+        if (flt) {
+            float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+#pragma unroll
+            for (int dr = -P; dr <= P; ++dr) {
+                if (dr < r0 || dr > r1) continue;
+                const uint32_t *srow = sf + ((int)threadIdx.y + P + dr) * SW + (int)threadIdx.x + P;
+#pragma unroll
+                for (int dc = -P; dc <= P; ++dc) {
+                    if (dc < c0 || dc > c1) continue;
+                    const uint32_t q = srow[dc];
+                    const int sr = min(max((int)(q >> 16) - dr, 0), h - 1);
+                    const int sc = min(max((int)(q & 0xFFFFu) - dc, 0), w - 1);
+                    const f32x4 x = gload<f32x4>(sp, 16u * (uint32_t)(sr * w + sc));
+                    x0 += x.x;
+                    x1 += x.y;
+                    x2 += x.z;
+                }
+            }
+            const float cnt = (float)((r1 - r0 + 1) * (c1 - c0 + 1));
+            a0 += T.weight * (x0 / cnt);
+            a1 += T.weight * (x1 / cnt);
+            a2 += T.weight * (x2 / cnt);
+            continue;
+        }
         uint32_t rb = 0, g = 0;
 #pragma unroll
         for (int dr = -P; dr <= P; ++dr) {
@@ -88,6 +124,11 @@ k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__
         a2 += T.weight * ((float)(rb >> 16) / denom);
     }
     if (!active) return;
+    if (fr.out_kind == 1) {
+        reinterpret_cast<float4 *>(fr.out)[(size_t)r * w + c] =
+            make_float4(a0 / fr.divisor, a1 / fr.divisor, a2 / fr.divisor, 0.f);
+        return;
+    }
     float *o = fr.out + ((size_t)r * w + c) * 3;
     o[0] = a0 / fr.divisor;
     o[1] = a1 / fr.divisor;

@@ -305,6 +305,29 @@ void add_remap_launch(Plan &P, const std::vector<RemapFrame> &frames,
     }});
 }
 
+// ---- fast mode (Section 3.4, Alg. 3-5, Eq. 6) ----
+
+// Frame of position k in table d (d = 1: the mirrored table of the
+// "symmetric" queries, frames in reverse order).
+int fast_frame(int d, int k, int N) { return d ? N - 1 - k : k; }
+
+// Alg. 5's blocks for the interval [l, r] (table positions): (i, L) with
+// BlendingTable(i, L) = sum of the 2^L frames ending at i, remapped to i;
+// the walk steps back by each block (i <- i - 2^L).
+std::vector<std::pair<int, int>> fast_query_blocks(int l, int r) {
+    std::vector<std::pair<int, int>> out;
+    for (int i = r; i >= l;) {
+        int L = 0;
+        while (((i >> L) & 1) && i - (1 << (L + 1)) + 1 >= l) ++L;
+        out.push_back({i, L});
+        i -= 1 << L;
+    }
+    return out;
+}
+
+// BlendingTable(k, L) exists when L == 0 or the low L bits of k are all set.
+bool fast_entry_valid(int k, int L) { return L == 0 || (k & ((1 << L) - 1)) == (1 << L) - 1; }
+
 }  // namespace
 
 struct fb_ctx {
@@ -312,7 +335,7 @@ struct fb_ctx {
     Buf table;
     std::vector<uint8_t> table_host;  // bytes currently in `table`
     uint64_t table_gen = 0;
-    Buf pyr, style, fe, tune_table, shat;
+    Buf pyr, style, fe, tune_table, shat, tables;
     std::map<std::string, int> tuned;
     int forced_cfg = -1;
     std::string graph_sig;
@@ -597,6 +620,138 @@ fb_status begin(fb_ctx *ctx) {
 
 }  // namespace
 
+// Fast-mode window blend: Alg. 3 (remapping table) and Alg. 4 (blending
+// table, its column prefix sums) for the forward and the mirrored frame
+// order, then every frame's window as the forward query [lo, i] plus the
+// mirrored query [i, hi] minus the frame itself (Eq. 6), divided by the
+// window's length.  All NNFs the tables and queries use run as one batch;
+// table column L is one remap launch (its entries add the column L - 1
+// entry and the frames of the new block), the output one more.
+fb_status blend_fast(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, int N, int h, int w, int M,
+                     const fb_params *params, float *out, hipStream_t stream) {
+    fb_status st;
+    const int p = params->patch_radius, K = params->levels;
+    if (params->flags & FB_STYLE_LOSS) return fail(FB_E_UNSUPPORTED, "FB_FAST_BLEND does not take FB_STYLE_LOSS");
+    int Lmax = 0;
+    while ((1 << Lmax) < N) ++Lmax;
+    const PyrLayout Lp = pyr_layout(h, w, K, p);
+    int32_t pitch = 0;
+    const size_t sbytes = padded_image_bytes(h, w, p, &pitch);
+    const size_t npx = (size_t)h * w;
+
+    // every NNF(G_src, G_tgt) the tables and the queries remap through
+    std::map<uint64_t, size_t> need;  // src * N + tgt -> pair index
+    std::vector<std::pair<int, int>> need_list;
+    auto add = [&](int src, int tgt) {
+        const uint64_t key = (uint64_t)src * N + tgt;
+        if (need.emplace(key, need_list.size()).second) need_list.push_back({src, tgt});
+    };
+    for (int d = 0; d < 2; ++d)
+        for (int i = 0; i < N; ++i)
+            for (int L = 0, j = i; L < Lmax; ++L) {
+                if ((i >> L) & 1) continue;
+                j |= 1 << L;
+                if (j < N) add(fast_frame(d, i, N), fast_frame(d, j, N));
+            }
+    std::vector<std::vector<std::pair<int, int>>> qblocks[2];
+    for (int i = 0; i < N; ++i) {
+        const int lo = std::max(0, i - M), hi = std::min(N - 1, i + M);
+        qblocks[0].push_back(fast_query_blocks(lo, i));
+        qblocks[1].push_back(fast_query_blocks(N - 1 - hi, N - 1 - i));
+        for (int d = 0; d < 2; ++d) {
+            const int r = d ? N - 1 - i : i;
+            for (const auto &b : qblocks[d].back())
+                if (b.first != r) add(fast_frame(d, b.first, N), i);
+        }
+    }
+    // table entries (d, k, L) -> slot
+    std::vector<int> slot(2 * (size_t)N * (Lmax + 1), -1);
+    int n_slots = 0;
+    for (int d = 0; d < 2; ++d)
+        for (int k = 0; k < N; ++k)
+            for (int L = 0; L <= Lmax; ++L)
+                if (fast_entry_valid(k, L)) slot[((size_t)d * N + k) * (Lmax + 1) + L] = n_slots++;
+    const size_t n_pairs = need_list.size();
+    if ((st = ensure(ctx, ctx->pyr, (size_t)N * Lp.bytes)) || (st = ensure(ctx, ctx->style, (size_t)N * sbytes)) ||
+        (st = ensure(ctx, ctx->fe, std::max<size_t>(n_pairs, 1) * npx * 16)) ||
+        (st = ensure(ctx, ctx->tables, (size_t)n_slots * npx * 16)))
+        return st;
+    uint8_t *pyr = static_cast<uint8_t *>(ctx->pyr.p);
+    uint8_t *sty = static_cast<uint8_t *>(ctx->style.p);
+    uint32_t *fe = static_cast<uint32_t *>(ctx->fe.p);
+    float *tab = static_cast<float *>(ctx->tables.p);
+
+    Plan P;
+    plan_pyramids(P, guides, N, h, w, Lp, pyr, Lp.bytes);
+    plan_style_pack(P, styles, N, h, w, p, sty, sbytes, pitch);
+    std::vector<PairSpec> pairs;
+    for (size_t k = 0; k < n_pairs; ++k) {
+        PairSpec ps{};
+        ps.src_pyr = pyr + (size_t)need_list[k].first * Lp.bytes;
+        ps.tgt_pyr = pyr + (size_t)need_list[k].second * Lp.bytes;
+        ps.L = Lp;
+        ps.pair_id = (uint32_t)need_list[k].first * (uint32_t)N + (uint32_t)need_list[k].second;
+        ps.f[0] = fe + k * npx;
+        ps.f[1] = fe + (n_pairs + k) * npx;
+        ps.e[0] = fe + (2 * n_pairs + k) * npx;
+        ps.e[1] = fe + (3 * n_pairs + k) * npx;
+        pairs.push_back(ps);
+    }
+    if (params->flags & FB_LEARNED_SEED)
+        if ((st = plan_learned_seeds(ctx, P, pairs))) return st;
+    const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
+    if (!pairs.empty()) plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg);
+
+    auto style_px = [&](int f) { return reinterpret_cast<const uint32_t *>(sty + (size_t)f * sbytes); };
+    auto field = [&](int src, int tgt) {
+        const PairSpec &ps = pairs[need.at((uint64_t)src * N + tgt)];
+        return (const uint32_t *)ps.f[ps.final_buf];
+    };
+    auto entry = [&](int d, int k, int L) { return tab + (size_t)slot[((size_t)d * N + k) * (Lmax + 1) + L] * npx * 4; };
+    for (int L = 0; L <= Lmax; ++L) {
+        std::vector<RemapTerm> terms;
+        std::vector<RemapFrame> frames;
+        for (int d = 0; d < 2; ++d)
+            for (int k = 0; k < N; ++k) {
+                if (!fast_entry_valid(k, L)) continue;
+                RemapFrame fr{entry(d, k, L), (int32_t)terms.size(), 0, 1.0f, 1};
+                const int fk = fast_frame(d, k, N);
+                if (L == 0) {
+                    terms.push_back(RemapTerm{style_px(fk), nullptr, 1.0f, kRemapStyle});
+                } else {
+                    terms.push_back(RemapTerm{reinterpret_cast<const uint32_t *>(entry(d, k, L - 1)), nullptr, 1.0f,
+                                              kRemapFloat});
+                    for (int i = k - (1 << L) + 1; i <= k - (1 << (L - 1)); ++i) {
+                        const int fi = fast_frame(d, i, N);
+                        terms.push_back(RemapTerm{style_px(fi), field(fi, fk), 1.0f, kRemapStyle});
+                    }
+                }
+                fr.n_terms = (int32_t)terms.size() - fr.term_base;
+                frames.push_back(fr);
+            }
+        if (!frames.empty()) add_remap_launch(P, frames, terms, h, w, pitch, p);
+    }
+    std::vector<RemapTerm> terms;
+    std::vector<RemapFrame> frames;
+    for (int i = 0; i < N; ++i) {
+        const int lo = std::max(0, i - M), hi = std::min(N - 1, i + M);
+        RemapFrame fr{out + (size_t)i * npx * 3, (int32_t)terms.size(), 0, (float)(hi - lo + 1), 0};
+        for (int d = 0; d < 2; ++d) {
+            const int r = d ? N - 1 - i : i;
+            for (const auto &b : qblocks[d][i]) {
+                const int fk = fast_frame(d, b.first, N);
+                terms.push_back(RemapTerm{reinterpret_cast<const uint32_t *>(entry(d, b.first, b.second)),
+                                          b.first == r ? nullptr : field(fk, i), 1.0f, kRemapFloat});
+            }
+        }
+        terms.push_back(RemapTerm{style_px(i), nullptr, -1.0f, kRemapStyle});
+        fr.n_terms = (int32_t)terms.size() - fr.term_base;
+        frames.push_back(fr);
+    }
+    add_remap_launch(P, frames, terms, h, w, pitch, p);
+    return run_plan(ctx, P, params->flags, stream, p, params->seed);
+}
+
 // ============================== C ABI ==================================
 
 extern "C" {
@@ -818,6 +973,8 @@ fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *sty
     if (radius_M < 0) return fail(FB_E_INVALID, "radius_M must be >= 0");
     const int N = n_frames, M = radius_M, p = params->patch_radius, K = params->levels;
     if ((uint64_t)N * (uint64_t)N > 0xFFFFFFFFull) return fail(FB_E_UNSUPPORTED, "pair ids j*N+i must fit in 32 bits");
+    if (params->flags & FB_FAST_BLEND)
+        return blend_fast(ctx, guides, styles, N, h, w, M, params, out, static_cast<hipStream_t>(stream));
     const PyrLayout L = pyr_layout(h, w, K, p);
     int32_t pitch = 0;
     const size_t pbytes = padded_image_bytes(h, w, p, &pitch);

@@ -1,0 +1,73 @@
+"""GPU parity of the fast-mode window blend (FB_FAST_BLEND: remapping and
+blending tables, interval queries, Eq. 6) against the CPU oracle, within
+1e-5 on [0, 1], through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2311_09265_amd import fastblend as fbm
+from paper_2311_09265_amd import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = fbm.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _video(N, h, w, seed):
+    g = synth.sprite_video(N, h, w, seed, n_sprites=2, side=(max(2, min(h, w) // 6), max(3, min(h, w) // 3)))
+    s = synth.flicker(synth.apply_lut(g, synth.random_lut(seed ^ 5)), seed ^ 9)
+    return g, s
+
+
+@pytest.mark.parametrize("N,h,w,M,K,iters", [(5, 40, 48, 2, 2, 2), (9, 33, 45, 3, 1, 3), (16, 32, 40, 4, 2, 2),
+                                             (7, 24, 30, 10, 1, 2), (1, 20, 20, 3, 1, 1)])
+def test_fast_blend_matches_oracle(ctx, N, h, w, M, K, iters):
+    g, s = _video(N, h, w, N * 7 + h)
+    seed = 23
+    out = host(ctx.fb_blend_window(dev(g), dev(s), M, fbm.make_params(2, K, iters, seed, fbm.FB_FAST_BLEND)))
+    ref = oracle.blend_window_fast(g, s, M, 2, K, iters, seed)
+    assert np.abs(out - ref).max() <= TOL
+
+
+def test_fast_blend_graph_replay_matches_eager(ctx):
+    g, s = _video(12, 32, 48, 3)
+    prm = fbm.make_params(2, 2, 2, 5, fbm.FB_FAST_BLEND)
+    ref = host(ctx.fb_blend_window(dev(g), dev(s), 4, prm))
+    gprm = fbm.make_params(2, 2, 2, 5, fbm.FB_FAST_BLEND | fbm.FB_USE_GRAPH)
+    for rep in range(3):
+        assert np.array_equal(host(ctx.fb_blend_window(dev(g), dev(s), 4, gprm)), ref), rep
+
+
+def test_fast_blend_full_size_frames(ctx):
+    """Full-size frames: the first 8 frames of the 512x512 blend workload,
+    3 levels x 6 iterations, window radius 5 (truncated windows, three table
+    levels), against the oracle's fast mode."""
+    guides, styles = synth.blend_workload(8, 512, 512)
+    seed = synth.PHILOX_SEED[2]
+    prm = fbm.make_params(2, 3, 6, seed, fbm.FB_FAST_BLEND)
+    out = host(ctx.fb_blend_window(dev(guides), dev(styles), 5, prm))
+    ref = oracle.blend_window_fast(guides, styles, 5, 2, 3, 6, seed)
+    assert np.abs(out - ref).max() <= TOL
+
+
+def test_fast_blend_rejects_style_loss(ctx):
+    g, s = _video(3, 16, 16, 1)
+    with pytest.raises(fbm.FastBlendError):
+        ctx.fb_blend_window(dev(g), dev(s), 1, fbm.make_params(2, 1, 1, 1, fbm.FB_FAST_BLEND | fbm.FB_STYLE_LOSS))
