@@ -84,6 +84,14 @@ def lib():
         L.fbo_remap_f64.restype = None
         L.fbo_blend_window_fast.argtypes = [u8p, u8p, I, I, I, I, I, I, I, U64, I, f64p]
         L.fbo_blend_window_fast.restype = I
+        L.fbo_window_mean_u8.argtypes = [u8p, I, ctypes.c_void_p, ctypes.c_void_p, I, I, I, I, u8p]
+        L.fbo_window_mean_u8.restype = None
+        L.fbo_pm_iteration_target.argtypes = [u8p, u8p, u8p, u8p, I, I, I, I, I, I, U64, U32, i32p, i32p, u32p]
+        L.fbo_pm_iteration_target.restype = None
+        L.fbo_patchmatch_target.argtypes = [u8p, u8p, u8p, u8p, I, I, I, I, I, U64, U32, I, i32p, u32p]
+        L.fbo_patchmatch_target.restype = I
+        L.fbo_blend_window_accurate.argtypes = [u8p, u8p, I, I, I, I, I, I, I, U64, I, f64p, ctypes.c_void_p]
+        L.fbo_blend_window_accurate.restype = I
         L.fbo_set_threads.argtypes = [I]
         L.fbo_set_threads.restype = None
         L.fbo_get_threads.argtypes = []
@@ -307,6 +315,58 @@ def blend_window_fast(guides, styles, M: int, p: int, levels: int, iters: int, s
     if st != 0:
         raise RuntimeError("fbo_blend_window_fast failed: %d" % st)
     return out
+
+
+def window_mean_u8(styles, i: int, js, fields, p: int) -> np.ndarray:
+    """T^- of Eq. 7 for target frame i: the exact average of S_i and the
+    styles js[k] remapped with fields[k], rounded half up, as uint8."""
+    styles = np.ascontiguousarray(styles, np.uint8)
+    N, h, w = styles.shape[:3]
+    fs = [np.ascontiguousarray(f, np.int32) for f in fields]
+    ptrs = (ctypes.c_void_p * max(1, len(fs)))(*[f.ctypes.data for f in fs])
+    js_a = np.ascontiguousarray(js, np.int32)
+    out = np.zeros((h, w, 3), np.uint8)
+    lib().fbo_window_mean_u8(styles, i, js_a.ctypes.data_as(ctypes.c_void_p), ctypes.cast(ptrs, ctypes.c_void_p),
+                             len(fs), h, w, p, out)
+    return out
+
+
+def pm_iteration_target(Gs, Gt, Ss, Tb, p: int, alpha16: int, level: int, it: int, seed: int, pair_id: int, F):
+    """One iteration under the Eq. 8 loss against a fixed T^- level."""
+    Gs, Gt, Ss, Tb = _img(Gs), _img(Gt), _img(Ss), _img(Tb)
+    h, w = Gs.shape[:2]
+    Fn = np.zeros((h, w, 2), np.int32)
+    En = np.zeros((h, w), np.uint32)
+    lib().fbo_pm_iteration_target(Gs, Gt, Ss, Tb, h, w, p, alpha16, level, it, seed, pair_id,
+                                  np.ascontiguousarray(F, np.int32), Fn, En)
+    return Fn, En
+
+
+def patchmatch_target(Gs, Gt, Ss, Tb, p: int, levels: int, iters: int, seed: int, pair_id: int, alpha16: int):
+    """NNF(G_j, G_i) under the Eq. 8 loss against T^-; returns level-0 F and E."""
+    Gs, Gt, Ss, Tb = _img(Gs), _img(Gt), _img(Ss), _img(Tb)
+    h, w = Gs.shape[:2]
+    F = np.zeros((h, w, 2), np.int32)
+    E = np.zeros((h, w), np.uint32)
+    st = lib().fbo_patchmatch_target(Gs, Gt, Ss, Tb, h, w, p, levels, iters, seed, pair_id, alpha16, F, E)
+    if st != 0:
+        raise RuntimeError("fbo_patchmatch_target failed: %d" % st)
+    return F, E
+
+
+def blend_window_accurate(guides, styles, M: int, p: int, levels: int, iters: int, seed: int, alpha16: int,
+                          return_tbar: bool = False):
+    """Accurate mode (Eq. 7-8 then Eq. 2), fp64 [N][h][w][3] (and T^- per frame)."""
+    guides = np.ascontiguousarray(guides, np.uint8)
+    styles = np.ascontiguousarray(styles, np.uint8)
+    N, h, w = guides.shape[:3]
+    out = np.zeros((N, h, w, 3), np.float64)
+    tb = np.zeros((N, h, w, 3), np.uint8)
+    st = lib().fbo_blend_window_accurate(guides, styles, N, h, w, M, p, levels, iters, seed, alpha16, out,
+                                         tb.ctypes.data_as(ctypes.c_void_p))
+    if st != 0:
+        raise RuntimeError("fbo_blend_window_accurate failed: %d" % st)
+    return (out, tb) if return_tbar else out
 
 
 def interpolate(guides, keys, key_styles, p: int, levels: int, iters: int, seed: int) -> np.ndarray:

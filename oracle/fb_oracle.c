@@ -718,6 +718,200 @@ done:
 }
 
 /* ------------------------------------------------------------------------ */
+/* Accurate mode (Section 3.4, "Quality Improvement", Eq. 7-8).  For target */
+/* frame i with window W = [max(0,i-M), min(N-1,i+M)]:                      */
+/*  1. T^-_i, the average of the window's style frames remapped to frame i  */
+/*     (Eq. 7) with the Eq. 1 NNFs (S_i itself for j == i);                 */
+/*  2. every NNF(G_j, G_i), j != i, estimated again under Eq. 8:            */
+/*       alpha ||G_j[u] - G_i[v]||^2 + ||S_j[u] - T^-_i[v]||^2;             */
+/*  3. the window mean of the styles remapped with the new NNFs (Eq. 2).    */
+/* Readings: the guide term uses the guides (the NNF is between guide       */
+/* frames) and the alignment term the style frames, the images that are     */
+/* averaged; T^-_i is fixed during step 2; it is kept as a uint8 image, the  */
+/* exact average rounded half up -- every remap at pixel v has the same     */
+/* in-image count c_v, so 255 T^- = (sum of the remaps' integer sums +      */
+/* c_v S_i(v)) / (c_v |W|); alpha = alpha16 / 16 and the loss is scaled by  */
+/* 16 as in Eq. 3; T^- is downsampled with the pyramid filter for the       */
+/* coarser levels; step 2 uses the same pair ids (j N + i) and draws.       */
+/* ------------------------------------------------------------------------ */
+
+/* T^- (uint8) of target frame i from the NNFs F[k] of the window's other    */
+/* frames js[k] (n of them) and the frame's own style.                      */
+void fbo_window_mean_u8(const uint8_t *styles, int i, const int *js, const int32_t *const *F, int n, int h,
+                        int w, int p, uint8_t *out)
+{
+    size_t fpix = (size_t)h * w;
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < h; ++r)
+        for (int c = 0; c < w; ++c) {
+            long num[3] = { 0, 0, 0 };
+            long cnt = 0;
+            for (int dr = -p; dr <= p; ++dr)
+                for (int dc = -p; dc <= p; ++dc)
+                    if (r + dr >= 0 && r + dr < h && c + dc >= 0 && c + dc < w) ++cnt;
+            for (int k = 0; k < n; ++k) {
+                const uint8_t *S = styles + (size_t)js[k] * fpix * 3;
+                for (int dr = -p; dr <= p; ++dr)
+                    for (int dc = -p; dc <= p; ++dc) {
+                        int qr = r + dr, qc = c + dc;
+                        if (qr < 0 || qr >= h || qc < 0 || qc >= w) continue;
+                        int sr = clampi(F[k][2 * (qr * w + qc)] - dr, 0, h - 1);
+                        int sc = clampi(F[k][2 * (qr * w + qc) + 1] - dc, 0, w - 1);
+                        for (int ch = 0; ch < 3; ++ch) num[ch] += S[(sr * w + sc) * 3 + ch];
+                    }
+            }
+            const uint8_t *Si = styles + (size_t)i * fpix * 3 + (r * w + c) * 3;
+            long den = cnt * (n + 1);
+            for (int ch = 0; ch < 3; ++ch) {
+                num[ch] += cnt * Si[ch];
+                out[(r * w + c) * 3 + ch] = (uint8_t)((2 * num[ch] + den) / (2 * den));
+            }
+        }
+}
+
+/* One iteration under the Eq. 8 loss against the fixed T^- level Tb: the   */
+/* same candidate sequence as fbo_pm_iteration, the incumbent scored under  */
+/* the loss.                                                                */
+void fbo_pm_iteration_target(const uint8_t *Gs, const uint8_t *Gt, const uint8_t *Ss, const uint8_t *Tb, int h,
+                             int w, int p, int alpha16, int level, int iter, uint64_t seed, uint32_t pair_id,
+                             const int32_t *Fo, int32_t *Fn, uint32_t *En)
+{
+    static const int D[4][2] = { { -1, 0 }, { 1, 0 }, { 0, -1 }, { 0, 1 } };
+    const int R = maxi(h, w);
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < h; ++r)
+        for (int c = 0; c < w; ++c) {
+            int br = Fo[2 * (r * w + c)], bc = Fo[2 * (r * w + c) + 1];
+            uint32_t be = fbo_style_loss(Gs, Gt, Ss, Tb, h, w, p, alpha16, br, bc, r, c);
+            for (int k = 0; k < 4; ++k) {
+                int qr = r + D[k][0], qc = c + D[k][1];
+                if (qr < 0 || qr >= h || qc < 0 || qc >= w) continue;
+                int cr = clampi(Fo[2 * (qr * w + qc)] - D[k][0], 0, h - 1);
+                int cc = clampi(Fo[2 * (qr * w + qc) + 1] - D[k][1], 0, w - 1);
+                uint32_t e = fbo_style_loss(Gs, Gt, Ss, Tb, h, w, p, alpha16, cr, cc, r, c);
+                if (e < be) { br = cr; bc = cc; be = e; }
+            }
+            uint32_t x[4] = { 0, 0, 0, 0 };
+            for (int m = 0; (R >> m) >= 1; ++m) {
+                int rho = R >> m;
+                if ((m & 3) == 0)
+                    draw_words(seed, (uint32_t)(r * w + c), pair_id, (uint32_t)level,
+                               (uint32_t)iter, (uint32_t)(m >> 2), x);
+                uint32_t word = x[m & 3];
+                int dr = (int)fbo_uniform16(word & 0xFFFFu, (uint32_t)(2 * rho + 1)) - rho;
+                int dc = (int)fbo_uniform16(word >> 16, (uint32_t)(2 * rho + 1)) - rho;
+                int cr = clampi(br + dr, 0, h - 1), cc = clampi(bc + dc, 0, w - 1);
+                uint32_t e = fbo_style_loss(Gs, Gt, Ss, Tb, h, w, p, alpha16, cr, cc, r, c);
+                if (e < be) { br = cr; bc = cc; be = e; }
+            }
+            Fn[2 * (r * w + c)] = br;
+            Fn[2 * (r * w + c) + 1] = bc;
+            En[r * w + c] = be;
+        }
+}
+
+/* NNF(G_j, G_i) under Eq. 8 against T^- (level-0 Tb0), coarse to fine, with */
+/* guide, style and T^- pyramids; iters >= 1.                               */
+int fbo_patchmatch_target(const uint8_t *G0s, const uint8_t *G0t, const uint8_t *S0s, const uint8_t *Tb0, int h,
+                          int w, int p, int levels, int iters, uint64_t seed, uint32_t pair_id, int alpha16,
+                          int32_t *F, uint32_t *E)
+{
+    if (levels < 1 || levels > 16 || h < 1 || w < 1 || p < 0 || iters < 1 || alpha16 < 0 || alpha16 > 512)
+        return FBO_E_INVALID;
+    int hs[16], ws[16];
+    const uint8_t *Gs[16], *Gt[16], *Ss[16], *Tb[16];
+    uint8_t *own[64];
+    int n_own = 0;
+    hs[0] = h; ws[0] = w; Gs[0] = G0s; Gt[0] = G0t; Ss[0] = S0s; Tb[0] = Tb0;
+    for (int l = 1; l < levels; ++l) {
+        hs[l] = (hs[l - 1] + 1) / 2;
+        ws[l] = (ws[l - 1] + 1) / 2;
+        const uint8_t *prev[4] = { Gs[l - 1], Gt[l - 1], Ss[l - 1], Tb[l - 1] };
+        uint8_t *next[4];
+        for (int k = 0; k < 4; ++k) {
+            next[k] = (uint8_t *)malloc((size_t)hs[l] * ws[l] * 3);
+            if (!next[k]) { for (int q = 0; q < k; ++q) free(next[q]); for (int i = 0; i < n_own; ++i) free(own[i]); return FBO_E_ALLOC; }
+            fbo_downsample(prev[k], hs[l - 1], ws[l - 1], next[k]);
+        }
+        for (int k = 0; k < 4; ++k) own[n_own++] = next[k];
+        Gs[l] = next[0]; Gt[l] = next[1]; Ss[l] = next[2]; Tb[l] = next[3];
+    }
+    size_t n0 = (size_t)h * w;
+    int32_t *Fa = (int32_t *)malloc(n0 * 2 * sizeof(int32_t));
+    int32_t *Fb = (int32_t *)malloc(n0 * 2 * sizeof(int32_t));
+    uint32_t *Ea = (uint32_t *)malloc(n0 * sizeof(uint32_t));
+    uint32_t *Eb = (uint32_t *)malloc(n0 * sizeof(uint32_t));
+    int status = FBO_OK;
+    if (!Fa || !Fb || !Ea || !Eb) { status = FBO_E_ALLOC; goto done; }
+    for (int l = levels - 1; l >= 0; --l) {
+        int hl = hs[l], wl = ws[l];
+        if (l == levels - 1) {
+            fbo_nnf_init_random(Gs[l], Gt[l], hl, wl, p, l, seed, pair_id, Fa, Ea);
+        } else {
+            fbo_nnf_upsample(Fa, hs[l + 1], ws[l + 1], Gs[l], Gt[l], hl, wl, p, Fb, Eb);
+            int32_t *tf = Fa; Fa = Fb; Fb = tf;
+            uint32_t *te = Ea; Ea = Eb; Eb = te;
+        }
+        for (int it = 0; it < iters; ++it) {
+            fbo_pm_iteration_target(Gs[l], Gt[l], Ss[l], Tb[l], hl, wl, p, alpha16, l, it, seed, pair_id, Fa, Fb, Eb);
+            int32_t *tf = Fa; Fa = Fb; Fb = tf;
+            uint32_t *te = Ea; Ea = Eb; Eb = te;
+        }
+    }
+    memcpy(F, Fa, n0 * 2 * sizeof(int32_t));
+    memcpy(E, Ea, n0 * sizeof(uint32_t));
+done:
+    free(Fa); free(Fb); free(Ea); free(Eb);
+    for (int i = 0; i < n_own; ++i) free(own[i]);
+    return status;
+}
+
+int fbo_blend_window_accurate(const uint8_t *guides, const uint8_t *styles, int N, int h, int w, int M, int p,
+                              int levels, int iters, uint64_t seed, int alpha16, double *out, uint8_t *tbar_out)
+{
+    if (N < 1 || M < 0 || iters < 1 || alpha16 < 0 || alpha16 > 512) return FBO_E_INVALID;
+    size_t fpix = (size_t)h * w, n3 = fpix * 3;
+    int wmax = 2 * M + 1 < N ? 2 * M + 1 : N;
+    int32_t **F = (int32_t **)calloc((size_t)wmax, sizeof(int32_t *));
+    int *js = (int *)malloc((size_t)wmax * sizeof(int));
+    uint32_t *E = (uint32_t *)malloc(fpix * sizeof(uint32_t));
+    uint8_t *tb = (uint8_t *)malloc(n3);
+    double *tmp = (double *)malloc(n3 * sizeof(double));
+    int status = FBO_OK;
+    if (!F || !js || !E || !tb || !tmp) { status = FBO_E_ALLOC; goto done; }
+    for (int k = 0; k < wmax; ++k)
+        if (!(F[k] = (int32_t *)malloc(fpix * 2 * sizeof(int32_t)))) { status = FBO_E_ALLOC; goto done; }
+    for (int i = 0; i < N; ++i) {
+        int lo = maxi(0, i - M), hi = (i + M < N - 1) ? i + M : N - 1, n = 0;
+        const uint8_t *Gi = guides + (size_t)i * n3;
+        for (int j = lo; j <= hi; ++j) {
+            if (j == i) continue;
+            status = fbo_patchmatch(guides + (size_t)j * n3, Gi, h, w, p, levels, iters, seed,
+                                    (uint32_t)(j * N + i), NULL, F[n], E);
+            if (status) goto done;
+            js[n++] = j;
+        }
+        fbo_window_mean_u8(styles, i, js, (const int32_t *const *)F, n, h, w, p, tb);
+        if (tbar_out) memcpy(tbar_out + (size_t)i * n3, tb, n3);
+        double *o = out + (size_t)i * n3;
+        for (size_t q = 0; q < n3; ++q) o[q] = styles[(size_t)i * n3 + q] / 255.0;
+        for (int k = 0; k < n; ++k) {
+            int j = js[k];
+            status = fbo_patchmatch_target(guides + (size_t)j * n3, Gi, styles + (size_t)j * n3, tb, h, w, p,
+                                           levels, iters, seed, (uint32_t)(j * N + i), alpha16, F[k], E);
+            if (status) goto done;
+            fbo_remap(styles + (size_t)j * n3, F[k], h, w, p, tmp);
+            for (size_t q = 0; q < n3; ++q) o[q] += tmp[q];
+        }
+        for (size_t q = 0; q < n3; ++q) o[q] /= (double)(n + 1);
+    }
+done:
+    if (F) for (int k = 0; k < wmax; ++k) free(F[k]);
+    free(F); free(js); free(E); free(tb); free(tmp);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Keyframe interpolation, Eq. (9): for l < i < r (l, r the bracketing keys) */
 /* out_i = (r-i)/(r-l) (S_l -> S_i) + (i-l)/(r-l) (S_r -> S_i); keyframes    */
 /* are passed through unchanged (Section 3.5).  Reading for frames before    */
