@@ -20,6 +20,7 @@ Prints one JSON line:
   style_loss the same blend with every NNF under the guide + style loss (Eq. 3)
   fast_mode  the fast-mode blend (tables and queries, Alg. 3-5) against the
              balanced one at window radius 5 and 15
+  accurate_mode  the accurate-mode blend (Eq. 7-8)
 """
 from __future__ import annotations
 
@@ -231,6 +232,29 @@ def bench_fast(ctx, fbm, g, s, out, p, levels, iters, seed, args, N, h, w):
     return res
 
 
+def bench_accurate(ctx, fbm, g, s, out, M, p, levels, iters, seed, args, N):
+    """Accurate mode (FB_ACCURATE_BLEND, Eq. 7-8, alpha = 1) on the same blend:
+    the window NNFs twice (Eq. 1, then Eq. 8 against T^-) and two remap
+    passes."""
+    import torch
+    prm = fbm.make_params(p, levels, iters, seed, fbm.FB_ACCURATE_BLEND, 16)
+    ctx.fb_blend_window(g, s, M, prm, out=out)
+    torch.cuda.synchronize()
+    ctx.fb_profile_enable(True)
+    ctx.fb_profile_read(reset=True)
+    steps = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.fb_blend_window(g, s, M, prm, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    prof = ctx.fb_profile_read(reset=True)
+    ctx.fb_profile_enable(False)
+    log("accurate mode: %.2f ms/step" % ms)
+    return {"alpha": 1.0, "ms_per_step": round(ms, 3), "blended_frames_per_s": round(N / (ms / 1e3), 3),
+            "kernel_ms_per_step": {k: round(v[1] / steps, 3) for k, v in prof.items() if v[0]}}
+
+
 def iter_kernel_traffic():
     """HBM bytes per launch of the PatchMatch iteration kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
@@ -263,6 +287,7 @@ def main():
     ap.add_argument("--learned-iters", type=int, default=2)
     ap.add_argument("--no-style", action="store_true", help="skip the Eq. 3 (guide + style loss) comparison")
     ap.add_argument("--no-fast", action="store_true", help="skip the fast-mode comparison")
+    ap.add_argument("--no-accurate", action="store_true", help="skip the accurate-mode timing")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (counter calibration)")
     args = ap.parse_args()
@@ -338,6 +363,10 @@ def main():
     if not args.no_fast:
         fast = bench_fast(ctx, fbm, g, s, out, p, levels, iters, seed, args, N, h, w)
 
+    accurate = None
+    if not args.no_accurate:
+        accurate = bench_accurate(ctx, fbm, g, s, out, M, p, levels, iters, seed, args, N)
+
     style = None
     if not args.no_style:
         style = bench_style(ctx, fbm, g, s, out, M, p, levels, iters, seed, args, pairs, N, h, w)
@@ -399,6 +428,7 @@ def main():
         "learned": learned,
         "style_loss": style,
         "fast_mode": fast,
+        "accurate_mode": accurate,
     }
     if learned:
         learned["speedup_vs_plain"] = round(ms / learned["ms_per_step"], 3)

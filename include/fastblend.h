@@ -70,8 +70,18 @@ typedef enum {
  * column prefix sums (the blending table) and a mirrored twin; each frame's
  * window is then a forward and a mirrored interval query, O(log M) further
  * remaps of table entries (Eq. 4-5 approximations), minus the frame itself
- * (Eq. 6).  Taken by fb_blend_window only; not with FB_STYLE_LOSS. */
+ * (Eq. 6).  Taken by fb_blend_window only; not with FB_STYLE_LOSS or
+ * FB_ACCURATE_BLEND. */
 #define FB_FAST_BLEND 0x10u
+/* Accurate mode of the window blend (Section 3.4, Eq. 7-8): the window's
+ * styles remapped with the Eq. 1 NNFs are averaged into T^-_i for every
+ * target frame (kept as uint8, the exact average rounded half up); every
+ * NNF is estimated again under alpha ||G_j[u] - G_i[v]||^2 + ||S_j[u] -
+ * T^-_i[v]||^2 (alpha = alpha16 / 16, loss x 16 as for FB_STYLE_LOSS); the
+ * output is the window mean of the styles remapped with the new NNFs.
+ * Needs iters >= 1 and 0 <= alpha16 <= 512.  Taken by fb_blend_window only;
+ * not with FB_STYLE_LOSS or FB_FAST_BLEND. */
+#define FB_ACCURATE_BLEND 0x20u
 
 /* PatchMatch parameters (Algorithm 1).  The paper names p, n and the pyramid
  * but gives no values; 2 / 3 / 6 are the values of the 512x512 blending

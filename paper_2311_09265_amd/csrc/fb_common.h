@@ -98,7 +98,9 @@ struct RemapTerm {
 };
 
 // Output frame of a remap sum: out = (sum of its terms) / divisor, written as
-// fp32 [h][w][3] (out_kind 0) or [h][w][4] with the 4th channel 0 (out_kind 1).
+// fp32 [h][w][3] (out_kind 0) or [h][w][4] with the 4th channel 0 (out_kind 1);
+// out_kind 2: the exact mean of its terms (all style terms of weight 1; the
+// divisor is ignored) rounded half up, as uint8 [h][w][3].
 struct RemapFrame {
     float *out;
     int32_t term_base, n_terms;

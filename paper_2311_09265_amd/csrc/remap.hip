@@ -51,8 +51,10 @@ k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__
     const bool active = r < h && c < w;  // no early exit: the term loop has barriers
     const int r0 = max(-P, -r), r1 = min(P, h - 1 - r);
     const int c0 = max(-P, -c), c1 = min(P, w - 1 - c);
-    const float denom = (float)(255 * (r1 - r0 + 1) * (c1 - c0 + 1));
+    const int cnt_v = (r1 - r0 + 1) * (c1 - c0 + 1);
+    const float denom = (float)(255 * cnt_v);
     float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    uint32_t n0 = 0, n1 = 0, n2 = 0;  // out_kind 2: exact integer totals (style terms, weight 1)
     for (int k = 0; k < fr.n_terms; ++k) {
         const RemapTerm T = terms[fr.term_base + k];
         const uint32_t *sp = T.style_px;
@@ -69,6 +71,9 @@ k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__
                     a0 += T.weight * ((float)(px & 0xFFu) / 255.0f);
                     a1 += T.weight * ((float)((px >> 8) & 0xFFu) / 255.0f);
                     a2 += T.weight * ((float)((px >> 16) & 0xFFu) / 255.0f);
+                    n0 += (uint32_t)cnt_v * (px & 0xFFu);
+                    n1 += (uint32_t)cnt_v * ((px >> 8) & 0xFFu);
+                    n2 += (uint32_t)cnt_v * ((px >> 16) & 0xFFu);
                 }
             }
             continue;
@@ -122,8 +127,21 @@ k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__
         a0 += T.weight * ((float)(rb & 0xFFFFu) / denom);
         a1 += T.weight * ((float)g / denom);
         a2 += T.weight * ((float)(rb >> 16) / denom);
+        n0 += rb & 0xFFFFu;
+        n1 += g;
+        n2 += rb >> 16;
     }
     if (!active) return;
+    if (fr.out_kind == 2) {
+        // the exact mean of the terms (every term's remap at this pixel has
+        // the same count cnt_v), rounded half up, as uint8 RGB
+        const uint32_t den = (uint32_t)cnt_v * (uint32_t)fr.n_terms;
+        uint8_t *o = reinterpret_cast<uint8_t *>(fr.out) + ((size_t)r * w + c) * 3;
+        o[0] = (uint8_t)((2u * n0 + den) / (2u * den));
+        o[1] = (uint8_t)((2u * n1 + den) / (2u * den));
+        o[2] = (uint8_t)((2u * n2 + den) / (2u * den));
+        return;
+    }
     if (fr.out_kind == 1) {
         reinterpret_cast<float4 *>(fr.out)[(size_t)r * w + c] =
             make_float4(a0 / fr.divisor, a1 / fr.divisor, a2 / fr.divisor, 0.f);

@@ -167,8 +167,9 @@ struct PairSpec {
     uint32_t *f[2], *e[2];     // ping-pong buffers (level-0 capacity)
     int32_t *nnf_abi;          // optional export of the final field
     uint32_t *energy_abi;
-    const uint8_t *src_sty_pyr;  // Eq. 3 loss: pyramid of the source style frame
+    const uint8_t *src_sty_pyr;  // Eq. 3 / Eq. 8 loss: pyramid of the source style frame
     uint32_t *sty_hat;         // Eq. 3 loss: padded S^ buffer (level-0 capacity)
+    const uint8_t *tbar_pyr;   // Eq. 8 loss: pyramid of the fixed target T^- (instead of S^)
     int final_buf;             // filled by the planner
 };
 
@@ -185,7 +186,9 @@ PMJob job_geom(const PairSpec &ps, int l) {
     j.level = l;
     if (ps.src_sty_pyr) {
         j.src_sty = reinterpret_cast<const uint32_t *>(ps.src_sty_pyr + g.px_off);
-        j.sty_hat = ps.sty_hat;
+        // the iteration only reads sty_hat; T^- is never written
+        j.sty_hat = ps.tbar_pyr ? const_cast<uint32_t *>(reinterpret_cast<const uint32_t *>(ps.tbar_pyr + g.px_off))
+                                : ps.sty_hat;
     }
     return j;
 }
@@ -213,9 +216,10 @@ std::string tune_key_of(const std::vector<PairSpec> &pairs, int p) {
 // level: a pair with K levels joins at pass Kmax - K, so at every pass all
 // active pairs sit at the same level number.  With the Eq. 3 loss (style),
 // every iteration launch is preceded by the refresh of the pairs' S^ from the
-// field the iteration starts from.
+// field the iteration starts from.  With the Eq. 8 loss (style and
+// fixed_target) the second patch is each pair's fixed T^-: no refresh.
 void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, uint64_t seed,
-                     TileCfg cfg, bool style = false, int alpha16 = 0) {
+                     TileCfg cfg, bool style = false, int alpha16 = 0, bool fixed_target = false) {
     int kmax = 0;
     for (const PairSpec &ps : pairs) kmax = std::max(kmax, ps.L.levels);
     std::vector<int> cur(pairs.size(), 0);
@@ -248,7 +252,7 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
         }
         add_pm_launch(P, kLaunchStart, js, cfg, p, seed, 0);
         for (int it = 0; it < iters; ++it) {
-            if (style) {
+            if (style && !fixed_target) {
                 js.clear();
                 for (size_t k : active) {
                     PMJob j = job_geom(pairs[k], l);
@@ -596,8 +600,8 @@ fb_status check_params(const fb_params *prm, bool need_levels) {
         return fail(FB_E_INVALID, "levels must be in [1, 16]");
     if (prm->iters < 0 || prm->iters > 0xFFFE) return fail(FB_E_INVALID, "iters must be in [0, 65534]");
     if (prm->reserved != 0) return fail(FB_E_INVALID, "params->reserved must be 0");
-    if (prm->flags & FB_STYLE_LOSS) {
-        if (prm->iters < 1) return fail(FB_E_INVALID, "FB_STYLE_LOSS needs iters >= 1");
+    if (prm->flags & (FB_STYLE_LOSS | FB_ACCURATE_BLEND)) {
+        if (prm->iters < 1) return fail(FB_E_INVALID, "FB_STYLE_LOSS and FB_ACCURATE_BLEND need iters >= 1");
         if (prm->alpha16 < 0 || prm->alpha16 > 512) return fail(FB_E_INVALID, "alpha16 must be in [0, 512]");
     }
     return FB_OK;
@@ -631,7 +635,8 @@ fb_status blend_fast(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, 
                      const fb_params *params, float *out, hipStream_t stream) {
     fb_status st;
     const int p = params->patch_radius, K = params->levels;
-    if (params->flags & FB_STYLE_LOSS) return fail(FB_E_UNSUPPORTED, "FB_FAST_BLEND does not take FB_STYLE_LOSS");
+    if (params->flags & (FB_STYLE_LOSS | FB_ACCURATE_BLEND))
+        return fail(FB_E_UNSUPPORTED, "FB_FAST_BLEND takes neither FB_STYLE_LOSS nor FB_ACCURATE_BLEND");
     int Lmax = 0;
     while ((1 << Lmax) < N) ++Lmax;
     const PyrLayout Lp = pyr_layout(h, w, K, p);
@@ -746,6 +751,104 @@ fb_status blend_fast(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, 
         }
         terms.push_back(RemapTerm{style_px(i), nullptr, -1.0f, kRemapStyle});
         fr.n_terms = (int32_t)terms.size() - fr.term_base;
+        frames.push_back(fr);
+    }
+    add_remap_launch(P, frames, terms, h, w, pitch, p);
+    return run_plan(ctx, P, params->flags, stream, p, params->seed);
+}
+
+// Accurate-mode window blend (Eq. 7-8): the window NNFs under Eq. 1; T^- of
+// every frame, the exact mean of its window's remapped styles rounded to
+// uint8 (one remap launch), and its pyramid; every NNF estimated again under
+// Eq. 8 against its target frame's T^- (the style iteration kernel, no
+// refresh); the window mean of the styles remapped with the new NNFs.
+fb_status blend_accurate(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, int N, int h, int w, int M,
+                         const fb_params *params, float *out, hipStream_t stream) {
+    fb_status st;
+    const int p = params->patch_radius, K = params->levels;
+    if (params->flags & (FB_STYLE_LOSS | FB_FAST_BLEND))
+        return fail(FB_E_UNSUPPORTED, "FB_ACCURATE_BLEND takes neither FB_STYLE_LOSS nor FB_FAST_BLEND");
+    const PyrLayout L = pyr_layout(h, w, K, p);
+    int32_t pitch = 0;
+    (void)padded_image_bytes(h, w, p, &pitch);
+    const size_t npx = (size_t)h * w;
+    size_t n_pairs = 0;
+    for (int i = 0; i < N; ++i) n_pairs += (size_t)(std::min(N - 1, i + M) - std::max(0, i - M));
+    // style: N style pyramids, then N T^- frames (uint8 RGB) and their pyramids
+    const size_t tbar_rgb = ((size_t)N * npx * 3 + 255) & ~(size_t)255;
+    if ((st = ensure(ctx, ctx->pyr, (size_t)N * L.bytes)) ||
+        (st = ensure(ctx, ctx->style, 2 * (size_t)N * L.bytes + tbar_rgb)) ||
+        (st = ensure(ctx, ctx->fe, std::max<size_t>(2 * n_pairs, 1) * npx * 16)))
+        return st;
+    uint8_t *pyr = static_cast<uint8_t *>(ctx->pyr.p);
+    uint8_t *sty = static_cast<uint8_t *>(ctx->style.p);
+    uint8_t *tbar = sty + (size_t)N * L.bytes;
+    uint8_t *tbar_in = tbar + (size_t)N * L.bytes;
+    uint32_t *fe = static_cast<uint32_t *>(ctx->fe.p);
+
+    Plan P;
+    plan_pyramids(P, guides, N, h, w, L, pyr, L.bytes);
+    plan_pyramids(P, styles, N, h, w, L, sty, L.bytes);
+    // fields and energies of pair k in pass q (0: Eq. 1, 1: Eq. 8), n pairs,
+    // in slices of npx entries of fe: f[0] at q n + k, f[1] at 2n + q n + k,
+    // e[0] at 4n + q n + k, e[1] at 6n + q n + k
+    std::vector<PairSpec> first, second;
+    auto bufs = [&](PairSpec &ps, int q, size_t k) {
+        ps.f[0] = fe + (q * n_pairs + k) * npx;
+        ps.f[1] = fe + (2 * n_pairs + q * n_pairs + k) * npx;
+        ps.e[0] = fe + (4 * n_pairs + q * n_pairs + k) * npx;
+        ps.e[1] = fe + (6 * n_pairs + q * n_pairs + k) * npx;
+    };
+    for (int i = 0; i < N; ++i)
+        for (int j = std::max(0, i - M); j <= std::min(N - 1, i + M); ++j) {
+            if (j == i) continue;
+            PairSpec ps{};
+            ps.src_pyr = pyr + (size_t)j * L.bytes;
+            ps.tgt_pyr = pyr + (size_t)i * L.bytes;
+            ps.L = L;
+            ps.pair_id = (uint32_t)j * (uint32_t)N + (uint32_t)i;
+            const size_t k = first.size();
+            bufs(ps, 0, k);
+            first.push_back(ps);
+            ps.src_sty_pyr = sty + (size_t)j * L.bytes;
+            ps.tbar_pyr = tbar + (size_t)i * L.bytes;
+            bufs(ps, 1, k);
+            second.push_back(ps);
+        }
+    if (params->flags & FB_LEARNED_SEED) {
+        if ((st = plan_learned_seeds(ctx, P, first))) return st;
+        for (size_t k = 0; k < first.size(); ++k) second[k].seed_offsets = first[k].seed_offsets;
+    }
+    const TileCfg cfg = choose_cfg(ctx, tune_key_of(first, p), params->flags);
+    if (!first.empty()) plan_patchmatch(P, first, params->iters, p, params->seed, cfg);
+    // T^- of every frame, then its pyramid
+    auto style_px = [&](int f) { return reinterpret_cast<const uint32_t *>(sty + (size_t)f * L.bytes); };
+    std::vector<RemapTerm> terms;
+    std::vector<RemapFrame> frames;
+    size_t k = 0;
+    for (int i = 0; i < N; ++i) {
+        const int lo = std::max(0, i - M), hi = std::min(N - 1, i + M);
+        RemapFrame fr{reinterpret_cast<float *>(tbar_in + (size_t)i * npx * 3), (int32_t)terms.size(), hi - lo + 1,
+                      1.0f, 2};
+        for (int j = lo; j <= hi; ++j) {
+            if (j == i) terms.push_back(RemapTerm{style_px(i), nullptr, 1.0f, kRemapStyle});
+            else { terms.push_back(RemapTerm{style_px(j), first[k].f[first[k].final_buf], 1.0f, kRemapStyle}); ++k; }
+        }
+        frames.push_back(fr);
+    }
+    add_remap_launch(P, frames, terms, h, w, pitch, p);
+    plan_pyramids(P, tbar_in, N, h, w, L, tbar, L.bytes);
+    if (!second.empty()) plan_patchmatch(P, second, params->iters, p, params->seed, cfg, true, params->alpha16, true);
+    terms.clear();
+    frames.clear();
+    k = 0;
+    for (int i = 0; i < N; ++i) {
+        const int lo = std::max(0, i - M), hi = std::min(N - 1, i + M);
+        RemapFrame fr{out + (size_t)i * npx * 3, (int32_t)terms.size(), hi - lo + 1, (float)(hi - lo + 1), 0};
+        for (int j = lo; j <= hi; ++j) {
+            if (j == i) terms.push_back(RemapTerm{style_px(i), nullptr, 1.0f, kRemapStyle});
+            else { terms.push_back(RemapTerm{style_px(j), second[k].f[second[k].final_buf], 1.0f, kRemapStyle}); ++k; }
+        }
         frames.push_back(fr);
     }
     add_remap_launch(P, frames, terms, h, w, pitch, p);
@@ -975,6 +1078,8 @@ fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *sty
     if ((uint64_t)N * (uint64_t)N > 0xFFFFFFFFull) return fail(FB_E_UNSUPPORTED, "pair ids j*N+i must fit in 32 bits");
     if (params->flags & FB_FAST_BLEND)
         return blend_fast(ctx, guides, styles, N, h, w, M, params, out, static_cast<hipStream_t>(stream));
+    if (params->flags & FB_ACCURATE_BLEND)
+        return blend_accurate(ctx, guides, styles, N, h, w, M, params, out, static_cast<hipStream_t>(stream));
     const PyrLayout L = pyr_layout(h, w, K, p);
     int32_t pitch = 0;
     const size_t pbytes = padded_image_bytes(h, w, p, &pitch);
