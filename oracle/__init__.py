@@ -92,6 +92,11 @@ def lib():
         L.fbo_patchmatch_target.restype = I
         L.fbo_blend_window_accurate.argtypes = [u8p, u8p, I, I, I, I, I, I, I, U64, I, f64p, ctypes.c_void_p]
         L.fbo_blend_window_accurate.restype = I
+        L.fbo_pm_iteration_ext.argtypes = [u8p, u8p, u8p, u8p, I, I, I, I, I, I, I, U64, U32, ctypes.c_void_p,
+                                           ctypes.c_void_p, I, I, I, I, i32p, u32p]
+        L.fbo_pm_iteration_ext.restype = None
+        L.fbo_interpolate_ext.argtypes = [u8p, I, I, I, i32p, u8p, I, I, I, I, U64, I, I, f64p]
+        L.fbo_interpolate_ext.restype = I
         L.fbo_set_threads.argtypes = [I]
         L.fbo_set_threads.restype = None
         L.fbo_get_threads.argtypes = []
@@ -367,6 +372,45 @@ def blend_window_accurate(guides, styles, M: int, p: int, levels: int, iters: in
     if st != 0:
         raise RuntimeError("fbo_blend_window_accurate failed: %d" % st)
     return (out, tb) if return_tbar else out
+
+
+TRACK, ALIGN = 1, 2
+
+
+def pm_iteration_ext(Gs, Gt, Ss, Sp, p: int, alpha16: int, flags: int, level: int, it: int, seed: int,
+                     pair_id: int, fields, energies, q: int, prev: int = -1, nxt: int = -1, partner: int = -1):
+    """One iteration of pair q of a jointly estimated interpolation (tracking
+    and / or alignment, Section 3.5, Eq. 10); fields / energies: the previous
+    fields and energies of all pairs.  Returns (F, E)."""
+    Gs, Gt, Ss, Sp = _img(Gs), _img(Gt), _img(Ss), _img(Sp)
+    h, w = Gs.shape[:2]
+    fs = [np.ascontiguousarray(f, np.int32) for f in fields]
+    es = [np.ascontiguousarray(e, np.uint32) for e in energies]
+    fp = (ctypes.c_void_p * len(fs))(*[f.ctypes.data for f in fs])
+    ep = (ctypes.c_void_p * len(es))(*[e.ctypes.data for e in es])
+    Fn = np.zeros((h, w, 2), np.int32)
+    En = np.zeros((h, w), np.uint32)
+    lib().fbo_pm_iteration_ext(Gs, Gt, Ss, Sp, h, w, p, alpha16, flags, level, it, seed, pair_id,
+                               ctypes.cast(fp, ctypes.c_void_p), ctypes.cast(ep, ctypes.c_void_p), q, prev, nxt,
+                               partner, Fn, En)
+    return Fn, En
+
+
+def interpolate_ext(guides, keys, key_styles, p: int, levels: int, iters: int, seed: int, alpha16: int = 16,
+                    track: bool = False, align: bool = False) -> np.ndarray:
+    """Eq. (9) with the NNFs estimated jointly with tracking and / or the
+    pairwise alignment loss (Eq. 10), fp64 [N][h][w][3]."""
+    guides = np.ascontiguousarray(guides, np.uint8)
+    keys = np.ascontiguousarray(keys, np.int32)
+    key_styles = np.ascontiguousarray(key_styles, np.uint8)
+    N, h, w = guides.shape[:3]
+    out = np.zeros((N, h, w, 3), np.float64)
+    flags = (TRACK if track else 0) | (ALIGN if align else 0)
+    st = lib().fbo_interpolate_ext(guides, N, h, w, keys, key_styles, len(keys), p, levels, iters, seed, alpha16,
+                                   flags, out)
+    if st != 0:
+        raise RuntimeError("fbo_interpolate_ext failed: %d" % st)
+    return out
 
 
 def interpolate(guides, keys, key_styles, p: int, levels: int, iters: int, seed: int) -> np.ndarray:

@@ -912,6 +912,219 @@ done:
 }
 
 /* ------------------------------------------------------------------------ */
+/* Interpolation extras (Section 3.5): tracking and the pairwise alignment  */
+/* loss (Eq. 10).  All NNF(G_k, G_i) of an interpolation (k a bracketing     */
+/* key of frame i) are estimated together, level by level and iteration by  */
+/* iteration, every pair reading only the previous iteration's fields      */
+/* (the concurrent update of Section 3.2 applied across pairs).             */
+/*  - tracking: NNF(G_k, G_i) also tries F_{k,i-1}(v) and F_{k,i+1}(v), the */
+/*    matches of the pairs with the same key and the neighbouring target    */
+/*    frames, when those pairs exist; they come after the 4 propagation     */
+/*    candidates and before the random search;                             */
+/*  - alignment: for a frame with both keys l and r, the pair (a, i) and    */
+/*    its partner (b, i) minimise                                          */
+/*       alpha ||G_a[u] - G_i[v]||^2 + ||S_a[u] - S_b[F_b(v)]||^2           */
+/*    (S the keyframe styles, F_b the partner's previous field; guide term  */
+/*    on guides, alignment on styles as in Eq. 8); the incumbent is scored  */
+/*    anew every iteration; alpha = alpha16 / 16, loss x 16, alpha16 >= 1;  */
+/*    frames with a single key keep the Eq. 1 loss.                         */
+/* ------------------------------------------------------------------------ */
+#define FBO_TRACK 1
+#define FBO_ALIGN 2
+
+/* One iteration of pair q.  Fo[k] / Eo[k]: previous fields and energies of  */
+/* all pairs; prev / next / partner: pair indices or -1.  Gs = G_a (source  */
+/* key), Gt = G_i, Ss = S_a and Sp = S_b (keyframe styles at this level).   */
+void fbo_pm_iteration_ext(const uint8_t *Gs, const uint8_t *Gt, const uint8_t *Ss, const uint8_t *Sp, int h, int w,
+                          int p, int alpha16, int flags, int level, int iter, uint64_t seed, uint32_t pair_id,
+                          const int32_t *const *Fo, const uint32_t *const *Eo, int q, int prev, int next,
+                          int partner, int32_t *Fn, uint32_t *En)
+{
+    static const int D[4][2] = { { -1, 0 }, { 1, 0 }, { 0, -1 }, { 0, 1 } };
+    const int R = maxi(h, w);
+    const int aligned = (flags & FBO_ALIGN) && partner >= 0;
+    const int32_t *F = Fo[q];
+    #pragma omp parallel for schedule(static)
+    for (int r = 0; r < h; ++r)
+        for (int c = 0; c < w; ++c) {
+            const int v = r * w + c;
+            int br = F[2 * v], bc = F[2 * v + 1];
+            /* the partner's match fixes this iteration's alignment patch */
+            const int pr = aligned ? Fo[partner][2 * v] : 0, pc = aligned ? Fo[partner][2 * v + 1] : 0;
+#define LOSS(UR, UC) (aligned ? (uint32_t)alpha16 * fbo_patch_ssd(Gs, Gt, h, w, p, UR, UC, r, c) + \
+                                    16u * fbo_patch_ssd(Ss, Sp, h, w, p, UR, UC, pr, pc)          \
+                              : fbo_patch_ssd(Gs, Gt, h, w, p, UR, UC, r, c))
+            uint32_t be = aligned ? LOSS(br, bc) : Eo[q][v];
+            for (int k = 0; k < 4; ++k) {
+                int qr = r + D[k][0], qc = c + D[k][1];
+                if (qr < 0 || qr >= h || qc < 0 || qc >= w) continue;
+                int cr = clampi(F[2 * (qr * w + qc)] - D[k][0], 0, h - 1);
+                int cc = clampi(F[2 * (qr * w + qc) + 1] - D[k][1], 0, w - 1);
+                uint32_t e = LOSS(cr, cc);
+                if (e < be) { br = cr; bc = cc; be = e; }
+            }
+            if (flags & FBO_TRACK) {
+                const int nb[2] = { prev, next };
+                for (int k = 0; k < 2; ++k) {
+                    if (nb[k] < 0) continue;
+                    int cr = Fo[nb[k]][2 * v], cc = Fo[nb[k]][2 * v + 1];
+                    uint32_t e = LOSS(cr, cc);
+                    if (e < be) { br = cr; bc = cc; be = e; }
+                }
+            }
+            uint32_t x[4] = { 0, 0, 0, 0 };
+            for (int m = 0; (R >> m) >= 1; ++m) {
+                int rho = R >> m;
+                if ((m & 3) == 0)
+                    draw_words(seed, (uint32_t)v, pair_id, (uint32_t)level, (uint32_t)iter, (uint32_t)(m >> 2), x);
+                uint32_t word = x[m & 3];
+                int dr = (int)fbo_uniform16(word & 0xFFFFu, (uint32_t)(2 * rho + 1)) - rho;
+                int dc = (int)fbo_uniform16(word >> 16, (uint32_t)(2 * rho + 1)) - rho;
+                int cr = clampi(br + dr, 0, h - 1), cc = clampi(bc + dc, 0, w - 1);
+                uint32_t e = LOSS(cr, cc);
+                if (e < be) { br = cr; bc = cc; be = e; }
+            }
+#undef LOSS
+            Fn[2 * v] = br;
+            Fn[2 * v + 1] = bc;
+            En[v] = be;
+        }
+}
+
+/* Eq. (9) with tracking and / or alignment (flags FBO_TRACK | FBO_ALIGN). */
+int fbo_interpolate_ext(const uint8_t *guides, int N, int h, int w, const int32_t *keys, const uint8_t *key_styles,
+                        int n_keys, int p, int levels, int iters, uint64_t seed, int alpha16, int flags,
+                        double *out)
+{
+    if (N < 1 || n_keys < 1 || levels < 1 || levels > 16 || iters < 0) return FBO_E_INVALID;
+    if ((flags & FBO_ALIGN) && (iters < 1 || alpha16 < 1 || alpha16 > 512)) return FBO_E_INVALID;
+    size_t fpix = (size_t)h * w, n3 = fpix * 3;
+    int hs[16], ws[16];
+    hs[0] = h; ws[0] = w;
+    for (int l = 1; l < levels; ++l) { hs[l] = (hs[l - 1] + 1) / 2; ws[l] = (ws[l - 1] + 1) / 2; }
+    /* pairs: (key index, frame) with the same order as the plain interpolation */
+    int *pk = (int *)malloc(sizeof(int) * 2 * (size_t)N), *pf = (int *)malloc(sizeof(int) * 2 * (size_t)N);
+    int *kself = (int *)malloc(sizeof(int) * (size_t)N), *kl = (int *)malloc(sizeof(int) * (size_t)N);
+    int *kr = (int *)malloc(sizeof(int) * (size_t)N);
+    int np = 0, status = FBO_OK;
+    uint8_t **G = (uint8_t **)calloc((size_t)N * levels, sizeof(uint8_t *));
+    uint8_t **KS = (uint8_t **)calloc((size_t)n_keys * levels, sizeof(uint8_t *));
+    int32_t **Fa = NULL, **Fb = NULL;
+    uint32_t **Ea = NULL, **Eb = NULL;
+    int *prev = NULL, *next = NULL, *partner = NULL;
+    double *tmp = (double *)malloc(n3 * sizeof(double));
+    if (!pk || !pf || !kself || !kl || !kr || !G || !KS || !tmp) { status = FBO_E_ALLOC; goto done; }
+    for (int i = 0; i < N; ++i) {
+        kself[i] = kl[i] = kr[i] = -1;
+        for (int k = 0; k < n_keys; ++k) {
+            if (keys[k] == i) kself[i] = k;
+            if (keys[k] < i) kl[i] = k;
+            if (keys[k] > i && kr[i] < 0) kr[i] = k;
+        }
+        if (kself[i] >= 0) continue;
+        if (kl[i] >= 0) { pk[np] = kl[i]; pf[np] = i; ++np; }
+        if (kr[i] >= 0) { pk[np] = kr[i]; pf[np] = i; ++np; }
+    }
+    /* pyramids of every guide frame and every keyframe style */
+    for (int i = 0; i < N; ++i) {
+        G[(size_t)i * levels] = (uint8_t *)(guides + (size_t)i * n3);
+        for (int l = 1; l < levels; ++l) {
+            uint8_t *d = (uint8_t *)malloc((size_t)hs[l] * ws[l] * 3);
+            if (!d) { status = FBO_E_ALLOC; goto done; }
+            fbo_downsample(G[(size_t)i * levels + l - 1], hs[l - 1], ws[l - 1], d);
+            G[(size_t)i * levels + l] = d;
+        }
+    }
+    for (int k = 0; k < n_keys; ++k) {
+        KS[(size_t)k * levels] = (uint8_t *)(key_styles + (size_t)k * n3);
+        for (int l = 1; l < levels; ++l) {
+            uint8_t *d = (uint8_t *)malloc((size_t)hs[l] * ws[l] * 3);
+            if (!d) { status = FBO_E_ALLOC; goto done; }
+            fbo_downsample(KS[(size_t)k * levels + l - 1], hs[l - 1], ws[l - 1], d);
+            KS[(size_t)k * levels + l] = d;
+        }
+    }
+    Fa = (int32_t **)calloc((size_t)np + 1, sizeof(int32_t *));
+    Fb = (int32_t **)calloc((size_t)np + 1, sizeof(int32_t *));
+    Ea = (uint32_t **)calloc((size_t)np + 1, sizeof(uint32_t *));
+    Eb = (uint32_t **)calloc((size_t)np + 1, sizeof(uint32_t *));
+    prev = (int *)malloc(sizeof(int) * ((size_t)np + 1));
+    next = (int *)malloc(sizeof(int) * ((size_t)np + 1));
+    partner = (int *)malloc(sizeof(int) * ((size_t)np + 1));
+    if (!Fa || !Fb || !Ea || !Eb || !prev || !next || !partner) { status = FBO_E_ALLOC; goto done; }
+    for (int q = 0; q < np; ++q) {
+        Fa[q] = (int32_t *)malloc(fpix * 2 * sizeof(int32_t));
+        Fb[q] = (int32_t *)malloc(fpix * 2 * sizeof(int32_t));
+        Ea[q] = (uint32_t *)malloc(fpix * sizeof(uint32_t));
+        Eb[q] = (uint32_t *)malloc(fpix * sizeof(uint32_t));
+        if (!Fa[q] || !Fb[q] || !Ea[q] || !Eb[q]) { status = FBO_E_ALLOC; goto done; }
+        prev[q] = next[q] = partner[q] = -1;
+        for (int t = 0; t < np; ++t) {
+            if (pk[t] == pk[q] && pf[t] == pf[q] - 1) prev[q] = t;
+            if (pk[t] == pk[q] && pf[t] == pf[q] + 1) next[q] = t;
+            if (t != q && pf[t] == pf[q]) partner[q] = t;
+        }
+    }
+    for (int l = levels - 1; l >= 0; --l) {
+        int hl = hs[l], wl = ws[l];
+        for (int q = 0; q < np; ++q) {
+            const uint8_t *Gs = G[(size_t)keys[pk[q]] * levels + l], *Gt = G[(size_t)pf[q] * levels + l];
+            uint32_t pid = (uint32_t)(keys[pk[q]] * N + pf[q]);
+            if (l == levels - 1) {
+                fbo_nnf_init_random(Gs, Gt, hl, wl, p, l, seed, pid, Fa[q], Ea[q]);
+            } else {
+                fbo_nnf_upsample(Fa[q], hs[l + 1], ws[l + 1], Gs, Gt, hl, wl, p, Fb[q], Eb[q]);
+                int32_t *tf = Fa[q]; Fa[q] = Fb[q]; Fb[q] = tf;
+                uint32_t *te = Ea[q]; Ea[q] = Eb[q]; Eb[q] = te;
+            }
+        }
+        for (int it = 0; it < iters; ++it) {
+            for (int q = 0; q < np; ++q) {
+                const uint8_t *Gs = G[(size_t)keys[pk[q]] * levels + l], *Gt = G[(size_t)pf[q] * levels + l];
+                const uint8_t *Ss = KS[(size_t)pk[q] * levels + l];
+                const uint8_t *Sp = partner[q] >= 0 ? KS[(size_t)pk[partner[q]] * levels + l] : Ss;
+                fbo_pm_iteration_ext(Gs, Gt, Ss, Sp, hl, wl, p, alpha16, flags, l, it, seed,
+                                     (uint32_t)(keys[pk[q]] * N + pf[q]), (const int32_t *const *)Fa,
+                                     (const uint32_t *const *)Ea, q, prev[q], next[q], partner[q], Fb[q], Eb[q]);
+            }
+            for (int q = 0; q < np; ++q) {
+                int32_t *tf = Fa[q]; Fa[q] = Fb[q]; Fb[q] = tf;
+                uint32_t *te = Ea[q]; Ea[q] = Eb[q]; Eb[q] = te;
+            }
+        }
+    }
+    /* Eq. (9) with the final fields */
+    for (int i = 0, q = 0; i < N; ++i) {
+        double *o = out + (size_t)i * n3;
+        if (kself[i] >= 0) {
+            for (size_t t = 0; t < n3; ++t) o[t] = key_styles[(size_t)kself[i] * n3 + t] / 255.0;
+            continue;
+        }
+        for (size_t t = 0; t < n3; ++t) o[t] = 0.0;
+        const int both = kl[i] >= 0 && kr[i] >= 0;
+        for (int side = 0; side < 2; ++side) {
+            int k = side == 0 ? kl[i] : kr[i];
+            if (k < 0) continue;
+            double wgt = 1.0;
+            if (both) {
+                int lk = keys[kl[i]], rk = keys[kr[i]];
+                wgt = side == 0 ? (double)(rk - i) / (double)(rk - lk) : (double)(i - lk) / (double)(rk - lk);
+            }
+            fbo_remap(key_styles + (size_t)k * n3, Fa[q], h, w, p, tmp);
+            for (size_t t = 0; t < n3; ++t) o[t] += wgt * tmp[t];
+            ++q;
+        }
+    }
+done:
+    if (G) for (int i = 0; i < N; ++i) for (int l = 1; l < levels; ++l) free(G[(size_t)i * levels + l]);
+    if (KS) for (int k = 0; k < n_keys; ++k) for (int l = 1; l < levels; ++l) free(KS[(size_t)k * levels + l]);
+    if (Fa) for (int q = 0; q < np; ++q) { free(Fa[q]); free(Fb[q]); free(Ea[q]); free(Eb[q]); }
+    free(G); free(KS); free(Fa); free(Fb); free(Ea); free(Eb); free(prev); free(next); free(partner);
+    free(pk); free(pf); free(kself); free(kl); free(kr); free(tmp);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Keyframe interpolation, Eq. (9): for l < i < r (l, r the bracketing keys) */
 /* out_i = (r-i)/(r-l) (S_l -> S_i) + (i-l)/(r-l) (S_r -> S_i); keyframes    */
 /* are passed through unchanged (Section 3.5).  Reading for frames before    */
