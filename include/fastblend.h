@@ -82,6 +82,19 @@ typedef enum {
  * Needs iters >= 1 and 0 <= alpha16 <= 512.  Taken by fb_blend_window only;
  * not with FB_STYLE_LOSS or FB_FAST_BLEND. */
 #define FB_ACCURATE_BLEND 0x20u
+/* Interpolation extras (Section 3.5), taken by fb_interpolate only.  All
+ * NNF(G_k, G_i) of the call are estimated together, level by level and
+ * iteration by iteration, each reading the previous iteration's fields.
+ * FB_TRACKING: NNF(G_k, G_i) also tries the matches of NNF(G_k, G_{i-1}) and
+ * NNF(G_k, G_{i+1}) at the same pixel (when those pairs exist), after the
+ * propagation candidates.  FB_ALIGN: the two keyframe fields F_l, F_r of a
+ * frame between keys minimise the pairwise alignment loss of Eq. 10,
+ * alpha ||G_a[u] - G_i[v]||^2 + ||S_a[u] - S_b[F_b(v)]||^2 (a, b the two keys,
+ * S the keyframe styles, F_b the partner's previous field), re-scoring the
+ * incumbent every iteration; energies are the loss x 16, alpha = alpha16 / 16,
+ * 1 <= alpha16 <= 512, iters >= 1; frames with one key keep Eq. 1. */
+#define FB_TRACKING 0x40u
+#define FB_ALIGN 0x80u
 
 /* PatchMatch parameters (Algorithm 1).  The paper names p, n and the pyramid
  * but gives no values; 2 / 3 / 6 are the values of the 512x512 blending

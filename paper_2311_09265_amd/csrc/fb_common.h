@@ -63,8 +63,12 @@ struct PMJob {
     const uint32_t *e_abi;     // ABI energies (start mode 4)
     int32_t *nnf_abi;          // export destinations
     uint32_t *energy_abi;
-    const uint32_t *src_sty;   // Eq. 3 loss: padded pixels of the source style level
-    uint32_t *sty_hat;         // Eq. 3 loss: the remapped style S^, padded like the level
+    const uint32_t *src_sty;   // Eq. 3 / 8 / 10 losses: padded pixels of the source style level
+    uint32_t *sty_hat;         // Eq. 3 loss: the remapped style S^ (Eq. 8: T^-), padded like the level
+    const uint32_t *trk_prev;  // tracking: packed fields of the pairs with the same source and the
+    const uint32_t *trk_next;  //   previous / next target frame (nullptr: none)
+    const uint32_t *pair_f;    // Eq. 10: the partner pair's packed field (nullptr: not aligned)
+    const uint32_t *pair_sty;  // Eq. 10: padded pixels of the partner's source style level
     int32_t h, w, pitch;       // level size; row pitch in pixels
     int32_t hc, wc;            // coarse size for upsampling
     uint32_t pair_id;
@@ -117,10 +121,12 @@ hipError_t launch_downsample(const uint8_t *base, size_t stride, int n, const Le
 
 hipError_t launch_pm_start(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
                            TileCfg cfg, int p, uint64_t seed, hipStream_t s);
-// style: the Eq. 3 loss (guide + style against sty_hat), which re-scores the
-// incumbent instead of reading e_in
+// mode bit kIterStyle: the guide + style loss (Eq. 3 / 8 against sty_hat, or
+// Eq. 10 against the partner's patch when pair_f is set), which re-scores the
+// incumbent instead of reading e_in; bit kIterTrack: tracking candidates
+enum IterMode : int { kIterPlain = 0, kIterStyle = 1, kIterTrack = 2 };
 hipError_t launch_pm_iter(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
-                          TileCfg cfg, int p, int iter, uint64_t seed, bool style, hipStream_t s);
+                          TileCfg cfg, int p, int iter, uint64_t seed, int mode, hipStream_t s);
 // S^ = Alg. 2 remap of src_sty through f_in, rounded, into sty_hat (border replicated)
 hipError_t launch_style_refresh(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
                                 TileCfg cfg, int p, hipStream_t s);

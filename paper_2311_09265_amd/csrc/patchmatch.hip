@@ -239,15 +239,20 @@ k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unif
     gstore<uint32_t>(J.e_out, 4u * v, patch_loss<P>(J.src_px, 4u * (uint32_t)(fr * J.pitch + fc), pitch_b, t));
 }
 
-// STYLE: the guide + style loss of Eq. 3, scaled by 16 to stay an integer,
-//   alpha16 SSD(G_j[u], G_i[v]) + 16 SSD(S_j[u], S^[v]),
-// with S^ the remapped style of the current field (refreshed by
-// k_style_refresh before every iteration launch).  The incumbent is re-scored
-// under that S^ instead of taking e_in.
-template <int P, int TW, int TH, bool STYLE>
+// MODE & kIterStyle: a guide + style loss scaled by 16 to stay an integer,
+//   alpha16 SSD(G_j[u], G_i[v]) + 16 SSD(S_j[u], X),
+// where X is the patch of sty_hat at v (Eq. 3: the remapped style S^,
+// refreshed by k_style_refresh before every iteration launch; Eq. 8: the
+// fixed average T^-), or, when pair_f is set, the partner's source-style
+// patch at the partner's current match (Eq. 10, the pairwise patch error).
+// The incumbent is re-scored under X instead of taking e_in.
+// MODE & kIterTrack: after propagation, the matches of the pairs with the
+// same source and the neighbouring target frames are candidates too.
+template <int P, int TW, int TH, int MODE>
 __global__ void __launch_bounds__(TW *TH)
 k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles, int iter,
           uint32_t k0, uint32_t k1) {
+    constexpr bool STYLE = (MODE & kIterStyle) != 0, TRACK = (MODE & kIterTrack) != 0;
     const TileCoord tc = locate<TW, TH>(jobs, n_jobs, total_tiles, uniform_tiles);
     if (!tc.active) return;
     const PMJob &J = jobs[tc.job];
@@ -262,7 +267,14 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     load_target_patch<P>(J.tgt_px, 4u * (uint32_t)(r * pitch + c), pitch_b, t);
     const uint32_t *src_sty = J.src_sty;
     const uint32_t a16 = STYLE ? (uint32_t)J.alpha16 : 1u;
-    if constexpr (STYLE) load_target_patch<P>(J.sty_hat, 4u * (uint32_t)(r * pitch + c), pitch_b, ts);
+    if constexpr (STYLE) {
+        if (J.pair_f) {
+            const uint32_t q = gload<uint32_t>(J.pair_f, 4u * v);
+            load_target_patch<P>(J.pair_sty, 4u * (uint32_t)((int)(q >> 16) * pitch + (int)(q & 0xFFFFu)), pitch_b, ts);
+        } else {
+            load_target_patch<P>(J.sty_hat, 4u * (uint32_t)(r * pitch + c), pitch_b, ts);
+        }
+    }
 
     const uint32_t f0 = gload<uint32_t>(f_in, 4u * v);
     int br = (int)(f0 >> 16), bc = (int)(f0 & 0xFFFFu);
@@ -334,6 +346,16 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     if (c < w - 1) {
         const uint32_t q = gload<uint32_t>(f_in, 4u * (v + 1));
         consider((int)(q >> 16), max((int)(q & 0xFFFFu) - 1, 0));
+    }
+    if constexpr (TRACK) {
+        if (J.trk_prev) {
+            const uint32_t q = gload<uint32_t>(J.trk_prev, 4u * v);
+            consider((int)(q >> 16), (int)(q & 0xFFFFu));
+        }
+        if (J.trk_next) {
+            const uint32_t q = gload<uint32_t>(J.trk_next, 4u * v);
+            consider((int)(q >> 16), (int)(q & 0xFFFFu));
+        }
     }
 
     // random search around the running best, radius halving from max(h, w)
@@ -462,18 +484,23 @@ hipError_t launch_pm_start(const PMJob *jobs, int n_jobs, int total_tiles, int u
 }
 
 hipError_t launch_pm_iter(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
-                          TileCfg cfg, int p, int iter, uint64_t seed, bool style, hipStream_t s) {
+                          TileCfg cfg, int p, int iter, uint64_t seed, int mode, hipStream_t s) {
     if (total_tiles <= 0) return hipSuccess;
+    if (mode < 0 || mode > 3) return hipErrorInvalidValue;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-#define FB_ITER2(P_, TW, TH)                                                                           \
-    if (style) hipLaunchKernelGGL((k_pm_iter<P_, TW, TH, true>), dim3(total_tiles), dim3(TW, TH), 0, s, \
-                                  jobs, n_jobs, total_tiles, uniform_tiles, iter, k0, k1);             \
-    else hipLaunchKernelGGL((k_pm_iter<P_, TW, TH, false>), dim3(total_tiles), dim3(TW, TH), 0, s,     \
-                            jobs, n_jobs, total_tiles, uniform_tiles, iter, k0, k1)
+#define FB_ITER3(P_, TW, TH, M_)                                                                        \
+    hipLaunchKernelGGL((k_pm_iter<P_, TW, TH, M_>), dim3(total_tiles), dim3(TW, TH), 0, s, jobs, n_jobs, \
+                       total_tiles, uniform_tiles, iter, k0, k1)
+#define FB_ITER2(P_, TW, TH)                                                   \
+    if (mode == 0) FB_ITER3(P_, TW, TH, 0);                                    \
+    else if (mode == 1) FB_ITER3(P_, TW, TH, 1);                               \
+    else if (mode == 2) FB_ITER3(P_, TW, TH, 2);                               \
+    else FB_ITER3(P_, TW, TH, 3)
 #define FB_ITER(TW, TH) FB_P_SWITCH(p, FB_ITER2, TW, TH)
     FB_TILE_SWITCH(cfg, FB_ITER)
 #undef FB_ITER
 #undef FB_ITER2
+#undef FB_ITER3
     return hipGetLastError();
 }
 

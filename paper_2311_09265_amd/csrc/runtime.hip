@@ -59,7 +59,7 @@ struct Plan {
     bool has_tune = false;
     std::vector<PMJob> tune_jobs;
     int tune_iter = 0;
-    bool tune_style = false;
+    int tune_mode = kIterPlain;
     std::string tune_key;
 };
 
@@ -92,17 +92,16 @@ void assign_tiles(std::vector<PMJob> &jobs, TileCfg cfg, int *total, int *unifor
     *uniform = uni > 0 ? uni : 0;
 }
 
-enum LaunchKind { kLaunchStart, kLaunchIter, kLaunchStyleIter, kLaunchStyleRefresh, kLaunchExport };
+enum LaunchKind { kLaunchStart, kLaunchIter, kLaunchStyleRefresh, kLaunchExport };
 
 void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cfg, int p,
-                   uint64_t seed, int iter) {
+                   uint64_t seed, int iter, int mode = kIterPlain) {
     if (jobs.empty()) return;
     int total = 0, uniform = 0;
     assign_tiles(jobs, cfg, &total, &uniform);
     const size_t off = table_append(P, jobs.data(), jobs.size());
     const int n = (int)jobs.size();
-    sig_add(P, "pm", kind, (long long)off, n, ((long long)iter << 32) | (cfg.tw << 8) | cfg.th);
-    const bool style = kind == kLaunchStyleIter;
+    sig_add(P, "pm", kind * 16 + mode, (long long)off, n, ((long long)iter << 32) | (cfg.tw << 8) | cfg.th);
     switch (kind) {
     case kLaunchStart:
         P.ops.push_back({FB_KERNEL_PM_START, [=](hipStream_t s, const uint8_t *tab) {
@@ -111,10 +110,9 @@ void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cf
         }});
         break;
     case kLaunchIter:
-    case kLaunchStyleIter:
         P.ops.push_back({FB_KERNEL_PM_ITER, [=](hipStream_t s, const uint8_t *tab) {
             return launch_pm_iter(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform,
-                                  cfg, p, iter, seed, style, s);
+                                  cfg, p, iter, seed, mode, s);
         }});
         break;
     case kLaunchStyleRefresh:
@@ -170,6 +168,9 @@ struct PairSpec {
     const uint8_t *src_sty_pyr;  // Eq. 3 / Eq. 8 loss: pyramid of the source style frame
     uint32_t *sty_hat;         // Eq. 3 loss: padded S^ buffer (level-0 capacity)
     const uint8_t *tbar_pyr;   // Eq. 8 loss: pyramid of the fixed target T^- (instead of S^)
+    int trk_prev = -1, trk_next = -1;  // tracking: pairs with the same source, adjacent targets
+    int partner = -1;                  // Eq. 10: the pair it is aligned with
+    const uint8_t *partner_sty_pyr = nullptr;  // Eq. 10: the partner's source style pyramid
     int final_buf;             // filled by the planner
 };
 
@@ -218,8 +219,11 @@ std::string tune_key_of(const std::vector<PairSpec> &pairs, int p) {
 // every iteration launch is preceded by the refresh of the pairs' S^ from the
 // field the iteration starts from.  With the Eq. 8 loss (style and
 // fixed_target) the second patch is each pair's fixed T^-: no refresh.
+// Tracking (track) and the pairwise alignment loss (align, pairs with a
+// partner) read the fields the other pairs start the same iteration from.
 void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, uint64_t seed,
-                     TileCfg cfg, bool style = false, int alpha16 = 0, bool fixed_target = false) {
+                     TileCfg cfg, bool style = false, int alpha16 = 0, bool fixed_target = false,
+                     bool track = false, bool align = false) {
     int kmax = 0;
     for (const PairSpec &ps : pairs) kmax = std::max(kmax, ps.L.levels);
     std::vector<int> cur(pairs.size(), 0);
@@ -261,25 +265,39 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
                 }
                 add_pm_launch(P, kLaunchStyleRefresh, js, cfg, p, seed, it);
             }
-            js.clear();
+            // every pair reads the fields all pairs start this iteration from
+            std::vector<const uint32_t *> fin(pairs.size(), nullptr);
+            for (size_t k : active) fin[k] = pairs[k].f[cur[k]];
+            std::vector<PMJob> js_style, js_plain;
             for (size_t k : active) {
                 PairSpec &ps = pairs[k];
                 PMJob j = job_geom(ps, l);
-                j.f_in = ps.f[cur[k]];
+                j.f_in = fin[k];
                 j.e_in = ps.e[cur[k]];
                 j.f_out = ps.f[cur[k] ^ 1];
                 j.e_out = ps.e[cur[k] ^ 1];
                 j.alpha16 = alpha16;
-                cur[k] ^= 1;
-                js.push_back(j);
+                if (track) {
+                    j.trk_prev = ps.trk_prev >= 0 ? fin[ps.trk_prev] : nullptr;
+                    j.trk_next = ps.trk_next >= 0 ? fin[ps.trk_next] : nullptr;
+                }
+                const bool aligned = align && ps.partner >= 0;
+                if (aligned) {
+                    j.pair_f = fin[ps.partner];
+                    j.pair_sty = reinterpret_cast<const uint32_t *>(ps.partner_sty_pyr + ps.L.lv[l].px_off);
+                }
+                ((style || aligned) ? js_style : js_plain).push_back(j);
             }
+            for (size_t k : active) cur[k] ^= 1;
+            const int tmode = track ? kIterTrack : kIterPlain;
             if (l == 0 && it == iters - 1) {
                 P.has_tune = true;
-                P.tune_jobs = js;
+                P.tune_jobs = js_style.empty() ? js_plain : js_style;
                 P.tune_iter = it;
-                P.tune_style = style;
+                P.tune_mode = js_style.empty() ? tmode : (tmode | kIterStyle);
             }
-            add_pm_launch(P, style ? kLaunchStyleIter : kLaunchIter, js, cfg, p, seed, it);
+            add_pm_launch(P, kLaunchIter, js_style, cfg, p, seed, it, tmode | kIterStyle);
+            add_pm_launch(P, kLaunchIter, js_plain, cfg, p, seed, it, tmode);
         }
     }
     std::vector<PMJob> ex;
@@ -406,11 +424,11 @@ fb_status autotune(fb_ctx *ctx, Plan &P, hipStream_t s, int p, uint64_t seed) {
         const PMJob *dj = reinterpret_cast<const PMJob *>(ctx->tune_table.p);
         // reruns of the last iteration read what it read and write what it wrote
         FB_HIP(launch_pm_iter(dj, (int)jobs.size(), total, uniform, tile_cfg(c), p, P.tune_iter, seed,
-                              P.tune_style, s));
+                              P.tune_mode, s));
         FB_HIP(hipEventRecord(e0, s));
         for (int rep = 0; rep < 3; ++rep)
             FB_HIP(launch_pm_iter(dj, (int)jobs.size(), total, uniform, tile_cfg(c), p, P.tune_iter, seed,
-                                  P.tune_style, s));
+                                  P.tune_mode, s));
         FB_HIP(hipEventRecord(e1, s));
         FB_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -600,9 +618,10 @@ fb_status check_params(const fb_params *prm, bool need_levels) {
         return fail(FB_E_INVALID, "levels must be in [1, 16]");
     if (prm->iters < 0 || prm->iters > 0xFFFE) return fail(FB_E_INVALID, "iters must be in [0, 65534]");
     if (prm->reserved != 0) return fail(FB_E_INVALID, "params->reserved must be 0");
-    if (prm->flags & (FB_STYLE_LOSS | FB_ACCURATE_BLEND)) {
-        if (prm->iters < 1) return fail(FB_E_INVALID, "FB_STYLE_LOSS and FB_ACCURATE_BLEND need iters >= 1");
+    if (prm->flags & (FB_STYLE_LOSS | FB_ACCURATE_BLEND | FB_ALIGN)) {
+        if (prm->iters < 1) return fail(FB_E_INVALID, "FB_STYLE_LOSS, FB_ACCURATE_BLEND and FB_ALIGN need iters >= 1");
         if (prm->alpha16 < 0 || prm->alpha16 > 512) return fail(FB_E_INVALID, "alpha16 must be in [0, 512]");
+        if ((prm->flags & FB_ALIGN) && prm->alpha16 < 1) return fail(FB_E_INVALID, "FB_ALIGN needs alpha16 >= 1");
     }
     return FB_OK;
 }
@@ -1159,8 +1178,8 @@ fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, i
     if (st) return st;
     if (!guides || !key_idx || !key_styles || !out) return fail(FB_E_INVALID, "null pointer");
     if ((st = check_size(h, w)) || (st = check_params(params, true))) return st;
-    if (params->flags & FB_STYLE_LOSS)
-        return fail(FB_E_UNSUPPORTED, "FB_STYLE_LOSS is taken by fb_blend_window and fb_patchmatch_batch only");
+    if (params->flags & (FB_STYLE_LOSS | FB_FAST_BLEND | FB_ACCURATE_BLEND))
+        return fail(FB_E_UNSUPPORTED, "fb_interpolate takes FB_TRACKING and FB_ALIGN, not the blend's loss or modes");
     if (n_frames < 1 || n_keys < 1) return fail(FB_E_INVALID, "need n_frames >= 1 and n_keys >= 1");
     for (int k = 0; k < n_keys; ++k) {
         if (key_idx[k] < 0 || key_idx[k] >= n_frames) return fail(FB_E_INVALID, "key index out of range");
@@ -1183,8 +1202,12 @@ fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, i
     size_t n_pairs = 0;
     for (int i = 0; i < N; ++i)
         if (kself[i] < 0) n_pairs += (kl[i] >= 0) + (kr[i] >= 0);
+    const bool track = params->flags & FB_TRACKING, align = params->flags & FB_ALIGN;
+    // with the alignment loss the keyframe styles get whole pyramids (level 0
+    // of a pyramid is laid out as a padded frame)
+    const size_t kbytes = align ? L.bytes : sbytes;
     if ((st = ensure(ctx, ctx->pyr, (size_t)N * L.bytes)) ||
-        (st = ensure(ctx, ctx->style, (size_t)n_keys * sbytes)) ||
+        (st = ensure(ctx, ctx->style, (size_t)n_keys * kbytes)) ||
         (st = ensure(ctx, ctx->fe, std::max<size_t>(n_pairs, 1) * npx * 16)))
         return st;
     uint8_t *pyr = static_cast<uint8_t *>(ctx->pyr.p);
@@ -1193,7 +1216,8 @@ fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, i
 
     Plan P;
     plan_pyramids(P, guides, N, h, w, L, pyr, L.bytes);
-    plan_style_pack(P, key_styles, n_keys, h, w, p, sty, sbytes, pitch);
+    if (align) plan_pyramids(P, key_styles, n_keys, h, w, L, sty, L.bytes);
+    else plan_style_pack(P, key_styles, n_keys, h, w, p, sty, sbytes, pitch);
     std::vector<PairSpec> pairs;
     std::vector<int> pair_key;
     for (int i = 0; i < N; ++i) {
@@ -1211,14 +1235,32 @@ fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, i
             ps.f[1] = fe + (n_pairs + q) * npx;
             ps.e[0] = fe + (2 * n_pairs + q) * npx;
             ps.e[1] = fe + (3 * n_pairs + q) * npx;
+            if (align) ps.src_sty_pyr = sty + (size_t)k * kbytes;
             pairs.push_back(ps);
             pair_key.push_back(k);
         }
     }
+    // tracking neighbours (same key, adjacent target frames) and alignment
+    // partners (same target frame, the other key)
+    std::vector<int> pair_frame;
+    for (int i = 0, q = 0; i < N; ++i) {
+        if (kself[i] >= 0) continue;
+        for (int side = 0; side < 2; ++side)
+            if ((side == 0 ? kl[i] : kr[i]) >= 0) { pair_frame.push_back(i); ++q; }
+    }
+    for (size_t a = 0; a < pairs.size(); ++a)
+        for (size_t b = 0; b < pairs.size(); ++b) {
+            if (pair_key[b] == pair_key[a] && pair_frame[b] == pair_frame[a] - 1) pairs[a].trk_prev = (int)b;
+            if (pair_key[b] == pair_key[a] && pair_frame[b] == pair_frame[a] + 1) pairs[a].trk_next = (int)b;
+            if (b != a && pair_frame[b] == pair_frame[a]) {
+                pairs[a].partner = (int)b;
+                if (align) pairs[a].partner_sty_pyr = sty + (size_t)pair_key[b] * kbytes;
+            }
+        }
     if (params->flags & FB_LEARNED_SEED)
         if ((st = plan_learned_seeds(ctx, P, pairs))) return st;
     const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
-    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg);
+    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg, false, params->alpha16, false, track, align);
 
     std::vector<RemapTerm> terms;
     std::vector<RemapFrame> frames;
@@ -1226,7 +1268,7 @@ fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, i
     for (int i = 0; i < N; ++i) {
         RemapFrame fr{out + (size_t)i * npx * 3, (int32_t)terms.size(), 0, 1.0f, 0};
         if (kself[i] >= 0) {
-            terms.push_back(RemapTerm{reinterpret_cast<const uint32_t *>(sty + (size_t)kself[i] * sbytes),
+            terms.push_back(RemapTerm{reinterpret_cast<const uint32_t *>(sty + (size_t)kself[i] * kbytes),
                                       nullptr, 1.0f, 0});
         } else {
             const bool both = kl[i] >= 0 && kr[i] >= 0;
@@ -1236,7 +1278,7 @@ fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, i
                 if (k < 0) continue;
                 float wgt = 1.0f;
                 if (both) wgt = side == 0 ? (float)(r - i) / (float)(r - l) : (float)(i - l) / (float)(r - l);
-                terms.push_back(RemapTerm{reinterpret_cast<const uint32_t *>(sty + (size_t)pair_key[q] * sbytes),
+                terms.push_back(RemapTerm{reinterpret_cast<const uint32_t *>(sty + (size_t)pair_key[q] * kbytes),
                                           pairs[q].f[pairs[q].final_buf], wgt, 0});
                 ++q;
             }

@@ -26,6 +26,8 @@ FB_LEARNED_SEED = 0x4
 FB_STYLE_LOSS = 0x8
 FB_FAST_BLEND = 0x10
 FB_ACCURATE_BLEND = 0x20
+FB_TRACKING = 0x40
+FB_ALIGN = 0x80
 STATUS = {0: "FB_OK", -1: "FB_E_INVALID", -2: "FB_E_SHAPE", -3: "FB_E_UNSUPPORTED",
           -4: "FB_E_ALLOC", -5: "FB_E_HIP"}
 
