@@ -21,6 +21,8 @@ Prints one JSON line:
   fast_mode  the fast-mode blend (tables and queries, Alg. 3-5) against the
              balanced one at window radius 5 and 15
   accurate_mode  the accurate-mode blend (Eq. 7-8)
+  interpolation  the 1024x576 keyframe interpolation (Eq. 9), plain, with
+             tracking, and with tracking + pairwise alignment (Eq. 10)
 """
 from __future__ import annotations
 
@@ -255,6 +257,36 @@ def bench_accurate(ctx, fbm, g, s, out, M, p, levels, iters, seed, args, N):
             "kernel_ms_per_step": {k: round(v[1] / steps, 3) for k, v in prof.items() if v[0]}}
 
 
+def bench_interp(ctx, fbm, args):
+    """The interpolation workload (64 frames of 1024x576, keyframes every 16
+    frames, 4 levels x 6 iterations; Eq. 9): plain, with tracking, and with
+    tracking + the pairwise alignment loss (Eq. 10, alpha = 1)."""
+    import torch
+    from paper_2311_09265_amd import synth
+    guides, keys, key_styles = synth.interp_workload()
+    N, h, w = guides.shape[:3]
+    g = torch.from_numpy(guides).cuda()
+    ks = torch.from_numpy(key_styles).cuda()
+    out = torch.empty((N, h, w, 3), dtype=torch.float32, device=g.device)
+    seed = synth.PHILOX_SEED[3]
+    res = {"workload": "interpolation %d frames %dx%d, keys %s, 4 levels x 6 iterations" % (N, w, h, [int(k) for k in keys])}
+    for name, flags in (("plain", 0), ("tracking", fbm.FB_TRACKING),
+                        ("tracking_align", fbm.FB_TRACKING | fbm.FB_ALIGN)):
+        prm = fbm.make_params(2, 4, 6, seed, flags, 16)
+        ctx.fb_interpolate(g, list(keys), ks, prm, out=out)
+        torch.cuda.synchronize()
+        steps = max(1, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.fb_interpolate(g, list(keys), ks, prm, out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        res[name] = {"ms_per_call": round(ms, 3), "frames_per_s": round(N / (ms / 1e3), 3)}
+        log("interpolation %s: %.2f ms per call" % (name, ms))
+    del g, ks, out
+    return res
+
+
 def iter_kernel_traffic():
     """HBM bytes per launch of the PatchMatch iteration kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
@@ -288,6 +320,7 @@ def main():
     ap.add_argument("--no-style", action="store_true", help="skip the Eq. 3 (guide + style loss) comparison")
     ap.add_argument("--no-fast", action="store_true", help="skip the fast-mode comparison")
     ap.add_argument("--no-accurate", action="store_true", help="skip the accurate-mode timing")
+    ap.add_argument("--no-interp", action="store_true", help="skip the interpolation timings")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (counter calibration)")
     args = ap.parse_args()
@@ -363,6 +396,10 @@ def main():
     if not args.no_fast:
         fast = bench_fast(ctx, fbm, g, s, out, p, levels, iters, seed, args, N, h, w)
 
+    interp = None
+    if not args.no_interp:
+        interp = bench_interp(ctx, fbm, args)
+
     accurate = None
     if not args.no_accurate:
         accurate = bench_accurate(ctx, fbm, g, s, out, M, p, levels, iters, seed, args, N)
@@ -429,6 +466,7 @@ def main():
         "style_loss": style,
         "fast_mode": fast,
         "accurate_mode": accurate,
+        "interpolation": interp,
     }
     if learned:
         learned["speedup_vs_plain"] = round(ms / learned["ms_per_step"], 3)
