@@ -134,7 +134,9 @@ fb_status fb_set_tile_config(fb_ctx *ctx, int32_t index);
 /* 2x2 box filter with round-half-up, ceil sizes, clamped reads.  The      */
 /* pyramid is an opaque device buffer of fb_pyramid_bytes(h,w,levels,p)    */
 /* bytes allocated by the caller; it holds every level as 4-byte pixels   */
-/* with a border of p replicated pixels (p = patch radius).                */
+/* with a border of p replicated pixels (p = patch radius), each followed  */
+/* by a table of per-block ranges of the (2p+1)^2 patch sums (at most     */
+/* 16 KiB) that lets PatchMatch rule candidates out before reading them.  */
 /* ---------------------------------------------------------------------- */
 size_t fb_pyramid_bytes(int32_t h, int32_t w, int32_t levels, int32_t patch_radius);
 fb_status fb_build_pyramid(fb_ctx *ctx, const uint8_t *rgb, int32_t h, int32_t w,

@@ -7,6 +7,13 @@
 //   side (so a patch read never needs clamping), row pitch rounded up to 16
 //   pixels.  A (2p+1)-pixel patch row is one 16-byte + one 4-byte aligned
 //   load for p = 2.
+//   Each level is followed by its bound table: for every block of
+//   2^tab_shift x 2^tab_shift patch positions, the range [mn_c, mx_c] of
+//   each channel's (2p+1)^2 patch sum over the block, as three arrays of
+//   16-bit pairs (lower half first): (mn_R, mn_G), (mn_B, -mx_R),
+//   (-mx_G, -mx_B), each tab_w * tab_h words.  The block size is the
+//   smallest from 8 x 8 up whose table fits kBoundTabBytes, so one table
+//   always fits a workgroup's LDS.
 // * Style frames: the same format at full resolution (one aligned 4-byte
 //   gather per remapped pixel).
 // * NNFs inside the library are one uint32 per pixel: (row << 16) | col.
@@ -22,12 +29,17 @@ namespace fb {
 constexpr int kMaxLevels = 16;
 constexpr int kMaxP = 4;
 constexpr int kPitchAlign = 16;  // pixels
+constexpr int kBoundTabBytes = 16384;  // largest bound table of one level
+constexpr int kBoundTabMinShift = 3;   // smallest bound-table block: 8 x 8 positions
 
 struct LevelGeom {
     int32_t h, w;        // level size
     int32_t pitch;       // padded row pitch in pixels
     int32_t rows;        // padded rows = h + 2p
     size_t px_off;       // byte offset of the level in the pyramid
+    size_t tab_off;      // byte offset of the level's bound table
+    int32_t tab_shift;   // bound-table block side = 1 << tab_shift positions
+    int32_t tab_w, tab_h;  // bound-table size in blocks
 };
 
 struct PyrLayout {
@@ -77,7 +89,9 @@ struct PMJob {
     int32_t tile_base;         // first flat tile of this job in the launch
     int32_t tiles_x;           // tiles along w
     int32_t alpha16;           // Eq. 3 loss: guide weight alpha = alpha16 / 16
-    int32_t pad_;
+    int32_t tab_shift;         // bound table of the source level (see the layout above):
+    int32_t tab_w, tab_n;      //   block shift, width in blocks, entries (0: no table)
+    const uint32_t *btab;
 };
 static_assert(sizeof(PMJob) % 8 == 0, "PMJob is copied as an array");
 
@@ -118,6 +132,8 @@ hipError_t launch_pack_rgbx(const uint8_t *rgb, size_t rgb_stride, int n, int h,
                             hipStream_t s);
 hipError_t launch_downsample(const uint8_t *base, size_t stride, int n, const LevelGeom &in,
                              const LevelGeom &out, int p, hipStream_t s);
+// bound tables of every level of n pyramids at base + f * stride (after the levels are built)
+hipError_t launch_bound_tables(uint8_t *base, size_t stride, int n, const PyrLayout &L, hipStream_t s);
 
 hipError_t launch_pm_start(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
                            TileCfg cfg, int p, uint64_t seed, hipStream_t s);
@@ -125,8 +141,10 @@ hipError_t launch_pm_start(const PMJob *jobs, int n_jobs, int total_tiles, int u
 // Eq. 10 against the partner's patch when pair_f is set), which re-scores the
 // incumbent instead of reading e_in; bit kIterTrack: tracking candidates
 enum IterMode : int { kIterPlain = 0, kIterStyle = 1, kIterTrack = 2 };
+// tab_bytes: LDS for the largest bound table among the jobs (12 * max tab_n)
 hipError_t launch_pm_iter(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
-                          TileCfg cfg, int p, int iter, uint64_t seed, int mode, hipStream_t s);
+                          TileCfg cfg, int p, int iter, uint64_t seed, int mode, int tab_bytes,
+                          hipStream_t s);
 // S^ = Alg. 2 remap of src_sty through f_in, rounded, into sty_hat (border replicated)
 hipError_t launch_style_refresh(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
                                 TileCfg cfg, int p, hipStream_t s);

@@ -36,6 +36,8 @@
 // high 16 bits, a 16-bit draw u mapping to [0, n) as (u * n) >> 16.  The
 // initial draw uses iteration 0xFFFF and word 0.  Draws never depend on the
 // position of a pair in a batch or on the tile shape.
+#include <type_traits>
+
 #include "fb_common.h"
 
 namespace fb {
@@ -90,6 +92,9 @@ template <class T>
 using gptr_mut = __attribute__((address_space(1))) T *;
 
 // (a C-style cast is the one that may change the address space)
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
 template <class T>
 __device__ __forceinline__ T gload(const void *base, uint32_t byte_off) {
     return *(gptr<T>)((gptr<char>)base + byte_off);
@@ -248,14 +253,25 @@ k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unif
 // The incumbent is re-scored under X instead of taking e_in.
 // MODE & kIterTrack: after propagation, the matches of the pairs with the
 // same source and the neighbouring target frames are candidates too.
+// Every launch stages the source level's bound table (the per-block ranges
+// of the candidates' per-channel patch sums, built with the pyramid) in LDS:
+// a candidate whose Cauchy-Schwarz bound already reaches the running best is
+// ruled out before any of its pixels is fetched.
 template <int P, int TW, int TH, int MODE>
 __global__ void __launch_bounds__(TW *TH)
 k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles, int iter,
           uint32_t k0, uint32_t k1) {
     constexpr bool STYLE = (MODE & kIterStyle) != 0, TRACK = (MODE & kIterTrack) != 0;
+    extern __shared__ uint32_t s_btab[];  // the three 16-bit-pair arrays of the bound table
     const TileCoord tc = locate<TW, TH>(jobs, n_jobs, total_tiles, uniform_tiles);
-    if (!tc.active) return;
     const PMJob &J = jobs[tc.job];
+    const int tab_n = J.tab_n;  // the same for the whole workgroup
+    if (tab_n > 0) {
+        gptr<uint32_t> bt = (gptr<uint32_t>)J.btab;
+        for (int i = (int)(threadIdx.y * TW + threadIdx.x); i < 3 * tab_n; i += TW * TH) s_btab[i] = bt[i];
+        __syncthreads();
+    }
+    if (!tc.active) return;
     const int h = J.h, w = J.w, pitch = J.pitch, r = tc.r, c = tc.c;
     const int v = r * w + c;
     const uint32_t pitch_b = 4u * (uint32_t)pitch;
@@ -275,6 +291,27 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
             load_target_patch<P>(J.sty_hat, 4u * (uint32_t)(r * pitch + c), pitch_b, ts);
         }
     }
+
+    // the target patch's per-channel sums T_c, for the bound-table test
+    int ts0 = 0, ts1 = 0, ts2 = 0;
+    if (tab_n > 0) {
+        uint32_t a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                a0 = __builtin_amdgcn_udot4(t.px[i][j], 0x00000001u, a0, false);
+                a1 = __builtin_amdgcn_udot4(t.px[i][j], 0x00000100u, a1, false);
+                a2 = __builtin_amdgcn_udot4(t.px[i][j], 0x00010000u, a2, false);
+            }
+        ts0 = (int)a0;
+        ts1 = (int)a1;
+        ts2 = (int)a2;
+    }
+    const int tab_shift = J.tab_shift, tab_w = J.tab_w;
+    // added to the table's pairs (mn_R, mn_G), (mn_B, -mx_R), (-mx_G, -mx_B):
+    // the six differences whose positive parts are the distances to the ranges
+    const s16x2 u0 = {(short)-ts0, (short)-ts1}, u1 = {(short)-ts2, (short)ts0}, u2 = {(short)ts1, (short)ts2};
 
     const uint32_t f0 = gload<uint32_t>(f_in, 4u * v);
     int br = (int)(f0 >> 16), bc = (int)(f0 & 0xFFFFu);
@@ -296,8 +333,32 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     // (Eq. 3: both terms are sums of squares, so the weighted partial sums
     // are lower bounds in the same way; the weighted total stays below 2^32
     // for alpha16 <= 512.)
-    auto consider = [&](int cr, int cc) {
+    // (2p+1)^2 * be, saturated: a bound lb (< 2^32) at or above it rules the
+    // candidate out (plain loss; be may be any energy a caller passed in)
+    auto bound_threshold = [&]() {
+        const uint64_t x = (uint64_t)(K * K) * be;
+        return x > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)x;
+    };
+    uint32_t thr = 0;
+    auto consider = [&](int cr, int cc, auto use_bound) {
         if (cr == br && cc == bc) return;
+        if (decltype(use_bound)::value && tab_n > 0) {
+            // sum_c dist(T_c, [mn_c, mx_c])^2 <= (2p+1)^2 * SSD(G); at most one
+            // of each channel's two differences is positive
+            const int e = (cr >> tab_shift) * tab_w + (cc >> tab_shift);
+            const s16x2 z = {0, 0};
+            const s16x2 d0 = __builtin_elementwise_max(__builtin_bit_cast(s16x2, s_btab[e]) + u0, z);
+            const s16x2 d1 = __builtin_elementwise_max(__builtin_bit_cast(s16x2, s_btab[tab_n + e]) + u1, z);
+            const s16x2 d2 = __builtin_elementwise_max(__builtin_bit_cast(s16x2, s_btab[2 * tab_n + e]) + u2, z);
+            uint32_t lb = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, d0), __builtin_bit_cast(u16x2, d0), 0u, false);
+            lb = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, d1), __builtin_bit_cast(u16x2, d1), lb, false);
+            lb = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, d2), __builtin_bit_cast(u16x2, d2), lb, false);
+            if constexpr (STYLE) {
+                if ((uint64_t)a16 * lb >= (uint64_t)(K * K) * be) return;
+            } else {
+                if (lb >= thr) return;
+            }
+        }
         const uint32_t off = 4u * (uint32_t)(cr * pitch + cc);
         uint32_t acc = seg_loss<P, 0, S1>(src_px, off, t, 0), accs = 0;
         if constexpr (STYLE) {
@@ -327,34 +388,42 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
         uint32_t e;
         if constexpr (STYLE) e = a16 * (t.cum_tt[K - 1] + acc) + 16u * (ts.cum_tt[K - 1] + accs);
         else e = t.cum_tt[K - 1] + acc;
-        if (e < be) { br = cr; bc = cc; be = e; }
+        if (e < be) {
+            br = cr;
+            bc = cc;
+            be = e;
+            if constexpr (!STYLE) thr = bound_threshold();
+        }
     };
+    if constexpr (!STYLE) thr = bound_threshold();
+    constexpr std::false_type kNoBound{};
+    constexpr std::true_type kBound{};
 
     // propagation: F(v + d) - d for d = (-1,0), (1,0), (0,-1), (0,1)
     if (r > 0) {
         const uint32_t q = gload<uint32_t>(f_in, 4u * (v - w));
-        consider(min((int)(q >> 16) + 1, h - 1), (int)(q & 0xFFFFu));
+        consider(min((int)(q >> 16) + 1, h - 1), (int)(q & 0xFFFFu), kNoBound);
     }
     if (r < h - 1) {
         const uint32_t q = gload<uint32_t>(f_in, 4u * (v + w));
-        consider(max((int)(q >> 16) - 1, 0), (int)(q & 0xFFFFu));
+        consider(max((int)(q >> 16) - 1, 0), (int)(q & 0xFFFFu), kNoBound);
     }
     if (c > 0) {
         const uint32_t q = gload<uint32_t>(f_in, 4u * (v - 1));
-        consider((int)(q >> 16), min((int)(q & 0xFFFFu) + 1, w - 1));
+        consider((int)(q >> 16), min((int)(q & 0xFFFFu) + 1, w - 1), kNoBound);
     }
     if (c < w - 1) {
         const uint32_t q = gload<uint32_t>(f_in, 4u * (v + 1));
-        consider((int)(q >> 16), max((int)(q & 0xFFFFu) - 1, 0));
+        consider((int)(q >> 16), max((int)(q & 0xFFFFu) - 1, 0), kNoBound);
     }
     if constexpr (TRACK) {
         if (J.trk_prev) {
             const uint32_t q = gload<uint32_t>(J.trk_prev, 4u * v);
-            consider((int)(q >> 16), (int)(q & 0xFFFFu));
+            consider((int)(q >> 16), (int)(q & 0xFFFFu), kNoBound);
         }
         if (J.trk_next) {
             const uint32_t q = gload<uint32_t>(J.trk_next, 4u * v);
-            consider((int)(q >> 16), (int)(q & 0xFFFFu));
+            consider((int)(q >> 16), (int)(q & 0xFFFFu), kNoBound);
         }
     }
 
@@ -370,7 +439,7 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
         const uint32_t n = 2u * (uint32_t)rho + 1u;
         const int dr = u16_to_range(word & 0xFFFFu, n) - rho;
         const int dc = u16_to_range(word >> 16, n) - rho;
-        consider(clampi(br + dr, 0, h - 1), clampi(bc + dc, 0, w - 1));
+        consider(clampi(br + dr, 0, h - 1), clampi(bc + dc, 0, w - 1), kBound);
     }
     gstore<uint32_t>(J.f_out, 4u * v, ((uint32_t)br << 16) | (uint32_t)bc);
     gstore<uint32_t>(J.e_out, 4u * v, be);
@@ -484,13 +553,14 @@ hipError_t launch_pm_start(const PMJob *jobs, int n_jobs, int total_tiles, int u
 }
 
 hipError_t launch_pm_iter(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
-                          TileCfg cfg, int p, int iter, uint64_t seed, int mode, hipStream_t s) {
+                          TileCfg cfg, int p, int iter, uint64_t seed, int mode, int tab_bytes,
+                          hipStream_t s) {
     if (total_tiles <= 0) return hipSuccess;
-    if (mode < 0 || mode > 3) return hipErrorInvalidValue;
+    if (mode < 0 || mode > 3 || tab_bytes < 0 || tab_bytes > kBoundTabBytes) return hipErrorInvalidValue;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-#define FB_ITER3(P_, TW, TH, M_)                                                                        \
-    hipLaunchKernelGGL((k_pm_iter<P_, TW, TH, M_>), dim3(total_tiles), dim3(TW, TH), 0, s, jobs, n_jobs, \
-                       total_tiles, uniform_tiles, iter, k0, k1)
+#define FB_ITER3(P_, TW, TH, M_)                                                                   \
+    hipLaunchKernelGGL((k_pm_iter<P_, TW, TH, M_>), dim3(total_tiles), dim3(TW, TH), (size_t)tab_bytes, \
+                       s, jobs, n_jobs, total_tiles, uniform_tiles, iter, k0, k1)
 #define FB_ITER2(P_, TW, TH)                                                   \
     if (mode == 0) FB_ITER3(P_, TW, TH, 0);                                    \
     else if (mode == 1) FB_ITER3(P_, TW, TH, 1);                               \

@@ -35,6 +35,18 @@ PyrLayout pyr_layout(int h, int w, int levels, int p) {
         g.px_off = off;
         off += (size_t)g.rows * g.pitch * 4;
         off = (off + 255) & ~(size_t)255;
+        // the level's bound table follows its pixels, so the first l levels
+        // of a deeper pyramid have the layout of an l-level one
+        int sh = kBoundTabMinShift;
+        while ((size_t)((g.h + (1 << sh) - 1) >> sh) * (size_t)((g.w + (1 << sh) - 1) >> sh) * 12 >
+               (size_t)kBoundTabBytes)
+            ++sh;
+        g.tab_shift = sh;
+        g.tab_h = (g.h + (1 << sh) - 1) >> sh;
+        g.tab_w = (g.w + (1 << sh) - 1) >> sh;
+        g.tab_off = off;
+        off += (size_t)g.tab_h * g.tab_w * 12;
+        off = (off + 255) & ~(size_t)255;
     }
     L.bytes = off;
     return L;
@@ -89,7 +101,65 @@ k_downsample(uint8_t *__restrict__ base, size_t stride, int hi_, int wi, int pit
     out[(size_t)R * pitch_o + C] = vr | (vg << 8) | (vb << 16);
 }
 
+// Bound table of one level: one wave per block of 2^sh x 2^sh patch
+// positions.  Every position's (2p+1)^2 per-channel patch sum is taken from
+// the padded level (so it sums the clamped patch the loss compares), and the
+// block keeps each channel's minimum and maximum.  By Cauchy-Schwarz,
+// (sum_k d_k)^2 <= (2p+1)^2 sum_k d_k^2 for the channel differences d_k of
+// two patches, so the distance from a target patch's channel sums to these
+// ranges bounds Eq. 1 from below for every candidate in the block.  Sums are
+// at most 81 * 255, so each value and its negation fit 16 bits.
+__global__ void __launch_bounds__(64)
+k_bound_table(uint8_t *__restrict__ base, size_t stride, int h, int w, int pitch, size_t px_off,
+              int sh, int tab_w, int tab_n, size_t tab_off, int p) {
+    const int f = blockIdx.y;
+    const int by = (int)blockIdx.x / tab_w, bx = (int)blockIdx.x - by * tab_w;
+    const uint8_t *fb = base + (size_t)f * stride;
+    const uint32_t *img = reinterpret_cast<const uint32_t *>(fb + px_off);
+    const int side = 1 << sh, k = 2 * p + 1;
+    int mn0 = 1 << 30, mn1 = 1 << 30, mn2 = 1 << 30, mx0 = 0, mx1 = 0, mx2 = 0;
+    for (int i = (int)threadIdx.x; i < side * side; i += 64) {
+        const int r = (by << sh) + (i >> sh), c = (bx << sh) + (i & (side - 1));
+        if (r >= h || c >= w) continue;
+        uint32_t rb = 0, g = 0;  // R and B sums in 16-bit halves; G alone
+        for (int dr = 0; dr < k; ++dr)
+            for (int dc = 0; dc < k; ++dc) {
+                const uint32_t px = img[(size_t)(r + dr) * pitch + c + dc];
+                rb += px & 0x00FF00FFu;
+                g += (px >> 8) & 0xFFu;
+            }
+        const int s0 = (int)(rb & 0xFFFFu), s1 = (int)g, s2 = (int)(rb >> 16);
+        mn0 = min(mn0, s0); mx0 = max(mx0, s0);
+        mn1 = min(mn1, s1); mx1 = max(mx1, s1);
+        mn2 = min(mn2, s2); mx2 = max(mx2, s2);
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        mn0 = min(mn0, __shfl_xor(mn0, m)); mx0 = max(mx0, __shfl_xor(mx0, m));
+        mn1 = min(mn1, __shfl_xor(mn1, m)); mx1 = max(mx1, __shfl_xor(mx1, m));
+        mn2 = min(mn2, __shfl_xor(mn2, m)); mx2 = max(mx2, __shfl_xor(mx2, m));
+    }
+    if (threadIdx.x == 0) {
+        auto pair16 = [](int lo, int hi) { return ((uint32_t)lo & 0xFFFFu) | ((uint32_t)hi << 16); };
+        uint32_t *t = reinterpret_cast<uint32_t *>(base + (size_t)f * stride + tab_off);
+        t[blockIdx.x] = pair16(mn0, mn1);
+        t[tab_n + blockIdx.x] = pair16(mn2, -mx0);
+        t[2 * tab_n + blockIdx.x] = pair16(-mx1, -mx2);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_bound_tables(uint8_t *base, size_t stride, int n, const PyrLayout &L, hipStream_t s) {
+    for (int l = 0; l < L.levels; ++l) {
+        const LevelGeom &g = L.lv[l];
+        hipLaunchKernelGGL(k_bound_table, dim3(g.tab_w * g.tab_h, n), dim3(64), 0, s, base, stride,
+                           g.h, g.w, g.pitch, g.px_off, g.tab_shift, g.tab_w, g.tab_w * g.tab_h, g.tab_off, L.p);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_pack_rgbx(const uint8_t *rgb, size_t rgb_stride, int n, int h, int w, int p,
                             uint8_t *dst, size_t dst_stride, size_t px_off, int pitch,

@@ -94,6 +94,13 @@ void assign_tiles(std::vector<PMJob> &jobs, TileCfg cfg, int *total, int *unifor
 
 enum LaunchKind { kLaunchStart, kLaunchIter, kLaunchStyleRefresh, kLaunchExport };
 
+// LDS an iteration launch stages: the largest source bound table of its jobs
+int max_tab_bytes(const std::vector<PMJob> &jobs) {
+    int n = 0;
+    for (const PMJob &j : jobs) n = std::max(n, j.tab_n);
+    return n * 12;
+}
+
 void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cfg, int p,
                    uint64_t seed, int iter, int mode = kIterPlain) {
     if (jobs.empty()) return;
@@ -109,12 +116,14 @@ void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cf
                                    cfg, p, seed, s);
         }});
         break;
-    case kLaunchIter:
+    case kLaunchIter: {
+        const int tab_bytes = max_tab_bytes(jobs);
         P.ops.push_back({FB_KERNEL_PM_ITER, [=](hipStream_t s, const uint8_t *tab) {
             return launch_pm_iter(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform,
-                                  cfg, p, iter, seed, mode, s);
+                                  cfg, p, iter, seed, mode, tab_bytes, s);
         }});
         break;
+    }
     case kLaunchStyleRefresh:
         P.ops.push_back({FB_KERNEL_STYLE, [=](hipStream_t s, const uint8_t *tab) {
             return launch_style_refresh(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform,
@@ -131,17 +140,20 @@ void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cf
 }
 
 // Pyramids of n frames (uint8 [n][h][w][3], contiguous) into dst[f * stride].
+// Pyramids whose frames are never a PatchMatch source (styles, T^-) skip the
+// bound tables (tables = false).
 void plan_pyramids(Plan &P, const uint8_t *rgb, int n, int h, int w, const PyrLayout &L,
-                   uint8_t *dst, size_t stride) {
+                   uint8_t *dst, size_t stride, bool tables = true) {
     const int p = L.p;
     const size_t rgb_stride = (size_t)h * w * 3;
-    sig_add(P, "pyr", (long long)(uintptr_t)rgb, n, ((long long)h << 32) | w,
+    sig_add(P, tables ? "pyr" : "pyr-nt", (long long)(uintptr_t)rgb, n, ((long long)h << 32) | w,
             (long long)(uintptr_t)dst + L.levels);
     P.ops.push_back({FB_KERNEL_PYRAMID, [=](hipStream_t s, const uint8_t *) {
         hipError_t e = launch_pack_rgbx(rgb, rgb_stride, n, h, w, p, dst, stride, L.lv[0].px_off,
                                         L.lv[0].pitch, s);
         for (int l = 1; l < L.levels && e == hipSuccess; ++l)
             e = launch_downsample(dst, stride, n, L.lv[l - 1], L.lv[l], p, s);
+        if (e == hipSuccess && tables) e = launch_bound_tables(dst, stride, n, L, s);
         return e;
     }});
 }
@@ -185,6 +197,10 @@ PMJob job_geom(const PairSpec &ps, int l) {
     j.pitch = g.pitch;
     j.pair_id = ps.pair_id;
     j.level = l;
+    j.btab = reinterpret_cast<const uint32_t *>(ps.src_pyr + g.tab_off);
+    j.tab_shift = g.tab_shift;
+    j.tab_w = g.tab_w;
+    j.tab_n = g.tab_w * g.tab_h;
     if (ps.src_sty_pyr) {
         j.src_sty = reinterpret_cast<const uint32_t *>(ps.src_sty_pyr + g.px_off);
         // the iteration only reads sty_hat; T^- is never written
@@ -423,12 +439,13 @@ fb_status autotune(fb_ctx *ctx, Plan &P, hipStream_t s, int p, uint64_t seed) {
                          hipMemcpyHostToDevice));
         const PMJob *dj = reinterpret_cast<const PMJob *>(ctx->tune_table.p);
         // reruns of the last iteration read what it read and write what it wrote
+        const int tab_bytes = max_tab_bytes(jobs);
         FB_HIP(launch_pm_iter(dj, (int)jobs.size(), total, uniform, tile_cfg(c), p, P.tune_iter, seed,
-                              P.tune_mode, s));
+                              P.tune_mode, tab_bytes, s));
         FB_HIP(hipEventRecord(e0, s));
         for (int rep = 0; rep < 3; ++rep)
             FB_HIP(launch_pm_iter(dj, (int)jobs.size(), total, uniform, tile_cfg(c), p, P.tune_iter, seed,
-                                  P.tune_mode, s));
+                                  P.tune_mode, tab_bytes, s));
         FB_HIP(hipEventRecord(e1, s));
         FB_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -807,7 +824,7 @@ fb_status blend_accurate(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styl
 
     Plan P;
     plan_pyramids(P, guides, N, h, w, L, pyr, L.bytes);
-    plan_pyramids(P, styles, N, h, w, L, sty, L.bytes);
+    plan_pyramids(P, styles, N, h, w, L, sty, L.bytes, false);
     // fields and energies of pair k in pass q (0: Eq. 1, 1: Eq. 8), n pairs,
     // in slices of npx entries of fe: f[0] at q n + k, f[1] at 2n + q n + k,
     // e[0] at 4n + q n + k, e[1] at 6n + q n + k
@@ -856,7 +873,7 @@ fb_status blend_accurate(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styl
         frames.push_back(fr);
     }
     add_remap_launch(P, frames, terms, h, w, pitch, p);
-    plan_pyramids(P, tbar_in, N, h, w, L, tbar, L.bytes);
+    plan_pyramids(P, tbar_in, N, h, w, L, tbar, L.bytes, false);
     if (!second.empty()) plan_patchmatch(P, second, params->iters, p, params->seed, cfg, true, params->alpha16, true);
     terms.clear();
     frames.clear();
@@ -958,6 +975,7 @@ fb_status fb_build_pyramid(fb_ctx *ctx, const uint8_t *rgb, int32_t h, int32_t w
     for (int l = 1; l < levels; ++l)
         FB_HIP(launch_downsample(static_cast<uint8_t *>(pyr), 0, 1, L.lv[l - 1], L.lv[l],
                                  patch_radius, s));
+    FB_HIP(launch_bound_tables(static_cast<uint8_t *>(pyr), 0, 1, L, s));
     return FB_OK;
 }
 
@@ -1121,7 +1139,7 @@ fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *sty
 
     Plan P;
     plan_pyramids(P, guides, N, h, w, L, pyr, L.bytes);
-    if (style) plan_pyramids(P, styles, N, h, w, L, sty, L.bytes);
+    if (style) plan_pyramids(P, styles, N, h, w, L, sty, L.bytes, false);
     else plan_style_pack(P, styles, N, h, w, p, sty, sbytes, pitch);
     std::vector<PairSpec> pairs;
     pairs.reserve(n_pairs);
@@ -1216,7 +1234,7 @@ fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, i
 
     Plan P;
     plan_pyramids(P, guides, N, h, w, L, pyr, L.bytes);
-    if (align) plan_pyramids(P, key_styles, n_keys, h, w, L, sty, L.bytes);
+    if (align) plan_pyramids(P, key_styles, n_keys, h, w, L, sty, L.bytes, false);
     else plan_style_pack(P, key_styles, n_keys, h, w, p, sty, sbytes, pitch);
     std::vector<PairSpec> pairs;
     std::vector<int> pair_key;

@@ -40,7 +40,9 @@ def test_binding_covers_the_header(lib):
 
 def test_pyramid_bytes_layout(lib):
     # level l: (h_l + 2p) rows x pitch 4-byte pixels, pitch = w_l + 2p rounded
-    # up to 16, each level 256-byte aligned
+    # up to 16, then its bound table of 12-byte entries, one per block of
+    # b x b positions with b the smallest power of two >= 8 that keeps the
+    # table within 16 KiB; every part 256-byte aligned
     def expect(h, w, levels, p):
         off = 0
         for l in range(levels):
@@ -48,8 +50,14 @@ def test_pyramid_bytes_layout(lib):
             pitch = -(-(wl + 2 * p) // 16) * 16
             off += (hl + 2 * p) * pitch * 4
             off = -(-off // 256) * 256
+            b = 8
+            while -(-hl // b) * -(-wl // b) * 12 > 16384:
+                b *= 2
+            off += -(-hl // b) * -(-wl // b) * 12
+            off = -(-off // 256) * 256
         return off
-    for args in [(64, 64, 1, 2), (512, 512, 3, 2), (576, 1024, 4, 2), (37, 53, 3, 1), (5, 3, 2, 4)]:
+    for args in [(64, 64, 1, 2), (512, 512, 3, 2), (576, 1024, 4, 2), (720, 1280, 4, 2), (37, 53, 3, 1),
+                 (5, 3, 2, 4), (2160, 3840, 1, 2)]:
         assert lib.fb_pyramid_bytes(*args) == expect(*args), args
     # invalid arguments give 0
     assert lib.fb_pyramid_bytes(0, 5, 1, 2) == 0

@@ -52,17 +52,50 @@ def pair_images(h, w, seed, kind="sprites"):
 
 def _pyramid_layout(h, w, levels, p):
     """Byte layout of a pyramid buffer: per level its padded 4-byte pixels,
-    (h_l + 2p) rows of pitch = w_l + 2p rounded up to 16, 256-byte aligned."""
+    (h_l + 2p) rows of pitch = w_l + 2p rounded up to 16, then its bound table
+    (12 bytes per block of b x b positions, b the smallest power of two >= 8
+    keeping the table within 16 KiB), every part 256-byte aligned."""
     out, off = [], 0
     for l in range(levels):
         hl, wl = -(-h // (1 << l)), -(-w // (1 << l))
         pitch = -(-(wl + 2 * p) // 16) * 16
-        out.append((hl, wl, pitch, off))
+        px_off = off
         off = -(-(off + (hl + 2 * p) * pitch * 4) // 256) * 256
+        b = 8
+        while -(-hl // b) * -(-wl // b) * 12 > 16384:
+            b *= 2
+        out.append((hl, wl, pitch, px_off, b, off))
+        off = -(-(off + -(-hl // b) * -(-wl // b) * 12) // 256) * 256
     return out, off
 
 
-@pytest.mark.parametrize("h,w,levels,p", [(37, 53, 3, 1), (40, 33, 2, 2), (19, 70, 2, 3), (11, 9, 2, 4)])
+def _bound_table(level_img, p, b):
+    """Per block of b x b patch positions, each channel's min and max of the
+    (2p+1)^2 patch sums over the clamped patch, as stored: three arrays of
+    int16 pairs (mn_R, mn_G), (mn_B, -mx_R), (-mx_G, -mx_B), one entry per
+    block in row-major block order.  Written from the definition (an
+    edge-padded box filter), not from the kernel."""
+    k = 2 * p + 1
+    hl, wl = level_img.shape[:2]
+    x = np.pad(level_img.astype(np.int64), ((p, p), (p, p), (0, 0)), mode="edge")
+    sums = np.zeros((hl, wl, 3), np.int64)
+    for dr in range(k):
+        for dc in range(k):
+            sums += x[dr:dr + hl, dc:dc + wl]
+    th, tw = -(-hl // b), -(-wl // b)
+    out = np.zeros((3, th, tw, 2), np.int16)
+    for by in range(th):
+        for bx in range(tw):
+            blk = sums[by * b:(by + 1) * b, bx * b:(bx + 1) * b].reshape(-1, 3)
+            mn, mx = blk.min(0), blk.max(0)
+            out[0, by, bx] = (mn[0], mn[1])
+            out[1, by, bx] = (mn[2], -mx[0])
+            out[2, by, bx] = (-mx[1], -mx[2])
+    return out
+
+
+@pytest.mark.parametrize("h,w,levels,p", [(37, 53, 3, 1), (40, 33, 2, 2), (19, 70, 2, 3), (11, 9, 2, 4),
+                                          (400, 720, 2, 2)])
 def test_pyramid_buffer_matches_oracle(ctx, h, w, levels, p):
     """Every level of the pyramid buffer byte for byte: the oracle's level with
     a replicated p-pixel border, as (R, G, B, 0) words."""
@@ -71,11 +104,14 @@ def test_pyramid_buffer_matches_oracle(ctx, h, w, levels, p):
     ref = oracle.pyramid(img, levels)
     lay, total = _pyramid_layout(h, w, levels, p)
     assert buf.size == total
-    for l, (hl, wl, pitch, px_off) in enumerate(lay):
+    for l, (hl, wl, pitch, px_off, b, tab_off) in enumerate(lay):
         padded = np.pad(ref[l], ((p, p), (p, p), (0, 0)), mode="edge")
         px = buf[px_off:px_off + (hl + 2 * p) * pitch * 4].reshape(hl + 2 * p, pitch, 4)
         assert np.array_equal(px[:, :wl + 2 * p, :3], padded), l
         assert not px[:, :wl + 2 * p, 3].any(), l
+        want = _bound_table(ref[l], p, b)
+        got = buf[tab_off:tab_off + want.size * 2].view(np.int16).reshape(want.shape)
+        assert np.array_equal(got, want), l
 
 
 def test_config1_translation_pair(ctx):
@@ -118,6 +154,26 @@ def test_per_level_api_matches_oracle(ctx, h, w, levels, p, iters):
         for it in range(iters):
             Fo, Eo = oracle.pm_iteration(Sp[l], Tp[l], p, l, it, seed, pair, Fo, Eo)
         assert_field_equal(nnf, en, Fo, Eo, "level %d" % l)
+
+
+def test_caller_energies_of_any_size(ctx):
+    """A field and energies passed in by the caller: energies up to 2^32 - 1,
+    where (2p+1)^2 * E leaves 32 bits, keep every candidate test exact."""
+    h, w, p, iters = 48, 80, 2, 2
+    S, T = pair_images(h, w, 77)
+    seed, pair = 0x5EED, 3
+    prm = fbm.make_params(p, 1, iters, seed)
+    pa, pb = ctx.fb_build_pyramid(dev(S), 1, p), ctx.fb_build_pyramid(dev(T), 1, p)
+    rng = np.random.default_rng(5)
+    F0 = np.stack([rng.integers(0, h, (h, w)), rng.integers(0, w, (h, w))], -1).astype(np.int32)
+    E0 = rng.choice(np.array([0xFFFFFFFF, 0x80000000, 0x0A000000, 171798692, 171798691, 1000, 0], np.uint32),
+                    (h, w))
+    nnf, en = ctx.fb_patchmatch_level(pa, pb, h, w, 0, prm, pair, nnf=dev(F0), energy=dev(E0.view(np.int32)))
+    Fo, Eo = F0, E0
+    for it in range(iters):
+        Fo, Eo = oracle.pm_iteration(S, T, p, 0, it, seed, pair, Fo, Eo)
+    assert np.array_equal(host(nnf), Fo)
+    assert np.array_equal(host(en).view(np.uint32), Eo.astype(np.uint32))
 
 
 def test_seed_offsets_init(ctx):
