@@ -93,6 +93,7 @@ using gptr_mut = __attribute__((address_space(1))) T *;
 
 // (a C-style cast is the one that may change the address space)
 typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 template <class T>
@@ -127,6 +128,26 @@ struct TargetPatch {
     uint32_t head_tt;    // sum t^2 of the first S1 pixels of row 0
     uint32_t cum_tt[K];  // sum t^2 of rows 0..i; cum_tt[K - 1] is the patch's
 };
+
+// the patch whose top-left padded pixel is element base of a tile staged in
+// LDS with row stride SW
+template <int P, int SW>
+__device__ __forceinline__ void load_target_patch_lds(const uint32_t *s, int base, TargetPatch<P> &t) {
+    constexpr int K = 2 * P + 1;
+    uint32_t tt = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            t.px[i][j] = s[base + i * SW + j];
+            acc = __builtin_amdgcn_udot4(t.px[i][j], t.px[i][j], acc, false);
+            if (i == 0 && j == TargetPatch<P>::S1 - 1) t.head_tt = acc;
+        }
+        tt += acc;
+        t.cum_tt[i] = tt;
+    }
+}
 
 template <int P>
 __device__ __forceinline__ void load_target_patch(const uint32_t *tp, uint32_t off, uint32_t pitch_b,
@@ -253,34 +274,59 @@ k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unif
 // The incumbent is re-scored under X instead of taking e_in.
 // MODE & kIterTrack: after propagation, the matches of the pairs with the
 // same source and the neighbouring target frames are candidates too.
-// Every launch stages the source level's bound table (the per-block ranges
-// of the candidates' per-channel patch sums, built with the pyramid) in LDS:
-// a candidate whose Cauchy-Schwarz bound already reaches the running best is
-// ruled out before any of its pixels is fetched.
+// Every launch stages in LDS, with coalesced loads: the tile's target pixels
+// with their patch border, the tile's old field with a 1-entry border (the
+// incumbent and the propagation neighbours), and the source level's bound
+// table (the per-block ranges of the candidates' per-channel patch sums,
+// built with the pyramid), by which a candidate whose Cauchy-Schwarz bound
+// already reaches the running best is ruled out before any of its pixels is
+// fetched.
 template <int P, int TW, int TH, int MODE>
 __global__ void __launch_bounds__(TW *TH)
 k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles, int iter,
           uint32_t k0, uint32_t k1) {
     constexpr bool STYLE = (MODE & kIterStyle) != 0, TRACK = (MODE & kIterTrack) != 0;
-    extern __shared__ uint32_t s_btab[];  // the three 16-bit-pair arrays of the bound table
+    constexpr int K = 2 * P + 1, S1 = TargetPatch<P>::S1;
+    constexpr int SW = TW + 2 * P, SH = TH + 2 * P;  // target tile with its patch border
+    constexpr int FW = TW + 2, FH = TH + 2;          // field tile with a 1-entry border
+    __shared__ uint32_t s_tgt[SH * SW];
+    __shared__ uint32_t s_f[FH * FW];
+    extern __shared__ u32x4 s_btab4[];  // the three 16-bit-pair arrays of the bound table
+    const uint32_t *s_btab = reinterpret_cast<const uint32_t *>(s_btab4);
     const TileCoord tc = locate<TW, TH>(jobs, n_jobs, total_tiles, uniform_tiles);
     const PMJob &J = jobs[tc.job];
-    const int tab_n = J.tab_n;  // the same for the whole workgroup
-    if (tab_n > 0) {
-        gptr<uint32_t> bt = (gptr<uint32_t>)J.btab;
-        for (int i = (int)(threadIdx.y * TW + threadIdx.x); i < 3 * tab_n; i += TW * TH) s_btab[i] = bt[i];
-        __syncthreads();
-    }
-    if (!tc.active) return;
     const int h = J.h, w = J.w, pitch = J.pitch, r = tc.r, c = tc.c;
+    const int tab_n = J.tab_n;  // the same for the whole workgroup
+    {
+        const int tid = (int)(threadIdx.y * TW + threadIdx.x);
+        const int rt = r - (int)threadIdx.y, ct = c - (int)threadIdx.x;  // tile origin
+        // padded target rows rt .. rt + TH + 2P - 1; reads past the image are clamped (never used)
+        gptr<uint32_t> tp = (gptr<uint32_t>)J.tgt_px;
+        for (int i = tid; i < SH * SW; i += TW * TH) {
+            const int yy = min(rt + i / SW, h + 2 * P - 1), xx = min(ct + i % SW, w + 2 * P - 1);
+            s_tgt[i] = tp[yy * pitch + xx];
+        }
+        gptr<uint32_t> fp = (gptr<uint32_t>)J.f_in;
+        for (int i = tid; i < FH * FW; i += TW * TH) {
+            const int yy = rt - 1 + i / FW, xx = ct - 1 + i % FW;
+            s_f[i] = (yy >= 0 && yy < h && xx >= 0 && xx < w) ? fp[yy * w + xx] : 0u;
+        }
+        if (tab_n > 0) {
+            // 16-byte loads; the table's region is padded to 256 bytes, so the
+            // last load stays inside it
+            gptr<u32x4> bt = (gptr<u32x4>)J.btab;
+            for (int i = tid; i < (3 * tab_n + 3) / 4; i += TW * TH) s_btab4[i] = bt[i];
+        }
+    }
+    __syncthreads();
+    if (!tc.active) return;
     const int v = r * w + c;
     const uint32_t pitch_b = 4u * (uint32_t)pitch;
-    const uint32_t *f_in = J.f_in;
     const uint32_t *src_px = J.src_px;
-    constexpr int K = 2 * P + 1, S1 = TargetPatch<P>::S1;
+    const int fc0 = ((int)threadIdx.y + 1) * FW + (int)threadIdx.x + 1;  // this pixel in s_f
 
     TargetPatch<P> t, ts;  // ts: the patch of S^ (Eq. 3 loss only)
-    load_target_patch<P>(J.tgt_px, 4u * (uint32_t)(r * pitch + c), pitch_b, t);
+    load_target_patch_lds<P, SW>(s_tgt, (int)threadIdx.y * SW + (int)threadIdx.x, t);
     const uint32_t *src_sty = J.src_sty;
     const uint32_t a16 = STYLE ? (uint32_t)J.alpha16 : 1u;
     if constexpr (STYLE) {
@@ -313,7 +359,7 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     // the six differences whose positive parts are the distances to the ranges
     const s16x2 u0 = {(short)-ts0, (short)-ts1}, u1 = {(short)-ts2, (short)ts0}, u2 = {(short)ts1, (short)ts2};
 
-    const uint32_t f0 = gload<uint32_t>(f_in, 4u * v);
+    const uint32_t f0 = s_f[fc0];
     int br = (int)(f0 >> 16), bc = (int)(f0 & 0xFFFFu);
     uint32_t be;
     if constexpr (STYLE) {
@@ -401,19 +447,19 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
 
     // propagation: F(v + d) - d for d = (-1,0), (1,0), (0,-1), (0,1)
     if (r > 0) {
-        const uint32_t q = gload<uint32_t>(f_in, 4u * (v - w));
+        const uint32_t q = s_f[fc0 - FW];
         consider(min((int)(q >> 16) + 1, h - 1), (int)(q & 0xFFFFu), kNoBound);
     }
     if (r < h - 1) {
-        const uint32_t q = gload<uint32_t>(f_in, 4u * (v + w));
+        const uint32_t q = s_f[fc0 + FW];
         consider(max((int)(q >> 16) - 1, 0), (int)(q & 0xFFFFu), kNoBound);
     }
     if (c > 0) {
-        const uint32_t q = gload<uint32_t>(f_in, 4u * (v - 1));
+        const uint32_t q = s_f[fc0 - 1];
         consider((int)(q >> 16), min((int)(q & 0xFFFFu) + 1, w - 1), kNoBound);
     }
     if (c < w - 1) {
-        const uint32_t q = gload<uint32_t>(f_in, 4u * (v + 1));
+        const uint32_t q = s_f[fc0 + 1];
         consider((int)(q >> 16), max((int)(q & 0xFFFFu) - 1, 0), kNoBound);
     }
     if constexpr (TRACK) {

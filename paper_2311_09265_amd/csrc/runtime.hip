@@ -98,7 +98,7 @@ enum LaunchKind { kLaunchStart, kLaunchIter, kLaunchStyleRefresh, kLaunchExport 
 int max_tab_bytes(const std::vector<PMJob> &jobs) {
     int n = 0;
     for (const PMJob &j : jobs) n = std::max(n, j.tab_n);
-    return n * 12;
+    return (n * 12 + 15) & ~15;  // staged with 16-byte loads
 }
 
 void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cfg, int p,
