@@ -371,14 +371,13 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
 
     // Every pixel's share of the loss is a square, so any part of the patch
     // whose loss alone reaches the running best rules the candidate out of
-    // '<'.  The first S1 pixels of row 0 are tested first (far random-search
-    // candidates, divergent gathers, usually stop after that one load), then
-    // every complete row: a row is fetched only by lanes still in the race.
-    // The sum of s^2 - 2 s t wraps in uint32, but with the t^2 sums added
-    // back every partial loss is the exact nonnegative value.
-    // (Eq. 3: both terms are sums of squares, so the weighted partial sums
-    // are lower bounds in the same way; the weighted total stays below 2^32
-    // for alpha16 <= 512.)
+    // '<'.  A random-search candidate first meets the table bound (no memory
+    // read); then the patch is tested after every complete row, so a row is
+    // fetched only by lanes still in the race.  The sum of s^2 - 2 s t wraps
+    // in uint32, but with the t^2 sums added back every partial loss is the
+    // exact nonnegative value.  (Eq. 3: both terms are sums of squares, so the
+    // weighted partial sums are lower bounds in the same way; the weighted
+    // total stays below 2^32 for alpha16 <= 512.)
     // (2p+1)^2 * be, saturated: a bound lb (< 2^32) at or above it rules the
     // candidate out (plain loss; be may be any energy a caller passed in)
     auto bound_threshold = [&]() {
@@ -408,10 +407,9 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
         const uint32_t off = 4u * (uint32_t)(cr * pitch + cc);
         uint32_t acc = seg_loss<P, 0, S1>(src_px, off, t, 0), accs = 0;
         if constexpr (STYLE) {
+            // no table bound covers the style term: the first S1 pixels are tested first
             accs = seg_loss<P, 0, S1>(src_sty, off, ts, 0);
             if (a16 * (t.head_tt + acc) + 16u * (ts.head_tt + accs) >= be) return;
-        } else {
-            if (t.head_tt + acc >= be) return;
         }
         if constexpr (S1 < K) {
             acc += seg_loss<P, S1, K - S1>(src_px, off + 4u * S1, t, 0);
@@ -477,6 +475,7 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     const int R = max(h, w);
     const uint32_t ctr2 = ((uint32_t)J.level << 16) | (uint32_t)iter;
     uint4 x = make_uint4(0, 0, 0, 0);
+#pragma unroll 4  // the Philox word of radius m is then picked at compile time
     for (int m = 0; (R >> m) > 0; ++m) {
         if ((m & 3) == 0) x = philox4x32_10(make_uint4((uint32_t)v, J.pair_id, ctr2, (uint32_t)(m >> 2)), k0, k1);
         const int s = m & 3;
