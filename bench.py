@@ -287,6 +287,56 @@ def bench_interp(ctx, fbm, args):
     return res
 
 
+def bench_mixed(ctx, fbm, args):
+    """The mixed-size batch: 12 pairs (t, t + d), d in 1..5, of each of 256x256
+    and 512x512 (3 levels) and 1024x576 and 1280x720 (4 levels), 6 iterations:
+    all 48 whole pyramids in one fb_patchmatch_batch call (grouped launches,
+    eager and replayed as a graph) against one call per pair."""
+    import torch
+    from paper_2311_09265_amd import synth
+    p, iters = 2, 6
+    seed = synth.PHILOX_SEED[4]
+    pairs = synth.mixed_pairs()
+    descs, pix = [], 0
+    for k, (a, b, lv) in enumerate(pairs):
+        h, w = a.shape[:2]
+        descs.append(dict(src_pyr=ctx.fb_build_pyramid(torch.from_numpy(a).cuda(), lv, p),
+                          tgt_pyr=ctx.fb_build_pyramid(torch.from_numpy(b).cuda(), lv, p),
+                          h=h, w=w, levels=lv, pair_id=k))
+        pix += n_pix_iters(h, w, lv, iters)
+    res = {"workload": "48 pairs: 12 each of 256x256 and 512x512 (3 levels), 1024x576 and 1280x720 "
+                       "(4 levels), patch 5x5, 6 iterations",
+           "pixel_iterations_per_call": pix}
+    steps = max(1, args.steps // 2)
+    for name, flags, per_pair in (("batched", 0, False), ("batched_graph", fbm.FB_USE_GRAPH, False),
+                                  ("per_pair", 0, True)):
+        prm = fbm.make_params(p, 4, iters, seed, flags)
+        if per_pair:
+            def run():
+                for d in descs:
+                    ctx.fb_patchmatch_batch([d], prm)
+        else:
+            def run():
+                ctx.fb_patchmatch_batch(descs, prm)
+        run()  # tunes the tile shape of every batch shape; captures the graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        res[name] = {"ms_per_call": round(ms, 3), "mpix_iter_per_s": round(pix / (ms / 1e3) / 1e6, 3)}
+        log("mixed batch, %s: %.2f ms per call" % (name, ms))
+    res["speedup_batched_graph_vs_per_pair"] = round(res["per_pair"]["ms_per_call"] /
+                                                     res["batched_graph"]["ms_per_call"], 3)
+    del descs
+    return res
+
+
+def n_pix_iters(h, w, levels, iters):
+    return sum(hl * wl for hl, wl in level_sizes(h, w, levels)) * iters
+
+
 def iter_kernel_traffic():
     """HBM bytes per launch of the PatchMatch iteration kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
@@ -321,6 +371,7 @@ def main():
     ap.add_argument("--no-fast", action="store_true", help="skip the fast-mode comparison")
     ap.add_argument("--no-accurate", action="store_true", help="skip the accurate-mode timing")
     ap.add_argument("--no-interp", action="store_true", help="skip the interpolation timings")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch timings")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (counter calibration)")
     args = ap.parse_args()
@@ -400,6 +451,10 @@ def main():
     if not args.no_interp:
         interp = bench_interp(ctx, fbm, args)
 
+    mixed = None
+    if not args.no_mixed:
+        mixed = bench_mixed(ctx, fbm, args)
+
     accurate = None
     if not args.no_accurate:
         accurate = bench_accurate(ctx, fbm, g, s, out, M, p, levels, iters, seed, args, N)
@@ -467,6 +522,7 @@ def main():
         "fast_mode": fast,
         "accurate_mode": accurate,
         "interpolation": interp,
+        "mixed_batch": mixed,
     }
     if learned:
         learned["speedup_vs_plain"] = round(ms / learned["ms_per_step"], 3)
