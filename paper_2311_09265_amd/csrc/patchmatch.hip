@@ -215,13 +215,34 @@ __device__ __forceinline__ TileCoord locate(const PMJob *__restrict__ jobs, int 
     return tc;
 }
 
+// The tile's padded target pixels with their patch border, (TH + 2P) rows of
+// TW + 2P, into LDS with coalesced loads; reads past the image are clamped
+// into it (those entries are never used).
+template <int P, int TW, int TH>
+__device__ __forceinline__ void stage_target_tile(uint32_t *s_tgt, const PMJob &J, const TileCoord &tc) {
+    constexpr int SW = TW + 2 * P, SH = TH + 2 * P;
+    const int tid = (int)(threadIdx.y * TW + threadIdx.x);
+    const int rt = tc.r - (int)threadIdx.y, ct = tc.c - (int)threadIdx.x;  // tile origin
+    gptr<uint32_t> tp = (gptr<uint32_t>)J.tgt_px;
+    for (int i = tid; i < SH * SW; i += TW * TH) {
+        const int yy = min(rt + i / SW, J.h + 2 * P - 1), xx = min(ct + i % SW, J.w + 2 * P - 1);
+        s_tgt[i] = tp[yy * J.pitch + xx];
+    }
+}
+
 template <int P, int TW, int TH>
 __global__ void __launch_bounds__(TW *TH)
 k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles,
            uint32_t k0, uint32_t k1) {
+    constexpr int SW = TW + 2 * P, SH = TH + 2 * P;
+    __shared__ uint32_t s_tgt[SH * SW];
     const TileCoord tc = locate<TW, TH>(jobs, n_jobs, total_tiles, uniform_tiles);
-    if (!tc.active) return;
     const PMJob &J = jobs[tc.job];
+    if (J.mode != kStartCopyAbi) {  // the same for the whole workgroup
+        stage_target_tile<P, TW, TH>(s_tgt, J, tc);
+        __syncthreads();
+    }
+    if (!tc.active) return;
     const int h = J.h, w = J.w, r = tc.r, c = tc.c;
     const int v = r * w + c;
     int fr, fc;
@@ -260,7 +281,7 @@ k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unif
     }
     const uint32_t pitch_b = 4u * (uint32_t)J.pitch;
     TargetPatch<P> t;
-    load_target_patch<P>(J.tgt_px, 4u * (uint32_t)(r * J.pitch + c), pitch_b, t);
+    load_target_patch_lds<P, SW>(s_tgt, (int)threadIdx.y * SW + (int)threadIdx.x, t);
     gstore<uint32_t>(J.f_out, 4u * v, ((uint32_t)fr << 16) | (uint32_t)fc);
     gstore<uint32_t>(J.e_out, 4u * v, patch_loss<P>(J.src_px, 4u * (uint32_t)(fr * J.pitch + fc), pitch_b, t));
 }
@@ -297,15 +318,10 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     const PMJob &J = jobs[tc.job];
     const int h = J.h, w = J.w, pitch = J.pitch, r = tc.r, c = tc.c;
     const int tab_n = J.tab_n;  // the same for the whole workgroup
+    stage_target_tile<P, TW, TH>(s_tgt, J, tc);
     {
         const int tid = (int)(threadIdx.y * TW + threadIdx.x);
         const int rt = r - (int)threadIdx.y, ct = c - (int)threadIdx.x;  // tile origin
-        // padded target rows rt .. rt + TH + 2P - 1; reads past the image are clamped (never used)
-        gptr<uint32_t> tp = (gptr<uint32_t>)J.tgt_px;
-        for (int i = tid; i < SH * SW; i += TW * TH) {
-            const int yy = min(rt + i / SW, h + 2 * P - 1), xx = min(ct + i % SW, w + 2 * P - 1);
-            s_tgt[i] = tp[yy * pitch + xx];
-        }
         gptr<uint32_t> fp = (gptr<uint32_t>)J.f_in;
         for (int i = tid; i < FH * FW; i += TW * TH) {
             const int yy = rt - 1 + i / FW, xx = ct - 1 + i % FW;
