@@ -123,9 +123,7 @@ __device__ __forceinline__ PixRow<N> load_pixrow(const void *base, uint32_t byte
 template <int P>
 struct TargetPatch {
     static constexpr int K = 2 * P + 1;
-    static constexpr int S1 = K < 4 ? K : 4;  // pixels of the first-row test
     uint32_t px[K][K];
-    uint32_t head_tt;    // sum t^2 of the first S1 pixels of row 0
     uint32_t cum_tt[K];  // sum t^2 of rows 0..i; cum_tt[K - 1] is the patch's
 };
 
@@ -142,7 +140,6 @@ __device__ __forceinline__ void load_target_patch_lds(const uint32_t *s, int bas
         for (int j = 0; j < K; ++j) {
             t.px[i][j] = s[base + i * SW + j];
             acc = __builtin_amdgcn_udot4(t.px[i][j], t.px[i][j], acc, false);
-            if (i == 0 && j == TargetPatch<P>::S1 - 1) t.head_tt = acc;
         }
         tt += acc;
         t.cum_tt[i] = tt;
@@ -162,7 +159,6 @@ __device__ __forceinline__ void load_target_patch(const uint32_t *tp, uint32_t o
         for (int j = 0; j < K; ++j) {
             t.px[i][j] = row.v[j];
             acc = __builtin_amdgcn_udot4(row.v[j], row.v[j], acc, false);
-            if (i == 0 && j == TargetPatch<P>::S1 - 1) t.head_tt = acc;
         }
         tt += acc;
         t.cum_tt[i] = tt;
@@ -302,12 +298,14 @@ k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unif
 // built with the pyramid), by which a candidate whose Cauchy-Schwarz bound
 // already reaches the running best is ruled out before any of its pixels is
 // fetched.
+// With the style loss and p <= 2 the kernel is held to 5 waves per SIMD
+// (at most 96 VGPRs, no spills); larger patches keep the compiler's choice.
 template <int P, int TW, int TH, int MODE>
-__global__ void __launch_bounds__(TW *TH)
+__global__ void __launch_bounds__(TW *TH, ((MODE & kIterStyle) && P <= 2) ? 5 * 256 / (TW * TH) : 1)
 k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles, int iter,
           uint32_t k0, uint32_t k1) {
     constexpr bool STYLE = (MODE & kIterStyle) != 0, TRACK = (MODE & kIterTrack) != 0;
-    constexpr int K = 2 * P + 1, S1 = TargetPatch<P>::S1;
+    constexpr int K = 2 * P + 1;
     constexpr int SW = TW + 2 * P, SH = TH + 2 * P;  // target tile with its patch border
     constexpr int FW = TW + 2, FH = TH + 2;          // field tile with a 1-entry border
     __shared__ uint32_t s_tgt[SH * SW];
@@ -421,22 +419,11 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
             }
         }
         const uint32_t off = 4u * (uint32_t)(cr * pitch + cc);
-        uint32_t acc = seg_loss<P, 0, S1>(src_px, off, t, 0), accs = 0;
-        if constexpr (STYLE) {
-            // no table bound covers the style term: the first S1 pixels are tested first
-            accs = seg_loss<P, 0, S1>(src_sty, off, ts, 0);
-            if (a16 * (t.head_tt + acc) + 16u * (ts.head_tt + accs) >= be) return;
-        }
-        if constexpr (S1 < K) {
-            acc += seg_loss<P, S1, K - S1>(src_px, off + 4u * S1, t, 0);
-            if constexpr (STYLE) accs += seg_loss<P, S1, K - S1>(src_sty, off + 4u * S1, ts, 0);
-        }
+        uint32_t acc = 0, accs = 0;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            if (i > 0) {
-                acc += seg_loss<P, 0, K>(src_px, off + (uint32_t)i * pitch_b, t, i);
-                if constexpr (STYLE) accs += seg_loss<P, 0, K>(src_sty, off + (uint32_t)i * pitch_b, ts, i);
-            }
+            acc += seg_loss<P, 0, K>(src_px, off + (uint32_t)i * pitch_b, t, i);
+            if constexpr (STYLE) accs += seg_loss<P, 0, K>(src_sty, off + (uint32_t)i * pitch_b, ts, i);
             if (i < K - 1) {
                 if constexpr (STYLE) {
                     if (a16 * (t.cum_tt[i] + acc) + 16u * (ts.cum_tt[i] + accs) >= be) return;
