@@ -6,7 +6,7 @@ on NNFs that the plain method computes (fb_patchmatch_batch: random
 initialisation, levels x iters concurrent PatchMatch), then seeds the
 coarsest level of PatchMatch in place of the random draw (FB_LEARNED_SEED),
 which lets the finer levels run fewer iterations.  Plain PatchMatch stays the
-default, the fallback and the judge: ``evaluate`` measures the mean level-0
+default, the fallback and the reference a model is measured against: ``evaluate`` measures the mean level-0
 patch energy of the seeded, shorter run against the plain run, and a model is
 accepted only if it stays within the stated margin.
 
