@@ -95,7 +95,7 @@ def _bound_table(level_img, p, b):
 
 
 @pytest.mark.parametrize("h,w,levels,p", [(37, 53, 3, 1), (40, 33, 2, 2), (19, 70, 2, 3), (11, 9, 2, 4),
-                                          (400, 720, 2, 2)])
+                                          (400, 720, 2, 2), (1500, 2000, 1, 3)])
 def test_pyramid_buffer_matches_oracle(ctx, h, w, levels, p):
     """Every level of the pyramid buffer byte for byte: the oracle's level with
     a replicated p-pixel border, as (R, G, B, 0) words."""
