@@ -176,6 +176,24 @@ def test_caller_energies_of_any_size(ctx):
     assert np.array_equal(host(en).view(np.uint32), Eo.astype(np.uint32))
 
 
+@pytest.mark.parametrize("p", [3, 4])
+def test_saturated_values_large_patches(ctx, p):
+    """Binary 0/255 noise with the largest patches: patch sums reach
+    (2p+1)^2 * 255 and the table bound's 16-bit differences and 32-bit sums of
+    squares their extremes; fields and energies stay bit-exact."""
+    h, w, levels, iters = 96, 136, 2, 3
+    rng = np.random.default_rng(40 + p)
+    S = (rng.integers(0, 2, (h, w, 3)) * 255).astype(np.uint8)
+    T = (rng.integers(0, 2, (h, w, 3)) * 255).astype(np.uint8)
+    T[: h // 2] = 255                       # a saturated half: sums at their maximum
+    seed, pair = 0xC0FFEE + p, 11
+    prm = fbm.make_params(p, levels, iters, seed)
+    pa, pb = ctx.fb_build_pyramid(dev(S), levels, p), ctx.fb_build_pyramid(dev(T), levels, p)
+    (nnf, en), = ctx.fb_patchmatch_batch([dict(src_pyr=pa, tgt_pyr=pb, h=h, w=w, levels=levels, pair_id=pair)], prm)
+    F, E = oracle.patchmatch(S, T, p, levels, iters, seed, pair)
+    assert_field_equal(nnf, en, F, E, "p=%d" % p)
+
+
 def test_seed_offsets_init(ctx):
     h, w, p = 45, 66, 2
     S, T = pair_images(h, w, 5)
