@@ -162,8 +162,9 @@ fb_status fb_nnf_init(fb_ctx *ctx, const void *src_pyr, const void *tgt_pyr, int
 /* Otherwise nnf / energy are read as the starting field (e.g. from         */
 /* fb_nnf_init): field entries are clamped into the level, energies are    */
 /* taken as given (any uint32; a pixel moves only to a candidate whose     */
-/* loss is strictly lower).  Then params->iters concurrent iterations run: each pixel  */
-/* tries propagation F(v+d)-d for d = (-1,0),(1,0),(0,-1),(0,1), then       */
+/* loss is strictly lower).  Then params->iters concurrent iterations     */
+/* run: each pixel tries propagation F(v+d)-d for d = (-1,0),(1,0),(0,-1), */
+/* (0,1), then                                                              */
 /* random search around its running best at radii max(h_l,w_l) >> m, and   */
 /* keeps a candidate only if its loss is strictly lower.  Writes nnf and    */
 /* energy (int32 [h_l][w_l][2], uint32 [h_l][w_l]) in place.               */
