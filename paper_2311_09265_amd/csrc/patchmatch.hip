@@ -301,7 +301,7 @@ k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unif
 // With the style loss and p <= 2 the kernel is held to 5 waves per SIMD
 // (at most 96 VGPRs, no spills); larger patches keep the compiler's choice.
 template <int P, int TW, int TH, int MODE>
-__global__ void __launch_bounds__(TW *TH, ((MODE & kIterStyle) && P <= 2) ? 5 * 256 / (TW * TH) : 1)
+__global__ void __launch_bounds__(TW *TH, ((MODE & kIterStyle) && P <= 2) ? 5 : 1)
 k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles, int iter,
           uint32_t k0, uint32_t k1) {
     constexpr bool STYLE = (MODE & kIterStyle) != 0, TRACK = (MODE & kIterTrack) != 0;

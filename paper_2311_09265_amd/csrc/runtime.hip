@@ -1261,10 +1261,10 @@ fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, i
     // tracking neighbours (same key, adjacent target frames) and alignment
     // partners (same target frame, the other key)
     std::vector<int> pair_frame;
-    for (int i = 0, q = 0; i < N; ++i) {
+    for (int i = 0; i < N; ++i) {
         if (kself[i] >= 0) continue;
         for (int side = 0; side < 2; ++side)
-            if ((side == 0 ? kl[i] : kr[i]) >= 0) { pair_frame.push_back(i); ++q; }
+            if ((side == 0 ? kl[i] : kr[i]) >= 0) pair_frame.push_back(i);
     }
     for (size_t a = 0; a < pairs.size(); ++a)
         for (size_t b = 0; b < pairs.size(); ++b) {
