@@ -92,6 +92,8 @@ struct PMJob {
     int32_t tab_shift;         // bound table of the source level (see the layout above):
     int32_t tab_w, tab_n;      //   block shift, width in blocks, entries (0: no table)
     const uint32_t *btab;
+    const uint32_t *f_prev;    // Eq. 3 refresh: the field the level's previous refresh used
+                               //   (nullptr: refresh every pixel)
 };
 static_assert(sizeof(PMJob) % 8 == 0, "PMJob is copied as an array");
 

@@ -498,21 +498,43 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
 // ((2 sum + count) / (2 count)), as (R,G,B,0) pixels written into the padded
 // sty_hat together with its replicated border, so the loss never clamps.
 // The tile's field entries with a P-pixel border are staged in LDS once.
+// After a level's first iteration (f_prev set) only the waves whose field
+// neighbourhood changed since the previous refresh recompute their pixels.
 template <int P, int TW, int TH>
 __global__ void __launch_bounds__(TW *TH)
 k_style_refresh(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles) {
     constexpr int SW = TW + 2 * P, SH = TH + 2 * P;
+    constexpr int WROWS = TW < 64 ? 64 / TW : 1;  // tile rows of one wave
     __shared__ uint32_t sf[SH * SW];
+    __shared__ uint32_t s_rowch[SH];  // staged row holds an entry that differs from f_prev
     const TileCoord tc = locate<TW, TH>(jobs, n_jobs, total_tiles, uniform_tiles);
     const PMJob &J = jobs[tc.job];
     const int h = J.h, w = J.w, pitch = J.pitch, r = tc.r, c = tc.c;
     const int rt = r - (int)threadIdx.y, ct = c - (int)threadIdx.x;  // tile origin
-    for (int i = (int)(threadIdx.y * TW + threadIdx.x); i < SH * SW; i += TW * TH) {
+    const int tid = (int)(threadIdx.y * TW + threadIdx.x);
+    const bool incr = J.f_prev != nullptr;  // the same for the whole workgroup
+    if (incr) {
+        for (int i = tid; i < SH; i += TW * TH) s_rowch[i] = 0u;
+        __syncthreads();
+    }
+    for (int i = tid; i < SH * SW; i += TW * TH) {
         const int yy = rt - P + i / SW, xx = ct - P + i % SW;
-        sf[i] = (yy >= 0 && yy < h && xx >= 0 && xx < w) ? gload<uint32_t>(J.f_in, 4u * (uint32_t)(yy * w + xx)) : 0u;
+        const bool in = yy >= 0 && yy < h && xx >= 0 && xx < w;
+        const uint32_t q = in ? gload<uint32_t>(J.f_in, 4u * (uint32_t)(yy * w + xx)) : 0u;
+        sf[i] = q;
+        if (incr && in && q != gload<uint32_t>(J.f_prev, 4u * (uint32_t)(yy * w + xx))) s_rowch[i / SW] = 1u;
     }
     __syncthreads();
     if (!tc.active) return;
+    if (incr) {
+        // S^ at a pixel depends only on the field entries within P of it: a wave
+        // whose pixels saw no change keeps the previous refresh's values (and
+        // border copies) in sty_hat
+        const int wr0 = (tid >> 6) * WROWS;
+        bool changed = false;
+        for (int y = wr0; y < wr0 + WROWS + 2 * P; ++y) changed |= s_rowch[y] != 0u;
+        if (!changed) return;
+    }
     uint32_t rb = 0, g = 0, cnt = 0;  // R and B sums in 16-bit halves; G alone
 #pragma unroll
     for (int dr = -P; dr <= P; ++dr) {

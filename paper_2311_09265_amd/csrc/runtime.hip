@@ -277,6 +277,9 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
                 for (size_t k : active) {
                     PMJob j = job_geom(pairs[k], l);
                     j.f_in = pairs[k].f[cur[k]];
+                    // after the level's first iteration the other buffer still holds
+                    // the field the previous refresh used
+                    if (it > 0) j.f_prev = pairs[k].f[cur[k] ^ 1];
                     js.push_back(j);
                 }
                 add_pm_launch(P, kLaunchStyleRefresh, js, cfg, p, seed, it);
