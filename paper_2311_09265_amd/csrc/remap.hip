@@ -110,6 +110,13 @@ k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__
             continue;
         }
         uint32_t rb = 0, g = 0;
+        // Where the field is one translation around v (F(v+d) - d = F(v) for
+        // every in-image d; packed, F(v+d) = F(v) + (d_r << 16) + d_c, and a
+        // borrow can never match a field entry since sides are below 2^15),
+        // every term of the sum is S(F(v)): a wave whose pixels all qualify
+        // gathers once per pixel instead of (2p+1)^2 times.
+        const uint32_t q0 = sf[((int)threadIdx.y + P) * SW + (int)threadIdx.x + P];
+        bool coherent = true;
 #pragma unroll
         for (int dr = -P; dr <= P; ++dr) {
             if (dr < r0 || dr > r1) continue;
@@ -117,11 +124,28 @@ k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__
 #pragma unroll
             for (int dc = -P; dc <= P; ++dc) {
                 if (dc < c0 || dc > c1) continue;
-                const uint32_t q = srow[dc];
-                const int sr = (int)(q >> 16) - dr + P, sc = (int)(q & 0xFFFFu) - dc + P;
-                const uint32_t px = gload<uint32_t>(sp, 4u * (uint32_t)(sr * pitch + sc));
-                rb += px & 0x00FF00FFu;
-                g += (px >> 8) & 0xFFu;
+                coherent &= srow[dc] == q0 + ((uint32_t)dr << 16) + (uint32_t)dc;
+            }
+        }
+        if (__all(coherent)) {
+            const int sr = (int)(q0 >> 16) + P, sc = (int)(q0 & 0xFFFFu) + P;
+            const uint32_t px = gload<uint32_t>(sp, 4u * (uint32_t)(sr * pitch + sc));
+            rb = (uint32_t)cnt_v * (px & 0x00FF00FFu);
+            g = (uint32_t)cnt_v * ((px >> 8) & 0xFFu);
+        } else {
+#pragma unroll
+            for (int dr = -P; dr <= P; ++dr) {
+                if (dr < r0 || dr > r1) continue;
+                const uint32_t *srow = sf + ((int)threadIdx.y + P + dr) * SW + (int)threadIdx.x + P;
+#pragma unroll
+                for (int dc = -P; dc <= P; ++dc) {
+                    if (dc < c0 || dc > c1) continue;
+                    const uint32_t q = srow[dc];
+                    const int sr = (int)(q >> 16) - dr + P, sc = (int)(q & 0xFFFFu) - dc + P;
+                    const uint32_t px = gload<uint32_t>(sp, 4u * (uint32_t)(sr * pitch + sc));
+                    rb += px & 0x00FF00FFu;
+                    g += (px >> 8) & 0xFFu;
+                }
             }
         }
         a0 += T.weight * ((float)(rb & 0xFFFFu) / denom);
