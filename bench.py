@@ -113,10 +113,10 @@ def bench_learned(ctx, fbm, g, s, out, M, p, levels, seed, wpath, args, pairs, N
         descs = [dict(src_pyr=pyrs[j], tgt_pyr=pyrs[i], h=h, w=w, levels=levels, pair_id=j * N + i)
                  for (j, i) in pairs]
         energies = [e for _, e in ctx.fb_patchmatch_batch(descs, lprm)]
-        energy = round(float(torch.stack(energies).double().mean().item()), 2)
+        energy = round(float(fbm.energy_u32(torch.stack(energies)).double().mean().item()), 2)
         pprm = fbm.make_params(p, levels, args.learned_iters, seed)
         energies = [e for _, e in ctx.fb_patchmatch_batch(descs, pprm)]
-        plain_same = round(float(torch.stack(energies).double().mean().item()), 2)
+        plain_same = round(float(fbm.energy_u32(torch.stack(energies)).double().mean().item()), 2)
         del energies, pyrs
     hc, wc = -(-h // (1 << (levels - 1))), -(-w // (1 << (levels - 1)))
     flops = fbm.load_library().fb_unet_forward_flops(len(pairs), -(-hc // 8) * 8, -(-wc // 8) * 8)
@@ -169,7 +169,7 @@ def bench_style(ctx, fbm, g, s, out, M, p, levels, iters, seed, args, pairs, N, 
         descs = [dict(src_pyr=pyrs[j], tgt_pyr=pyrs[i], src_style_pyr=spyrs[j], h=h, w=w, levels=levels,
                       pair_id=j * N + i) for (j, i) in pairs]
         energies = [e for _, e in ctx.fb_patchmatch_batch(descs, sprm)]
-        loss = round(float(torch.stack(energies).double().mean().item()) / 16.0, 2)
+        loss = round(float(fbm.energy_u32(torch.stack(energies)).double().mean().item()) / 16.0, 2)
         del energies, pyrs, spyrs
     return {"alpha": 1.0, "ms_per_step": round(ms, 3), "blended_frames_per_s": round(N / (ms / 1e3), 3),
             "mpix_iter_per_s": round(pix / (ms / 1e3) / 1e6, 3),
@@ -440,7 +440,7 @@ def main():
         descs = [dict(src_pyr=pyrs[j], tgt_pyr=pyrs[i], h=h, w=w, levels=levels, pair_id=j * N + i)
                  for (j, i) in pairs]
         energies = [e for _, e in ctx.fb_patchmatch_batch(descs, prm)]
-        mean_energy = round(float(torch.stack(energies).double().mean().item()), 2)
+        mean_energy = round(float(fbm.energy_u32(torch.stack(energies)).double().mean().item()), 2)
         del energies, pyrs
 
     fast = None

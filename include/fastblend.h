@@ -60,7 +60,10 @@ typedef enum {
  * incumbent is re-scored under it).  S^_i is kept as a uint8 image (each
  * channel's average rounded half up); alpha = alpha16 / 16 and the energies
  * are the loss scaled by 16, alpha16 SSD(G) + 16 SSD(S, S^), exact in
- * uint32.  Needs iters >= 1 and 0 <= alpha16 <= 512.  Taken by
+ * uint32.  Needs iters >= 1 and 0 <= alpha16 <= fb_alpha16_max(p): a patch
+ * SSD is at most 3 * 255^2 * (2p+1)^2, and (alpha16 + 16) times that must
+ * stay below 2^32 (alpha16 <= 512 for p = 1, 2; 433 for p = 3; 255 for
+ * p = 4); larger values return FB_E_INVALID.  Taken by
  * fb_blend_window (the styles are the sources' S_j) and fb_patchmatch_batch
  * (each descriptor's src_style_pyr); the per-level calls and
  * fb_interpolate return FB_E_UNSUPPORTED with it. */
@@ -79,8 +82,8 @@ typedef enum {
  * NNF is estimated again under alpha ||G_j[u] - G_i[v]||^2 + ||S_j[u] -
  * T^-_i[v]||^2 (alpha = alpha16 / 16, loss x 16 as for FB_STYLE_LOSS); the
  * output is the window mean of the styles remapped with the new NNFs.
- * Needs iters >= 1 and 0 <= alpha16 <= 512.  Taken by fb_blend_window only;
- * not with FB_STYLE_LOSS or FB_FAST_BLEND. */
+ * Needs iters >= 1 and 0 <= alpha16 <= fb_alpha16_max(p).  Taken by
+ * fb_blend_window only; not with FB_STYLE_LOSS or FB_FAST_BLEND. */
 #define FB_ACCURATE_BLEND 0x20u
 /* Interpolation extras (Section 3.5), taken by fb_interpolate only.  All
  * NNF(G_k, G_i) of the call are estimated together, level by level and
@@ -92,7 +95,8 @@ typedef enum {
  * alpha ||G_a[u] - G_i[v]||^2 + ||S_a[u] - S_b[F_b(v)]||^2 (a, b the two keys,
  * S the keyframe styles, F_b the partner's previous field), re-scoring the
  * incumbent every iteration; energies are the loss x 16, alpha = alpha16 / 16,
- * 1 <= alpha16 <= 512, iters >= 1; frames with one key keep Eq. 1. */
+ * 1 <= alpha16 <= fb_alpha16_max(p), iters >= 1; frames with one key keep
+ * Eq. 1. */
 #define FB_TRACKING 0x40u
 #define FB_ALIGN 0x80u
 
@@ -119,6 +123,11 @@ fb_status fb_create(int32_t device, fb_ctx **out);
 void fb_destroy(fb_ctx *ctx);
 /* Message of the last non-OK status on this thread ("" if none). */
 const char *fb_last_error(void);
+/* Largest alpha16 the scaled losses of FB_STYLE_LOSS (Eq. 3),
+ * FB_ACCURATE_BLEND (Eq. 8) and FB_ALIGN (Eq. 10) accept for patch radius p:
+ * min(512, floor((2^32 - 1) / (3 * 255^2 * (2p+1)^2)) - 16), so that every
+ * loss value fits its uint32 energy.  0 for p outside [1, 4]. */
+int32_t fb_alpha16_max(int32_t patch_radius);
 
 /* Tile shapes of the PatchMatch kernels.  By default the first batched call
  * of every batch shape times each shape on the finest-level iteration and

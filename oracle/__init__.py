@@ -23,10 +23,10 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile ``fb_oracle.c`` into ``liboracle.so`` next to it (gcc, -O2, OpenMP)."""
+    """Compile ``fb_oracle.c`` into ``liboracle.so`` next to it (gcc, -O3, OpenMP)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-std=c99", "-O2", "-fopenmp", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-std=c99", "-O3", "-fopenmp", "-fPIC", "-shared",
                                "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -72,7 +72,9 @@ def lib():
         L.fbo_remap_u8.argtypes = [u8p, i32p, I, I, I, u8p]
         L.fbo_remap_u8.restype = None
         L.fbo_style_loss.argtypes = [u8p, u8p, u8p, u8p, I, I, I, I, I, I, I, I]
-        L.fbo_style_loss.restype = U32
+        L.fbo_style_loss.restype = U64
+        L.fbo_alpha16_max.argtypes = [I]
+        L.fbo_alpha16_max.restype = I
         L.fbo_pm_iteration_style.argtypes = [u8p, u8p, u8p, I, I, I, I, I, I, U64, U32, i32p, i32p, u32p, u8p]
         L.fbo_pm_iteration_style.restype = None
         L.fbo_patchmatch_style.argtypes = [u8p, u8p, u8p, I, I, I, I, I, U64, U32, I, i32p, u32p,
@@ -253,8 +255,20 @@ def remap_u8(style, F, p: int) -> np.ndarray:
     return out
 
 
+def alpha16_max(p: int) -> int:
+    """Largest alpha16 whose scaled Eq. 3 / 8 / 10 losses fit the uint32
+    energies, min(512, floor((2^32 - 1) / (3 * 255^2 * (2p+1)^2)) - 16)."""
+    return int(lib().fbo_alpha16_max(int(p)))
+
+
+def _check_alpha16(p: int, alpha16: int) -> None:
+    if not 0 <= alpha16 <= alpha16_max(p):
+        raise ValueError("alpha16 must be in [0, %d] for p = %d" % (alpha16_max(p), p))
+
+
 def style_loss(Gs, Gt, Ss, Sh, p: int, alpha16: int, u, v) -> int:
-    """Eq. (3) for one match, scaled by 16: alpha16 SSD(G) + 16 SSD(S, S^)."""
+    """Eq. (3) for one match, scaled by 16: alpha16 SSD(G) + 16 SSD(S, S^),
+    exact (64-bit) for any alpha16."""
     Gs, Gt, Ss, Sh = _img(Gs), _img(Gt), _img(Ss), _img(Sh)
     h, w = Gs.shape[:2]
     return int(lib().fbo_style_loss(Gs, Gt, Ss, Sh, h, w, p, alpha16, int(u[0]), int(u[1]), int(v[0]), int(v[1])))
@@ -262,6 +276,7 @@ def style_loss(Gs, Gt, Ss, Sh, p: int, alpha16: int, u, v) -> int:
 
 def pm_iteration_style(Gs, Gt, Ss, p: int, alpha16: int, level: int, it: int, seed: int, pair_id: int, F):
     """One iteration under the Eq. (3) loss; returns (F, E, S^ of its refresh)."""
+    _check_alpha16(p, alpha16)
     Gs, Gt, Ss = _img(Gs), _img(Gt), _img(Ss)
     h, w = Gs.shape[:2]
     Fn = np.zeros((h, w, 2), np.int32)
@@ -338,6 +353,7 @@ def window_mean_u8(styles, i: int, js, fields, p: int) -> np.ndarray:
 
 def pm_iteration_target(Gs, Gt, Ss, Tb, p: int, alpha16: int, level: int, it: int, seed: int, pair_id: int, F):
     """One iteration under the Eq. 8 loss against a fixed T^- level."""
+    _check_alpha16(p, alpha16)
     Gs, Gt, Ss, Tb = _img(Gs), _img(Gt), _img(Ss), _img(Tb)
     h, w = Gs.shape[:2]
     Fn = np.zeros((h, w, 2), np.int32)
@@ -382,6 +398,8 @@ def pm_iteration_ext(Gs, Gt, Ss, Sp, p: int, alpha16: int, flags: int, level: in
     """One iteration of pair q of a jointly estimated interpolation (tracking
     and / or alignment, Section 3.5, Eq. 10); fields / energies: the previous
     fields and energies of all pairs.  Returns (F, E)."""
+    if flags & ALIGN:
+        _check_alpha16(p, alpha16)
     Gs, Gt, Ss, Sp = _img(Gs), _img(Gt), _img(Ss), _img(Sp)
     h, w = Gs.shape[:2]
     fs = [np.ascontiguousarray(f, np.int32) for f in fields]

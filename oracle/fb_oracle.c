@@ -350,9 +350,10 @@ void fbo_remap(const uint8_t *style, const int32_t *F, int h, int w, int p, doub
 /* Readings (the paper gives no precision for S^_i or alpha):               */
 /*   S^_i     a uint8 image: each channel of the Alg. 2 average rounded      */
 /*            half up, (2 sum + count) / (2 count) in integers;            */
-/*   alpha    fixed point, alpha = alpha16 / 16 with 0 <= alpha16 <= 512,   */
-/*            and the loss is scaled by 16 so that it stays an exact        */
-/*            integer: L = alpha16 SSD(G_j, G_i) + 16 SSD(S_j, S^_i).       */
+/*   alpha    fixed point, alpha = alpha16 / 16 with 0 <= alpha16 <=        */
+/*            fbo_alpha16_max(p), and the loss is scaled by 16 so that it   */
+/*            stays an exact integer: L = alpha16 SSD(G_j, G_i) + 16        */
+/*            SSD(S_j, S^_i), below 2^32 by the bound on alpha16.          */
 /* ------------------------------------------------------------------------ */
 
 /* S^ = Alg. 2 remap of `style` through F, as a uint8 image (rounded). */
@@ -377,12 +378,23 @@ void fbo_remap_u8(const uint8_t *style, const int32_t *F, int h, int w, int p, u
         }
 }
 
-/* Eq. (3) for one match, scaled by 16 (see above). */
-uint32_t fbo_style_loss(const uint8_t *Gs, const uint8_t *Gt, const uint8_t *Ss, const uint8_t *Sh,
+/* Eq. (3) for one match, scaled by 16 (see above), exact in 64 bits. */
+uint64_t fbo_style_loss(const uint8_t *Gs, const uint8_t *Gt, const uint8_t *Ss, const uint8_t *Sh,
                         int h, int w, int p, int alpha16, int ur, int uc, int vr, int vc)
 {
-    return (uint32_t)alpha16 * fbo_patch_ssd(Gs, Gt, h, w, p, ur, uc, vr, vc) +
-           16u * fbo_patch_ssd(Ss, Sh, h, w, p, ur, uc, vr, vc);
+    return (uint64_t)alpha16 * fbo_patch_ssd(Gs, Gt, h, w, p, ur, uc, vr, vc) +
+           16u * (uint64_t)fbo_patch_ssd(Ss, Sh, h, w, p, ur, uc, vr, vc);
+}
+
+/* Largest alpha16 whose scaled losses (Eq. 3, Eq. 8, Eq. 10) all fit the   */
+/* uint32 energies: one patch SSD is at most 3 * 255^2 * (2p+1)^2 (every    */
+/* channel difference 255), so the loss is at most (alpha16 + 16) times     */
+/* that; alpha16 is further limited to 512 (alpha <= 32).                   */
+int fbo_alpha16_max(int p)
+{
+    const uint64_t ssd_max = 3ull * 255 * 255 * (uint64_t)(2 * p + 1) * (uint64_t)(2 * p + 1);
+    const uint64_t a = 0xFFFFFFFFull / ssd_max - 16;
+    return a < 512 ? (int)a : 512;
 }
 
 /* One iteration under the Eq. (3) loss: S^ is refreshed from the previous   */
@@ -399,13 +411,13 @@ void fbo_pm_iteration_style(const uint8_t *Gs, const uint8_t *Gt, const uint8_t 
     for (int r = 0; r < h; ++r)
         for (int c = 0; c < w; ++c) {
             int br = Fo[2 * (r * w + c)], bc = Fo[2 * (r * w + c) + 1];
-            uint32_t be = fbo_style_loss(Gs, Gt, Ss, Sh, h, w, p, alpha16, br, bc, r, c);
+            uint64_t be = fbo_style_loss(Gs, Gt, Ss, Sh, h, w, p, alpha16, br, bc, r, c);
             for (int k = 0; k < 4; ++k) {
                 int qr = r + D[k][0], qc = c + D[k][1];
                 if (qr < 0 || qr >= h || qc < 0 || qc >= w) continue;
                 int cr = clampi(Fo[2 * (qr * w + qc)] - D[k][0], 0, h - 1);
                 int cc = clampi(Fo[2 * (qr * w + qc) + 1] - D[k][1], 0, w - 1);
-                uint32_t e = fbo_style_loss(Gs, Gt, Ss, Sh, h, w, p, alpha16, cr, cc, r, c);
+                uint64_t e = fbo_style_loss(Gs, Gt, Ss, Sh, h, w, p, alpha16, cr, cc, r, c);
                 if (e < be) { br = cr; bc = cc; be = e; }
             }
             uint32_t x[4] = { 0, 0, 0, 0 };
@@ -418,12 +430,12 @@ void fbo_pm_iteration_style(const uint8_t *Gs, const uint8_t *Gt, const uint8_t 
                 int dr = (int)fbo_uniform16(word & 0xFFFFu, (uint32_t)(2 * rho + 1)) - rho;
                 int dc = (int)fbo_uniform16(word >> 16, (uint32_t)(2 * rho + 1)) - rho;
                 int cr = clampi(br + dr, 0, h - 1), cc = clampi(bc + dc, 0, w - 1);
-                uint32_t e = fbo_style_loss(Gs, Gt, Ss, Sh, h, w, p, alpha16, cr, cc, r, c);
+                uint64_t e = fbo_style_loss(Gs, Gt, Ss, Sh, h, w, p, alpha16, cr, cc, r, c);
                 if (e < be) { br = cr; bc = cc; be = e; }
             }
             Fn[2 * (r * w + c)] = br;
             Fn[2 * (r * w + c) + 1] = bc;
-            En[r * w + c] = be;
+            En[r * w + c] = (uint32_t)be;  /* alpha16 <= fbo_alpha16_max(p): exact */
         }
 }
 
@@ -436,7 +448,7 @@ int fbo_patchmatch_style(const uint8_t *G0s, const uint8_t *G0t, const uint8_t *
                          int p, int levels, int iters, uint64_t seed, uint32_t pair_id, int alpha16,
                          int32_t *F, uint32_t *E, uint8_t *Sh0)
 {
-    if (levels < 1 || levels > 16 || h < 1 || w < 1 || p < 0 || iters < 1 || alpha16 < 0 || alpha16 > 512)
+    if (levels < 1 || levels > 16 || h < 1 || w < 1 || p < 0 || iters < 1 || alpha16 < 0 || alpha16 > fbo_alpha16_max(p))
         return FBO_E_INVALID;
     int hs[16], ws[16];
     const uint8_t *Gs[16], *Gt[16], *Ss[16];
@@ -782,13 +794,13 @@ void fbo_pm_iteration_target(const uint8_t *Gs, const uint8_t *Gt, const uint8_t
     for (int r = 0; r < h; ++r)
         for (int c = 0; c < w; ++c) {
             int br = Fo[2 * (r * w + c)], bc = Fo[2 * (r * w + c) + 1];
-            uint32_t be = fbo_style_loss(Gs, Gt, Ss, Tb, h, w, p, alpha16, br, bc, r, c);
+            uint64_t be = fbo_style_loss(Gs, Gt, Ss, Tb, h, w, p, alpha16, br, bc, r, c);
             for (int k = 0; k < 4; ++k) {
                 int qr = r + D[k][0], qc = c + D[k][1];
                 if (qr < 0 || qr >= h || qc < 0 || qc >= w) continue;
                 int cr = clampi(Fo[2 * (qr * w + qc)] - D[k][0], 0, h - 1);
                 int cc = clampi(Fo[2 * (qr * w + qc) + 1] - D[k][1], 0, w - 1);
-                uint32_t e = fbo_style_loss(Gs, Gt, Ss, Tb, h, w, p, alpha16, cr, cc, r, c);
+                uint64_t e = fbo_style_loss(Gs, Gt, Ss, Tb, h, w, p, alpha16, cr, cc, r, c);
                 if (e < be) { br = cr; bc = cc; be = e; }
             }
             uint32_t x[4] = { 0, 0, 0, 0 };
@@ -801,12 +813,12 @@ void fbo_pm_iteration_target(const uint8_t *Gs, const uint8_t *Gt, const uint8_t
                 int dr = (int)fbo_uniform16(word & 0xFFFFu, (uint32_t)(2 * rho + 1)) - rho;
                 int dc = (int)fbo_uniform16(word >> 16, (uint32_t)(2 * rho + 1)) - rho;
                 int cr = clampi(br + dr, 0, h - 1), cc = clampi(bc + dc, 0, w - 1);
-                uint32_t e = fbo_style_loss(Gs, Gt, Ss, Tb, h, w, p, alpha16, cr, cc, r, c);
+                uint64_t e = fbo_style_loss(Gs, Gt, Ss, Tb, h, w, p, alpha16, cr, cc, r, c);
                 if (e < be) { br = cr; bc = cc; be = e; }
             }
             Fn[2 * (r * w + c)] = br;
             Fn[2 * (r * w + c) + 1] = bc;
-            En[r * w + c] = be;
+            En[r * w + c] = (uint32_t)be;  /* alpha16 <= fbo_alpha16_max(p): exact */
         }
 }
 
@@ -816,7 +828,7 @@ int fbo_patchmatch_target(const uint8_t *G0s, const uint8_t *G0t, const uint8_t 
                           int w, int p, int levels, int iters, uint64_t seed, uint32_t pair_id, int alpha16,
                           int32_t *F, uint32_t *E)
 {
-    if (levels < 1 || levels > 16 || h < 1 || w < 1 || p < 0 || iters < 1 || alpha16 < 0 || alpha16 > 512)
+    if (levels < 1 || levels > 16 || h < 1 || w < 1 || p < 0 || iters < 1 || alpha16 < 0 || alpha16 > fbo_alpha16_max(p))
         return FBO_E_INVALID;
     int hs[16], ws[16];
     const uint8_t *Gs[16], *Gt[16], *Ss[16], *Tb[16];
@@ -869,7 +881,7 @@ done:
 int fbo_blend_window_accurate(const uint8_t *guides, const uint8_t *styles, int N, int h, int w, int M, int p,
                               int levels, int iters, uint64_t seed, int alpha16, double *out, uint8_t *tbar_out)
 {
-    if (N < 1 || M < 0 || iters < 1 || alpha16 < 0 || alpha16 > 512) return FBO_E_INVALID;
+    if (N < 1 || M < 0 || iters < 1 || alpha16 < 0 || alpha16 > fbo_alpha16_max(p)) return FBO_E_INVALID;
     size_t fpix = (size_t)h * w, n3 = fpix * 3;
     int wmax = 2 * M + 1 < N ? 2 * M + 1 : N;
     int32_t **F = (int32_t **)calloc((size_t)wmax, sizeof(int32_t *));
@@ -951,16 +963,16 @@ void fbo_pm_iteration_ext(const uint8_t *Gs, const uint8_t *Gt, const uint8_t *S
             int br = F[2 * v], bc = F[2 * v + 1];
             /* the partner's match fixes this iteration's alignment patch */
             const int pr = aligned ? Fo[partner][2 * v] : 0, pc = aligned ? Fo[partner][2 * v + 1] : 0;
-#define LOSS(UR, UC) (aligned ? (uint32_t)alpha16 * fbo_patch_ssd(Gs, Gt, h, w, p, UR, UC, r, c) + \
-                                    16u * fbo_patch_ssd(Ss, Sp, h, w, p, UR, UC, pr, pc)          \
-                              : fbo_patch_ssd(Gs, Gt, h, w, p, UR, UC, r, c))
-            uint32_t be = aligned ? LOSS(br, bc) : Eo[q][v];
+#define LOSS(UR, UC) (aligned ? (uint64_t)alpha16 * fbo_patch_ssd(Gs, Gt, h, w, p, UR, UC, r, c) + \
+                                    16u * (uint64_t)fbo_patch_ssd(Ss, Sp, h, w, p, UR, UC, pr, pc) \
+                              : (uint64_t)fbo_patch_ssd(Gs, Gt, h, w, p, UR, UC, r, c))
+            uint64_t be = aligned ? LOSS(br, bc) : Eo[q][v];
             for (int k = 0; k < 4; ++k) {
                 int qr = r + D[k][0], qc = c + D[k][1];
                 if (qr < 0 || qr >= h || qc < 0 || qc >= w) continue;
                 int cr = clampi(F[2 * (qr * w + qc)] - D[k][0], 0, h - 1);
                 int cc = clampi(F[2 * (qr * w + qc) + 1] - D[k][1], 0, w - 1);
-                uint32_t e = LOSS(cr, cc);
+                uint64_t e = LOSS(cr, cc);
                 if (e < be) { br = cr; bc = cc; be = e; }
             }
             if (flags & FBO_TRACK) {
@@ -968,7 +980,7 @@ void fbo_pm_iteration_ext(const uint8_t *Gs, const uint8_t *Gt, const uint8_t *S
                 for (int k = 0; k < 2; ++k) {
                     if (nb[k] < 0) continue;
                     int cr = Fo[nb[k]][2 * v], cc = Fo[nb[k]][2 * v + 1];
-                    uint32_t e = LOSS(cr, cc);
+                    uint64_t e = LOSS(cr, cc);
                     if (e < be) { br = cr; bc = cc; be = e; }
                 }
             }
@@ -981,13 +993,13 @@ void fbo_pm_iteration_ext(const uint8_t *Gs, const uint8_t *Gt, const uint8_t *S
                 int dr = (int)fbo_uniform16(word & 0xFFFFu, (uint32_t)(2 * rho + 1)) - rho;
                 int dc = (int)fbo_uniform16(word >> 16, (uint32_t)(2 * rho + 1)) - rho;
                 int cr = clampi(br + dr, 0, h - 1), cc = clampi(bc + dc, 0, w - 1);
-                uint32_t e = LOSS(cr, cc);
+                uint64_t e = LOSS(cr, cc);
                 if (e < be) { br = cr; bc = cc; be = e; }
             }
 #undef LOSS
             Fn[2 * v] = br;
             Fn[2 * v + 1] = bc;
-            En[v] = be;
+            En[v] = (uint32_t)be;  /* alpha16 <= fbo_alpha16_max(p): exact */
         }
 }
 
@@ -997,7 +1009,7 @@ int fbo_interpolate_ext(const uint8_t *guides, int N, int h, int w, const int32_
                         double *out)
 {
     if (N < 1 || n_keys < 1 || levels < 1 || levels > 16 || iters < 0) return FBO_E_INVALID;
-    if ((flags & FBO_ALIGN) && (iters < 1 || alpha16 < 1 || alpha16 > 512)) return FBO_E_INVALID;
+    if ((flags & FBO_ALIGN) && (iters < 1 || alpha16 < 1 || alpha16 > fbo_alpha16_max(p))) return FBO_E_INVALID;
     size_t fpix = (size_t)h * w, n3 = fpix * 3;
     int hs[16], ws[16];
     hs[0] = h; ws[0] = w;

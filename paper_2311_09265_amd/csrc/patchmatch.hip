@@ -26,9 +26,10 @@
 // sums t^2 stay in registers for the whole iteration; a source patch row is
 // one 16-byte + one 4-byte load from the padded image (no clamping needed).
 // Random-search candidates are divergent gathers, so the iteration kernel
-// fetches a candidate's patch piece by piece (the first four pixels of row
-// 0, then each complete row) and drops it as soon as the part fetched
-// already reaches the running best (exact: every pixel's loss is >= 0).
+// first tests a candidate against the bound table of its source block (no
+// pixel read), then fetches its patch row by row and drops it as soon as the
+// rows fetched already reach the running best (exact: every pixel's loss is
+// >= 0).
 //
 // Random draws: Philox4x32-10 (Salmon et al., SC'11), key = seed, counter =
 // (pixel index r*w + c, pair id, level << 16 | iteration, m >> 2); word m & 3
@@ -390,8 +391,9 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     // fetched only by lanes still in the race.  The sum of s^2 - 2 s t wraps
     // in uint32, but with the t^2 sums added back every partial loss is the
     // exact nonnegative value.  (Eq. 3: both terms are sums of squares, so the
-    // weighted partial sums are lower bounds in the same way; the weighted
-    // total stays below 2^32 for alpha16 <= 512.)
+    // weighted partial sums are lower bounds in the same way; the host admits
+    // only alpha16 with (alpha16 + 16) * 3 * 255^2 * (2p+1)^2 < 2^32, so the
+    // weighted total, and every partial sum below it, never wraps.)
     // (2p+1)^2 * be, saturated: a bound lb (< 2^32) at or above it rules the
     // candidate out (plain loss; be may be any energy a caller passed in)
     auto bound_threshold = [&]() {

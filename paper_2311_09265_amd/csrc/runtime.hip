@@ -630,6 +630,15 @@ fb_status check_unet_shape(int B, int h, int w) {
     return FB_OK;
 }
 
+// Largest alpha16 for which every scaled loss alpha16 SSD(G) + 16 SSD(S, X)
+// (Eq. 3, 8, 10) fits in uint32: a patch SSD is at most 3 * 255^2 * (2p+1)^2,
+// so (alpha16 + 16) times that must stay below 2^32; and alpha16 <= 512.
+int alpha16_max(int p) {
+    const uint64_t k = 2u * (uint64_t)p + 1u;
+    const uint64_t a = 0xFFFFFFFFull / (3ull * 255u * 255u * k * k) - 16u;
+    return (int)std::min<uint64_t>(a, 512u);
+}
+
 fb_status check_params(const fb_params *prm, bool need_levels) {
     if (!prm) return fail(FB_E_INVALID, "params is NULL");
     if (!valid_p(prm->patch_radius))
@@ -640,7 +649,10 @@ fb_status check_params(const fb_params *prm, bool need_levels) {
     if (prm->reserved != 0) return fail(FB_E_INVALID, "params->reserved must be 0");
     if (prm->flags & (FB_STYLE_LOSS | FB_ACCURATE_BLEND | FB_ALIGN)) {
         if (prm->iters < 1) return fail(FB_E_INVALID, "FB_STYLE_LOSS, FB_ACCURATE_BLEND and FB_ALIGN need iters >= 1");
-        if (prm->alpha16 < 0 || prm->alpha16 > 512) return fail(FB_E_INVALID, "alpha16 must be in [0, 512]");
+        const int amax = alpha16_max(prm->patch_radius);
+        if (prm->alpha16 < 0 || prm->alpha16 > amax)
+            return fail(FB_E_INVALID, "alpha16 must be in [0, " + std::to_string(amax) + "] for patch_radius " +
+                                          std::to_string(prm->patch_radius) + " (the loss must fit in uint32)");
         if ((prm->flags & FB_ALIGN) && prm->alpha16 < 1) return fail(FB_E_INVALID, "FB_ALIGN needs alpha16 >= 1");
     }
     return FB_OK;
@@ -930,6 +942,8 @@ void fb_destroy(fb_ctx *ctx) {
 }
 
 const char *fb_last_error(void) { return g_err.c_str(); }
+
+int32_t fb_alpha16_max(int32_t patch_radius) { return valid_p(patch_radius) ? alpha16_max(patch_radius) : 0; }
 
 fb_status fb_profile_enable(fb_ctx *ctx, int32_t on) {
     fb_status st = begin(ctx);

@@ -60,7 +60,8 @@ class fb_profile(ctypes.Structure):
 
 
 _lib = None
-_EXPORTS = ["fb_create", "fb_destroy", "fb_last_error", "fb_num_tile_configs", "fb_set_tile_config",
+_EXPORTS = ["fb_create", "fb_destroy", "fb_last_error", "fb_alpha16_max", "fb_num_tile_configs",
+            "fb_set_tile_config",
             "fb_pyramid_bytes", "fb_build_pyramid", "fb_nnf_init", "fb_patchmatch_level", "fb_remap",
             "fb_blend_window", "fb_interpolate", "fb_patchmatch_batch", "fb_profile_enable",
             "fb_profile_read", "fb_unet_param_count", "fb_unet_forward_flops", "fb_unet_load", "fb_unet_save",
@@ -81,6 +82,7 @@ def load_library(path: str = LIB_PATH):
         "fb_create": (i32, [i32, ctypes.POINTER(vp)]),
         "fb_destroy": (None, [vp]),
         "fb_last_error": (ctypes.c_char_p, []),
+        "fb_alpha16_max": (i32, [i32]),
         "fb_num_tile_configs": (i32, []),
         "fb_set_tile_config": (i32, [vp, i32]),
         "fb_pyramid_bytes": (sz, [i32, i32, i32, i32]),
@@ -145,6 +147,14 @@ def make_params(patch_radius: int = 2, levels: int = 3, iters: int = 6, seed: in
                 flags: int = 0, alpha16: int = 16) -> fb_params:
     """alpha16: the guide weight of the Eq. 3 loss (FB_STYLE_LOSS), alpha = alpha16 / 16."""
     return fb_params(patch_radius, levels, iters, flags, seed & 0xFFFFFFFFFFFFFFFF, alpha16, 0)
+
+
+def energy_u32(energy: torch.Tensor) -> torch.Tensor:
+    """The uint32 energies of the C ABI as int64 values.  The binding returns
+    energy tensors as int32 (torch's unsigned 32-bit type lacks most ops); a
+    value of 2^31 or more reads negative there, so compare or average this
+    view instead."""
+    return energy.to(torch.int64) & 0xFFFFFFFF
 
 
 def level_size(h: int, w: int, level: int):
@@ -278,7 +288,8 @@ class Context:
                             pair_id: int, nnf: Optional[torch.Tensor] = None,
                             energy: Optional[torch.Tensor] = None,
                             nnf_coarse: Optional[torch.Tensor] = None):
-        """Returns (nnf, energy) at ``level``; nnf/energy (int32) are updated in place if given."""
+        """Returns (nnf, energy) at ``level``; nnf/energy (int32) are updated in place if given.
+        Energies are uint32 values stored in int32 tensors (see ``energy_u32``)."""
         hl, wl = level_size(h, w, level)
         _check_pyr(src_pyr, "src_pyr", h, w, level + 1, params.patch_radius)
         _check_pyr(tgt_pyr, "tgt_pyr", h, w, level + 1, params.patch_radius)
@@ -333,7 +344,8 @@ class Context:
     def fb_patchmatch_batch(self, pairs: Sequence[dict], params: fb_params):
         """pairs: dicts with src_pyr, tgt_pyr, h, w, levels, pair_id[, seed_offsets]
         [, src_style_pyr (FB_STYLE_LOSS)].
-        Returns a list of (nnf int32 [h][w][2], energy int32 [h][w])."""
+        Returns a list of (nnf int32 [h][w][2], energy int32 [h][w]); the energies
+        are uint32 values stored in int32 tensors (see ``energy_u32``)."""
         descs = (fb_pair_desc * len(pairs))()
         outs, keep = [], []
         for k, d in enumerate(pairs):

@@ -100,3 +100,15 @@ def test_binding_structs_match_the_header(tmp_path):
         assert int(got[name]) == ctypes.sizeof(cls), name
         for f, _ in cls._fields_:
             assert int(got["%s.%s" % (name, f)]) == getattr(cls, f).offset, (name, f)
+
+
+def test_alpha16_bound_matches_the_oracle(lib):
+    """fb_alpha16_max (host-only) equals the oracle's bound and the largest
+    alpha16 <= 512 with (alpha16 + 16) * 3 * 255^2 * (2p+1)^2 < 2^32, in
+    Python integers; invalid radii give 0."""
+    import oracle
+    for p in range(1, 5):
+        worst = 3 * 255 * 255 * (2 * p + 1) ** 2
+        want = min(512, max(a for a in range(0, 2000) if (a + 16) * worst < 2 ** 32))
+        assert lib.fb_alpha16_max(p) == want == oracle.alpha16_max(p), p
+    assert lib.fb_alpha16_max(0) == 0 and lib.fb_alpha16_max(5) == 0

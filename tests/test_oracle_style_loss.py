@@ -145,3 +145,74 @@ def test_invalid_arguments_are_rejected():
         oracle.patchmatch_style(g[0], g[1], g[0], 2, 1, 0, 1, 0, 16)   # no iteration
     with pytest.raises(RuntimeError):
         oracle.patchmatch_style(g[0], g[1], g[0], 2, 1, 1, 1, 0, 513)  # alpha16 out of range
+
+
+# ---- the range of the scaled loss (Eq. 3; the same loss form serves Eq. 8 and Eq. 10) ----
+
+def _saturated(h, w, seed):
+    """Random 0 / 255 images: every channel difference is 0 or 255, so patch
+    SSDs reach the extreme 3 * 255^2 * (2p+1)^2 where the images are complements."""
+    rng = np.random.default_rng(seed)
+    return (rng.integers(0, 2, (h, w, 3)) * 255).astype(np.uint8)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_alpha16_bound_is_the_largest_that_fits_uint32(p):
+    """The accepted alpha16 range is exactly the one for which the worst-case
+    loss (alpha16 + 16) * 3 * 255^2 * (2p+1)^2, computed with Python's
+    unbounded integers, is below 2^32 (or the 512 cap)."""
+    worst = 3 * 255 * 255 * (2 * p + 1) ** 2
+    amax = oracle.alpha16_max(p)
+    assert (amax + 16) * worst < 2 ** 32
+    assert amax == 512 or (amax + 17) * worst >= 2 ** 32
+    assert {1: 512, 2: 512, 3: 433, 4: 255}[p] == amax
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_loss_is_exact_at_the_largest_alpha16(p):
+    """On saturated patches at the largest accepted alpha16 the oracle's loss
+    equals alpha16 SSD(G) + 16 SSD(S, S^) evaluated with Python integers from
+    an independent vectorised SSD, including the worst case (complementary
+    images, every difference 255) that a uint32 sum would wrap for larger
+    alpha16.  Above the bound the loss is still exact (64-bit), but the
+    coarse-to-fine run rejects the parameter because energies are uint32."""
+    from pins import ssd
+    h, w = 13, 14
+    amax = oracle.alpha16_max(p)
+    Gs, Ss = _saturated(h, w, 1), _saturated(h, w, 2)
+    Gt, Sh = 255 - Gs, 255 - Ss
+    worst = 3 * 255 * 255 * (2 * p + 1) ** 2
+    c = (6, 7)
+    assert oracle.style_loss(Gs, Gt, Ss, Sh, p, amax, c, c) == (amax + 16) * worst
+    assert oracle.style_loss(Gs, Gt, Ss, Sh, p, 512, c, c) == (512 + 16) * worst  # > 2^32 - 1, not wrapped
+    Gt2, Sh2 = _saturated(h, w, 3), _saturated(h, w, 4)
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        u = (int(rng.integers(0, h)), int(rng.integers(0, w)))
+        v = (int(rng.integers(0, h)), int(rng.integers(0, w)))
+        want = amax * ssd(Gs, Gt2, p, u, v) + 16 * ssd(Ss, Sh2, p, u, v)
+        assert oracle.style_loss(Gs, Gt2, Ss, Sh2, p, amax, u, v) == want
+    # the coarse-to-fine runs accept the bound and reject one more
+    F, E, _ = oracle.patchmatch_style(Gs, Gt, Ss, p, 1, 1, 3, 0, amax)
+    assert E.max() <= (amax + 16) * worst
+    with pytest.raises(RuntimeError):
+        oracle.patchmatch_style(Gs, Gt, Ss, p, 1, 1, 3, 0, amax + 1)
+    with pytest.raises(RuntimeError):
+        oracle.patchmatch_target(Gs, Gt, Ss, Sh, p, 1, 1, 3, 0, amax + 1)
+    with pytest.raises(ValueError):
+        oracle.pm_iteration_style(Gs, Gt, Ss, p, amax + 1, 0, 0, 3, 0, F)
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_saturated_run_at_the_bound_keeps_exact_energies(p):
+    """A whole Eq. 3 run at the largest alpha16 on saturated data: every
+    energy equals alpha16 SSD(G) + 16 SSD(S, S^) of its match, computed with
+    Python integers from the independent SSD and the final refresh S^."""
+    from pins import energy
+    h, w = 15, 17
+    amax = oracle.alpha16_max(p)
+    Gs, Gt, Ss = _saturated(h, w, 11), _saturated(h, w, 12), _saturated(h, w, 13)
+    F, E, Sh = oracle.patchmatch_style(Gs, Gt, Ss, p, 1, 2, 9, 4, amax)
+    want = amax * energy(Gs, Gt, F, p) + 16 * energy(Ss, Sh, F, p)
+    assert want.max() < 2 ** 32
+    assert np.array_equal(E.astype(np.int64), want)
