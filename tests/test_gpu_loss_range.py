@@ -37,11 +37,20 @@ def _sat(shape, seed):
 
 
 @pytest.mark.parametrize("p", [3, 4])
-def test_style_loss_at_the_largest_alpha16(ctx, p):
+@pytest.mark.parametrize("data", ["saturated", "opposite"])
+def test_style_loss_at_the_largest_alpha16(ctx, p, data):
+    """saturated: random 0 / 255 guides and style, where the search meets
+    losses near 2^31 on both sides of it; opposite: an all-0 source guide
+    against an all-255 target guide, so every guide SSD is the largest
+    possible and every energy lies in [2^31, 2^32) (uint32 exact, wrong if
+    read as signed)."""
     amax = oracle.alpha16_max(p)
     assert fbm.load_library().fb_alpha16_max(p) == amax
     h, w, K, iters, seed, pid = 40, 44, 2, 3, 5, 17
-    Gs, Gt, Ss = _sat((h, w, 3), 1), _sat((h, w, 3), 2), _sat((h, w, 3), 3)
+    if data == "saturated":
+        Gs, Gt, Ss = _sat((h, w, 3), 1), _sat((h, w, 3), 2), _sat((h, w, 3), 3)
+    else:
+        Gs, Gt, Ss = np.zeros((h, w, 3), np.uint8), np.full((h, w, 3), 255, np.uint8), _sat((h, w, 3), 4)
     desc = dict(src_pyr=ctx.fb_build_pyramid(dev(Gs), K, p), tgt_pyr=ctx.fb_build_pyramid(dev(Gt), K, p),
                 src_style_pyr=ctx.fb_build_pyramid(dev(Ss), K, p), h=h, w=w, levels=K, pair_id=pid)
     prm = fbm.make_params(p, K, iters, seed, fbm.FB_STYLE_LOSS, amax)
@@ -50,7 +59,8 @@ def test_style_loss_at_the_largest_alpha16(ctx, p):
     assert np.array_equal(host(nnf), F)
     e = fbm.energy_u32(en).cpu().numpy()
     assert np.array_equal(e, E.astype(np.int64))
-    assert e.max() >= 2 ** 31  # the range a signed read would get wrong is reached
+    if data == "opposite":
+        assert e.min() >= 2 ** 31 and e.max() < 2 ** 32
     with pytest.raises(fbm.FastBlendError):
         ctx.fb_patchmatch_batch([desc], fbm.make_params(p, K, iters, seed, fbm.FB_STYLE_LOSS, amax + 1))
 
