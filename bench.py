@@ -68,9 +68,29 @@ def pm_work(n_pairs, h, w, levels, iters, p):
     return pix, terms
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) and its logical CPU count."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
 def cpu_baseline(guides, pairs, p, levels, iters, seed, N, budget_s):
+    """The oracle on the host: as many of the blend's pairs as fit the time
+    budget on all threads, then one pair on one thread and the 64x64 pair
+    (1 level, 5 iterations) on one thread, median of 20."""
+    import numpy as np
     import oracle
+    from paper_2311_09265_amd import synth
     h, w = guides.shape[1:3]
+    threads = oracle.get_threads()
     done, t0 = 0, time.perf_counter()
     for (j, i) in pairs:
         oracle.patchmatch(guides[j], guides[i], p, levels, iters, seed, j * N + i)
@@ -79,10 +99,34 @@ def cpu_baseline(guides, pairs, p, levels, iters, seed, N, budget_s):
             break
     dt = time.perf_counter() - t0
     pix, _ = pm_work(done, h, w, levels, iters, p)
-    return {"value": round(pix / dt / 1e6, 3), "unit": "Mpix·iter/s", "cores": oracle.get_threads(),
-            "kind": "oracle",
+    model, ncpu = cpu_model()
+    single = {}
+    try:
+        oracle.set_threads(1)
+        (j, i) = pairs[0]
+        t1 = time.perf_counter()
+        oracle.patchmatch(guides[j], guides[i], p, levels, iters, seed, j * N + i)
+        d1 = time.perf_counter() - t1
+        pix1, _ = pm_work(1, h, w, levels, iters, p)
+        single["blend_pair"] = {"ms": round(d1 * 1e3, 2), "mpix_iter_per_s": round(pix1 / d1 / 1e6, 3),
+                                "pair": "%dx%d, %d levels x %d iterations" % (h, w, levels, iters)}
+        a, b, _ = synth.translation_pair(synth.CONFIG_SEED[1])
+        ts = []
+        for _ in range(20):
+            t1 = time.perf_counter()
+            oracle.patchmatch(a, b, p, 1, 5, synth.PHILOX_SEED[1], 0)
+            ts.append(time.perf_counter() - t1)
+        d1 = float(np.median(ts))
+        single["pair_64x64"] = {"ms_median_of_20": round(d1 * 1e3, 3),
+                                "mpix_iter_per_s": round(64 * 64 * 5 / d1 / 1e6, 3)}
+    finally:
+        oracle.set_threads(threads)
+    return {"value": round(pix / dt / 1e6, 3), "unit": "Mpix·iter/s", "cores": threads,
+            "kind": "oracle", "cpu_model": model, "logical_cpus": ncpu,
+            "build": "gcc -O3, OpenMP over rows, no hand-written SIMD",
             "sample": "%d of %d pairs, each the full %d-level x %d-iteration PatchMatch of a %dx%d pair "
-                      "(C oracle, OpenMP over rows), %.1f s" % (done, len(pairs), levels, iters, h, w, dt)}
+                      "(C oracle, %d threads), %.1f s" % (done, len(pairs), levels, iters, h, w, threads, dt),
+            "single_thread": single}
 
 
 def bench_learned(ctx, fbm, g, s, out, M, p, levels, seed, wpath, args, pairs, N, h, w, plain_energy):
@@ -287,6 +331,38 @@ def bench_interp(ctx, fbm, args):
     return res
 
 
+def bench_pair64(ctx, fbm, args):
+    """The 64x64 pair (value noise shifted by (3, -2) plus noise, 1 level, patch
+    5x5, 5 iterations): one fb_patchmatch_batch call, eager and replayed as a
+    HIP graph, median of 100 calls each (a latency figure: 20,480
+    pixel-iterations per call)."""
+    import numpy as np
+    import torch
+    from paper_2311_09265_amd import synth
+    a, b, _ = synth.translation_pair(synth.CONFIG_SEED[1])
+    pa = ctx.fb_build_pyramid(torch.from_numpy(a).cuda(), 1, 2)
+    pb = ctx.fb_build_pyramid(torch.from_numpy(b).cuda(), 1, 2)
+    desc = [dict(src_pyr=pa, tgt_pyr=pb, h=64, w=64, levels=1, pair_id=0)]
+    res = {"workload": "one 64x64 pair, 1 level, patch 5x5, 5 iterations", "pixel_iterations_per_call": 64 * 64 * 5}
+    for name, flags in (("eager", 0), ("graph", fbm.FB_USE_GRAPH)):
+        prm = fbm.make_params(2, 1, 5, synth.PHILOX_SEED[1], flags)
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            for _ in range(5):
+                ctx.fb_patchmatch_batch(desc, prm)
+            side.synchronize()
+            ts = []
+            for _ in range(100):
+                t0 = time.perf_counter()
+                ctx.fb_patchmatch_batch(desc, prm)
+                side.synchronize()
+                ts.append(time.perf_counter() - t0)
+        med = float(np.median(ts))
+        res[name] = {"ms_median_of_100": round(med * 1e3, 4), "mpix_iter_per_s": round(64 * 64 * 5 / med / 1e6, 3)}
+        log("64x64 pair, %s: %.3f ms per call" % (name, med * 1e3))
+    return res
+
+
 def bench_mixed(ctx, fbm, args):
     """The mixed-size batch: 12 pairs (t, t + d), d in 1..5, of each of 256x256
     and 512x512 (3 levels) and 1024x576 and 1280x720 (4 levels), 6 iterations:
@@ -372,6 +448,7 @@ def main():
     ap.add_argument("--no-accurate", action="store_true", help="skip the accurate-mode timing")
     ap.add_argument("--no-interp", action="store_true", help="skip the interpolation timings")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch timings")
+    ap.add_argument("--no-pair64", action="store_true", help="skip the 64x64 single-pair latency")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (counter calibration)")
     args = ap.parse_args()
@@ -455,6 +532,10 @@ def main():
     if not args.no_mixed:
         mixed = bench_mixed(ctx, fbm, args)
 
+    pair64 = None
+    if not args.no_pair64:
+        pair64 = bench_pair64(ctx, fbm, args)
+
     accurate = None
     if not args.no_accurate:
         accurate = bench_accurate(ctx, fbm, g, s, out, M, p, levels, iters, seed, args, N)
@@ -510,7 +591,8 @@ def main():
         "roofline": {"bound": "alu", "kernel": "k_pm_iter",
                      "achieved": round(achieved, 3), "peak": round(DOT4_PEAK_TOPS, 1), "unit": "TOP/s",
                      "frac": round(achieved / DOT4_PEAK_TOPS, 4), "traffic": traffic,
-                     "traffic_note": ("HBM bytes per launch, rocprofv3 FETCH_SIZE x %.2f + WRITE_SIZE x %.2f "
+                     "traffic_note": ("L2-to-fabric bytes per launch (includes Infinity-Cache hits, so an upper "
+                                      "bound on HBM bytes), rocprofv3 FETCH_SIZE x %.2f + WRITE_SIZE x %.2f "
                                       "(copy-calibrated), %s" % (traffic_info["fetch_scale"], traffic_info["write_scale"],
                                                                  traffic_info["summary"])
                                       if traffic is not None else traffic_info),
@@ -523,6 +605,7 @@ def main():
         "accurate_mode": accurate,
         "interpolation": interp,
         "mixed_batch": mixed,
+        "pair_64x64": pair64,
     }
     if learned:
         learned["speedup_vs_plain"] = round(ms / learned["ms_per_step"], 3)
