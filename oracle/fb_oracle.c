@@ -259,10 +259,49 @@ void fbo_pm_iteration(const uint8_t *S, const uint8_t *T, int h, int w, int p, i
 /* `iters` iterations at every level, upsampling between levels.             */
 /* `seed_off` (optional) is an int32 offset field at the coarsest level.     */
 /* ------------------------------------------------------------------------ */
+/* Convergence guard of a seeded run (a project addition; the paper's       */
+/* Alg. 1 starts from random fields and has no such rule).  When the seed   */
+/* is a prediction, the finest level may still be far from converged after  */
+/* the reduced iteration count, so: with P the sum of E over the level      */
+/* before its last iteration and C the sum after it (64-bit integers), the  */
+/* level runs one more iteration while 100 (P - C) > tau_pct P, at most     */
+/* max_extra times, each with the next iteration index (iters, iters + 1,   */
+/* ...), P and C moving to the last two sums.  max_extra = 0: no guard.     */
+/* ------------------------------------------------------------------------ */
+static uint64_t sum_u32(const uint32_t *E, size_t n)
+{
+    uint64_t s = 0;
+    for (size_t i = 0; i < n; ++i) s += E[i];
+    return s;
+}
+
+static int patchmatch_impl(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, int levels,
+                           int iters, uint64_t seed, uint32_t pair_id, const int32_t *seed_off,
+                           int max_extra, int tau_pct, int32_t *F, uint32_t *E, int *extra_out);
+
 int fbo_patchmatch(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, int levels,
                    int iters, uint64_t seed, uint32_t pair_id, const int32_t *seed_off,
                    int32_t *F, uint32_t *E)
 {
+    return patchmatch_impl(S0, T0, h, w, p, levels, iters, seed, pair_id, seed_off, 0, 0, F, E, NULL);
+}
+
+/* fbo_patchmatch with the convergence guard above at the finest level      */
+/* (needs iters >= 1); *extra_out receives the number of extra iterations.  */
+int fbo_patchmatch_guarded(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, int levels,
+                           int iters, uint64_t seed, uint32_t pair_id, const int32_t *seed_off,
+                           int max_extra, int tau_pct, int32_t *F, uint32_t *E, int *extra_out)
+{
+    if (iters < 1 || max_extra < 0 || tau_pct < 0) return FBO_E_INVALID;
+    return patchmatch_impl(S0, T0, h, w, p, levels, iters, seed, pair_id, seed_off, max_extra, tau_pct, F, E,
+                           extra_out);
+}
+
+static int patchmatch_impl(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, int levels,
+                           int iters, uint64_t seed, uint32_t pair_id, const int32_t *seed_off,
+                           int max_extra, int tau_pct, int32_t *F, uint32_t *E, int *extra_out)
+{
+    if (extra_out) *extra_out = 0;
     if (levels < 1 || levels > 16 || h < 1 || w < 1 || p < 0) return FBO_E_INVALID;
     int hs[16], ws[16];
     const uint8_t *Sl[16], *Tl[16];
@@ -302,6 +341,20 @@ int fbo_patchmatch(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, in
             fbo_pm_iteration(Sl[l], Tl[l], hl, wl, p, l, it, seed, pair_id, Fa, Ea, Fb, Eb);
             int32_t *tf = Fa; Fa = Fb; Fb = tf;
             uint32_t *te = Ea; Ea = Eb; Eb = te;
+        }
+        if (l == 0 && max_extra > 0) {
+            /* Eb: E before the last iteration, Ea: after it */
+            uint64_t P = sum_u32(Eb, n0), C = sum_u32(Ea, n0);
+            int extra = 0;
+            while (extra < max_extra && 100u * (P - C) > (uint64_t)tau_pct * P) {
+                fbo_pm_iteration(Sl[0], Tl[0], h, w, p, 0, iters + extra, seed, pair_id, Fa, Ea, Fb, Eb);
+                int32_t *tf = Fa; Fa = Fb; Fb = tf;
+                uint32_t *te = Ea; Ea = Eb; Eb = te;
+                P = C;
+                C = sum_u32(Ea, n0);
+                ++extra;
+            }
+            if (extra_out) *extra_out = extra;
         }
     }
     memcpy(F, Fa, n0 * 2 * sizeof(int32_t));
