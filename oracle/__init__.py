@@ -63,9 +63,9 @@ def lib():
         L.fbo_pm_iteration.restype = None
         L.fbo_patchmatch.argtypes = [u8p, u8p, I, I, I, I, I, U64, U32, ctypes.c_void_p, i32p, u32p]
         L.fbo_patchmatch.restype = I
-        L.fbo_patchmatch_guarded.argtypes = [u8p, u8p, I, I, I, I, I, U64, U32, ctypes.c_void_p, I, I, i32p, u32p,
-                                             ctypes.POINTER(ctypes.c_int)]
-        L.fbo_patchmatch_guarded.restype = I
+        L.fbo_patchmatch_raced.argtypes = [u8p, u8p, I, I, I, I, I, I, U64, U32, ctypes.c_void_p, i32p, u32p,
+                                           ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int)]
+        L.fbo_patchmatch_raced.restype = I
         L.fbo_remap.argtypes = [u8p, i32p, I, I, I, f64p]
         L.fbo_remap.restype = None
         L.fbo_blend_window.argtypes = [u8p, u8p, I, I, I, I, I, I, I, U64, f64p]
@@ -227,27 +227,26 @@ def patchmatch(S, T, p: int, levels: int, iters: int, seed: int, pair_id: int,
     return F, E
 
 
-GUARD_MAX_EXTRA, GUARD_TAU_PCT = 4, 1
-
-
-def patchmatch_guarded(S, T, p: int, levels: int, iters: int, seed: int, pair_id: int, seed_offsets,
-                       max_extra: int = GUARD_MAX_EXTRA, tau_pct: int = GUARD_TAU_PCT):
-    """Seeded NNF(S, T) with the convergence guard at the finest level: while
-    the last iteration lowered the level's summed energy by more than tau_pct
-    percent, one more iteration (next iteration index), at most max_extra.
-    Returns (F, E, number of extra iterations)."""
+def patchmatch_raced(S, T, p: int, levels: int, iters: int, plain_iters: int, seed: int, pair_id: int,
+                     seed_offsets):
+    """Seeded NNF(S, T) under the guard of a seeded run: at the coarsest level
+    the seeded start with `iters` iterations races the random start with
+    `plain_iters` iterations; if the seeded level's summed energy is the
+    larger, the whole result is the plain run (plain_iters iterations per
+    level), else the seeded run.  Returns (F, E, rejected, (seeded sum,
+    plain sum))."""
     S, T = _img(S), _img(T)
     h, w = S.shape[:2]
     F = np.zeros((h, w, 2), np.int32)
     E = np.zeros((h, w), np.uint32)
     off = np.ascontiguousarray(seed_offsets, np.int32)
-    extra = ctypes.c_int(0)
-    st = lib().fbo_patchmatch_guarded(S, T, h, w, p, levels, iters, seed, pair_id,
-                                      off.ctypes.data_as(ctypes.c_void_p), max_extra, tau_pct, F, E,
-                                      ctypes.byref(extra))
+    sums = (ctypes.c_uint64 * 2)()
+    rej = ctypes.c_int(0)
+    st = lib().fbo_patchmatch_raced(S, T, h, w, p, levels, iters, plain_iters, seed, pair_id,
+                                    off.ctypes.data_as(ctypes.c_void_p), F, E, sums, ctypes.byref(rej))
     if st != 0:
-        raise RuntimeError("fbo_patchmatch_guarded failed: %d" % st)
-    return F, E, int(extra.value)
+        raise RuntimeError("fbo_patchmatch_raced failed: %d" % st)
+    return F, E, bool(rej.value), (int(sums[0]), int(sums[1]))
 
 
 def remap(style, F, p: int) -> np.ndarray:

@@ -259,14 +259,26 @@ void fbo_pm_iteration(const uint8_t *S, const uint8_t *T, int h, int w, int p, i
 /* `iters` iterations at every level, upsampling between levels.             */
 /* `seed_off` (optional) is an int32 offset field at the coarsest level.     */
 /* ------------------------------------------------------------------------ */
-/* Convergence guard of a seeded run (a project addition; the paper's       */
-/* Alg. 1 starts from random fields and has no such rule).  When the seed   */
-/* is a prediction, the finest level may still be far from converged after  */
-/* the reduced iteration count, so: with P the sum of E over the level      */
-/* before its last iteration and C the sum after it (64-bit integers), the  */
-/* level runs one more iteration while 100 (P - C) > tau_pct P, at most     */
-/* max_extra times, each with the next iteration index (iters, iters + 1,   */
-/* ...), P and C moving to the last two sums.  max_extra = 0: no guard.     */
+static int patchmatch_impl(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, int levels,
+                           int iters, uint64_t seed, uint32_t pair_id, const int32_t *seed_off,
+                           int32_t *F, uint32_t *E);
+
+int fbo_patchmatch(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, int levels,
+                   int iters, uint64_t seed, uint32_t pair_id, const int32_t *seed_off,
+                   int32_t *F, uint32_t *E)
+{
+    return patchmatch_impl(S0, T0, h, w, p, levels, iters, seed, pair_id, seed_off, F, E);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Guard of a seeded run (a project addition: the learned proposal replaces  */
+/* Alg. 1's random initialisation, and Alg. 1 itself has no such rule).  At  */
+/* the coarsest level the seeded start followed by `iters` iterations races  */
+/* the random start followed by `plain_iters` iterations; sums[0], sums[1]   */
+/* are the two levels' summed energies (64-bit).  If the seeded sum is the   */
+/* larger, the seed is rejected and the result is the plain run (random      */
+/* start, plain_iters iterations at every level); otherwise it is the seeded */
+/* run (iters iterations at every level).  *rejected: 1 if plain was taken.  */
 /* ------------------------------------------------------------------------ */
 static uint64_t sum_u32(const uint32_t *E, size_t n)
 {
@@ -275,33 +287,66 @@ static uint64_t sum_u32(const uint32_t *E, size_t n)
     return s;
 }
 
-static int patchmatch_impl(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, int levels,
-                           int iters, uint64_t seed, uint32_t pair_id, const int32_t *seed_off,
-                           int max_extra, int tau_pct, int32_t *F, uint32_t *E, int *extra_out);
-
-int fbo_patchmatch(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, int levels,
-                   int iters, uint64_t seed, uint32_t pair_id, const int32_t *seed_off,
-                   int32_t *F, uint32_t *E)
+/* the coarsest level's summed energy after `iters` iterations from a seeded */
+/* (seed_off) or random (seed_off == NULL) start                             */
+static int coarse_energy(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, int levels, int iters,
+                         uint64_t seed, uint32_t pair_id, const int32_t *seed_off, uint64_t *sum)
 {
-    return patchmatch_impl(S0, T0, h, w, p, levels, iters, seed, pair_id, seed_off, 0, 0, F, E, NULL);
+    const int l = levels - 1;
+    int hl = h, wl = w;
+    for (int k = 0; k < l; ++k) { hl = (hl + 1) / 2; wl = (wl + 1) / 2; }
+    const size_t n = (size_t)hl * wl;
+    const size_t nb = (size_t)h * w * 3;
+    uint8_t *S = (uint8_t *)malloc(nb), *T = (uint8_t *)malloc(nb), *tmp = (uint8_t *)malloc(nb);
+    int32_t *Fa = (int32_t *)malloc(n * 2 * sizeof(int32_t)), *Fb = (int32_t *)malloc(n * 2 * sizeof(int32_t));
+    uint32_t *Ea = (uint32_t *)malloc(n * sizeof(uint32_t)), *Eb = (uint32_t *)malloc(n * sizeof(uint32_t));
+    int status = FBO_OK;
+    if (!S || !T || !tmp || !Fa || !Fb || !Ea || !Eb) { status = FBO_E_ALLOC; goto out; }
+    memcpy(S, S0, nb);
+    memcpy(T, T0, nb);
+    {
+        int hc = h, wc = w;
+        for (int k = 0; k < l; ++k) {
+            const size_t no = (size_t)((hc + 1) / 2) * ((wc + 1) / 2) * 3;
+            fbo_downsample(S, hc, wc, tmp);
+            memcpy(S, tmp, no);
+            fbo_downsample(T, hc, wc, tmp);
+            memcpy(T, tmp, no);
+            hc = (hc + 1) / 2;
+            wc = (wc + 1) / 2;
+        }
+    }
+    if (seed_off) fbo_nnf_init_offsets(S, T, hl, wl, p, seed_off, Fa, Ea);
+    else fbo_nnf_init_random(S, T, hl, wl, p, l, seed, pair_id, Fa, Ea);
+    for (int it = 0; it < iters; ++it) {
+        fbo_pm_iteration(S, T, hl, wl, p, l, it, seed, pair_id, Fa, Ea, Fb, Eb);
+        int32_t *tf = Fa; Fa = Fb; Fb = tf;
+        uint32_t *te = Ea; Ea = Eb; Eb = te;
+    }
+    *sum = sum_u32(Ea, n);
+out:
+    free(S); free(T); free(tmp); free(Fa); free(Fb); free(Ea); free(Eb);
+    return status;
 }
 
-/* fbo_patchmatch with the convergence guard above at the finest level      */
-/* (needs iters >= 1); *extra_out receives the number of extra iterations.  */
-int fbo_patchmatch_guarded(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, int levels,
-                           int iters, uint64_t seed, uint32_t pair_id, const int32_t *seed_off,
-                           int max_extra, int tau_pct, int32_t *F, uint32_t *E, int *extra_out)
+int fbo_patchmatch_raced(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, int levels,
+                         int iters, int plain_iters, uint64_t seed, uint32_t pair_id, const int32_t *seed_off,
+                         int32_t *F, uint32_t *E, uint64_t *sums, int *rejected)
 {
-    if (iters < 1 || max_extra < 0 || tau_pct < 0) return FBO_E_INVALID;
-    return patchmatch_impl(S0, T0, h, w, p, levels, iters, seed, pair_id, seed_off, max_extra, tau_pct, F, E,
-                           extra_out);
+    if (!seed_off || iters < 0 || plain_iters < 0 || levels < 1 || levels > 16 || h < 1 || w < 1 || p < 0)
+        return FBO_E_INVALID;
+    int st = coarse_energy(S0, T0, h, w, p, levels, iters, seed, pair_id, seed_off, &sums[0]);
+    if (st == FBO_OK) st = coarse_energy(S0, T0, h, w, p, levels, plain_iters, seed, pair_id, NULL, &sums[1]);
+    if (st != FBO_OK) return st;
+    *rejected = sums[0] > sums[1];
+    if (*rejected) return patchmatch_impl(S0, T0, h, w, p, levels, plain_iters, seed, pair_id, NULL, F, E);
+    return patchmatch_impl(S0, T0, h, w, p, levels, iters, seed, pair_id, seed_off, F, E);
 }
 
 static int patchmatch_impl(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, int levels,
                            int iters, uint64_t seed, uint32_t pair_id, const int32_t *seed_off,
-                           int max_extra, int tau_pct, int32_t *F, uint32_t *E, int *extra_out)
+                           int32_t *F, uint32_t *E)
 {
-    if (extra_out) *extra_out = 0;
     if (levels < 1 || levels > 16 || h < 1 || w < 1 || p < 0) return FBO_E_INVALID;
     int hs[16], ws[16];
     const uint8_t *Sl[16], *Tl[16];
@@ -341,20 +386,6 @@ static int patchmatch_impl(const uint8_t *S0, const uint8_t *T0, int h, int w, i
             fbo_pm_iteration(Sl[l], Tl[l], hl, wl, p, l, it, seed, pair_id, Fa, Ea, Fb, Eb);
             int32_t *tf = Fa; Fa = Fb; Fb = tf;
             uint32_t *te = Ea; Ea = Eb; Eb = te;
-        }
-        if (l == 0 && max_extra > 0) {
-            /* Eb: E before the last iteration, Ea: after it */
-            uint64_t P = sum_u32(Eb, n0), C = sum_u32(Ea, n0);
-            int extra = 0;
-            while (extra < max_extra && 100u * (P - C) > (uint64_t)tau_pct * P) {
-                fbo_pm_iteration(Sl[0], Tl[0], h, w, p, 0, iters + extra, seed, pair_id, Fa, Ea, Fb, Eb);
-                int32_t *tf = Fa; Fa = Fb; Fb = tf;
-                uint32_t *te = Ea; Ea = Eb; Eb = te;
-                P = C;
-                C = sum_u32(Ea, n0);
-                ++extra;
-            }
-            if (extra_out) *extra_out = extra;
         }
     }
     memcpy(F, Fa, n0 * 2 * sizeof(int32_t));
