@@ -44,8 +44,8 @@ def param_count() -> int:
     return sum(9 * ci * co + co for ci, co, _ in LAYERS)
 
 
-def unflatten(flat: torch.Tensor):
-    flat = flat.to(torch.float64)
+def unflatten(flat: torch.Tensor, dt=torch.float64):
+    flat = flat.to(dt)
     out, off = [], 0
     for ci, co, _ in LAYERS:
         w = flat[off:off + 9 * ci * co].reshape(co, ci, 3, 3)
@@ -69,18 +69,23 @@ def init_params(seed: int) -> torch.Tensor:
 
 
 def rb(x: torch.Tensor, emulate: bool) -> torch.Tensor:
-    return x.to(torch.bfloat16).to(torch.float64) if emulate else x
+    return x.to(torch.bfloat16).to(x.dtype) if emulate else x
 
 
 def _conv(x, w, b, emulate):
     return Fn.conv2d(x, rb(w, emulate), b, padding=1)
 
 
-def forward(flat, pair6, emulate_bf16: bool = True):
-    """Returns (pred NHWC [B][h][w][2] fp64, cache for backward)."""
+def forward(flat, pair6, emulate_bf16: bool = True, acc=torch.float64):
+    """Returns (pred NHWC [B][h][w][2], cache for backward).
+
+    acc is the type every sum is accumulated in: fp64 (the reference), or
+    fp32 to measure how far a change of accumulation precision alone moves
+    the bf16-rounded results (the tolerance of the GPU comparison is derived
+    from that spread)."""
     e = emulate_bf16
-    P = unflatten(flat)
-    x = rb(2.0 * pair6.to(torch.float64).permute(0, 3, 1, 2) - 1.0, e)
+    P = unflatten(flat, acc)
+    x = rb(2.0 * pair6.to(acc).permute(0, 3, 1, 2) - 1.0, e)
     acts = {"x0": x}
 
     def conv(i, inp):
@@ -106,17 +111,18 @@ def forward(flat, pair6, emulate_bf16: bool = True):
 
 
 def loss_value(pred, target, mask):
-    pred, target, mask = pred.to(torch.float64), target.to(torch.float64), mask.to(torch.float64)
+    dt = pred.dtype if pred.dtype in (torch.float32, torch.float64) else torch.float64
+    pred, target, mask = pred.to(dt), target.to(dt), mask.to(dt)
     d = torch.clamp(mask.sum(), min=1.0)
     return (mask[..., None] * (pred - target).abs()).sum() / d
 
 
-def loss_and_grads(flat, pair6, target, mask, emulate_bf16: bool = True):
-    """(loss, flat gradient fp64) by the hand-derived backward pass."""
+def loss_and_grads(flat, pair6, target, mask, emulate_bf16: bool = True, acc=torch.float64):
+    """(loss, flat gradient) by the hand-derived backward pass, accumulated in acc."""
     e = emulate_bf16
-    pred, (P, A) = forward(flat, pair6, e)
-    target = target.to(torch.float64)
-    mask = mask.to(torch.float64)
+    pred, (P, A) = forward(flat, pair6, e, acc)
+    target = target.to(acc)
+    mask = mask.to(acc)
     loss = loss_value(pred, target, mask)
     d = torch.clamp(mask.sum(), min=1.0)
     gpred = rb(mask[..., None] * torch.sign(pred - target) / d, e).permute(0, 3, 1, 2)
