@@ -151,6 +151,26 @@ def bench_learned(ctx, fbm, g, s, out, M, p, levels, seed, wpath, args, pairs, N
     prof = ctx.fb_profile_read(reset=True)
     ctx.fb_profile_enable(False)
     log("learned: %.2f ms/step" % ms)
+    # the guard: each seeded pair's coarsest level raced against plain@6 there
+    gs = ctx.fb_guard_read()
+    rejected = int((gs[:, 0] > gs[:, 1]).sum())
+    nprm = fbm.make_params(p, levels, args.learned_iters, seed, fbm.FB_LEARNED_SEED | fbm.FB_NO_GUARD)
+    ctx.fb_blend_window(g, s, M, nprm, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.fb_blend_window(g, s, M, nprm, out=out)
+    torch.cuda.synchronize()
+    ms_unguarded = (time.perf_counter() - t0) / args.steps * 1e3
+    log("learned without the guard: %.2f ms/step" % ms_unguarded)
+    guard = {"rule": "each seeded pair's coarsest level (seeded start, %d iterations) is raced against the "
+                     "plain random start (6 iterations); a seed whose summed energy is the larger is rejected "
+                     "and the pair's result is plain@6 exactly" % args.learned_iters,
+             "pairs": int(gs.shape[0]), "rejected": rejected,
+             "firing_rate": round(rejected / max(int(gs.shape[0]), 1), 4),
+             "seeded_over_plain_coarse_energy_mean": round(float((gs[:, 0].double() / gs[:, 1].double()).mean()), 4),
+             "ms_per_step_without_guard": round(ms_unguarded, 3),
+             "guard_cost_ms_per_step": round(ms - ms_unguarded, 3)}
     energy = plain_same = None
     if not args.no_energy:
         pyrs = [ctx.fb_build_pyramid(g[f], levels, p) for f in range(N)]
@@ -173,7 +193,7 @@ def bench_learned(ctx, fbm, g, s, out, M, p, levels, seed, wpath, args, pairs, N
             "iters_per_level": args.learned_iters, "pixel_iterations_per_step": pix,
             "mean_level0_patch_energy": energy, "plain_mean_level0_patch_energy": plain_energy,
             "plain_same_iters_mean_level0_patch_energy": plain_same,
-            "energy_margin": margin, "accepted": accepted,
+            "energy_margin": margin, "accepted": accepted, "guard": guard,
             "speedup_vs_plain": None,
             "kernel_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in prof.items() if v[0]},
             "network_roofline": {"bound": "mfma", "kernel": "k_conv3x3 (forward)", "achieved": round(tf, 3),

@@ -29,7 +29,13 @@
  * - Results are bit-identical for any batch composition, launch shape or
  *   graph replay: the random draws of a pixel depend only on (seed, pair id,
  *   level, iteration, pixel), never on where the pair sits in a batch.
- * - One fb_ctx may be used by one host thread at a time.
+ * - One fb_ctx may be used by one host thread at a time.  A context keeps a
+ *   workspace (pyramids, fields, launch tables) that grows on demand; its
+ *   calls run on the device in call order whatever their streams (a call on
+ *   another stream than the previous one waits on the device for it).  Launch
+ *   tables go to the device with stream-ordered copies from a ring of eight
+ *   slots; the host waits only when a slot is reused while the work that
+ *   last read it is still running, or when the workspace grows.
  */
 #ifndef FASTBLEND_H
 #define FASTBLEND_H
@@ -54,6 +60,11 @@ typedef enum {
 #define FB_USE_GRAPH   0x1u  /* replay the batched launch sequence as a HIP graph */
 #define FB_NO_AUTOTUNE 0x2u  /* use the default tile shape, skip the autotuner    */
 #define FB_LEARNED_SEED 0x4u /* seed the coarsest level with the proposal network */
+/* With FB_LEARNED_SEED, a seeded pair of a plain (Eq. 1) pass is raced, at
+ * its coarsest level, against the plain random start with plain_iters
+ * iterations (see fb_params and fb_guard_read); FB_NO_GUARD takes every seed
+ * as it is. */
+#define FB_NO_GUARD 0x100u
 /* Guide + style loss, Eq. 3 (Section 3.4): alpha ||G_j[u] - G_i[v]||^2 +
  * ||S_j[u] - S^_i[v]||^2, where S^_i is the source style S_j remapped (Alg. 2)
  * through the current field, refreshed at the start of every iteration (the
@@ -110,7 +121,9 @@ typedef struct {
     uint32_t flags;        /* FB_USE_GRAPH | FB_NO_AUTOTUNE | FB_LEARNED_SEED | FB_STYLE_LOSS */
     uint64_t seed;         /* key of the Philox4x32-10 draws                   */
     int32_t alpha16;       /* FB_STYLE_LOSS: guide weight alpha = alpha16 / 16 */
-    int32_t reserved;      /* must be 0                                        */
+    int32_t plain_iters;   /* FB_LEARNED_SEED: iterations per level of the     */
+                           /* plain run a seed is raced against and falls back */
+                           /* to; 0 selects 6; 0 <= plain_iters <= 65534       */
 } fb_params;
 
 typedef struct fb_ctx fb_ctx;
@@ -198,8 +211,7 @@ fb_status fb_remap(fb_ctx *ctx, const uint8_t *style, const int32_t *nnf, int32_
 /* S_j -> S_i remaps style j with NNF(G_j, G_i) estimated over `levels`     */
 /* levels (pair id j*N + i), and the j == i term is S_i / 255.              */
 /* guides, styles uint8 [N][h][w][3]; out fp32 [N][h][w][3].  Every pair of */
-/* the window runs batched, level by level.  The call may wait for the      */
-/* stream when its launch plan changes (new shapes or pointers).            */
+/* the window runs batched, level by level.                               */
 /* ---------------------------------------------------------------------- */
 fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, int32_t n_frames,
                           int32_t h, int32_t w, int32_t radius_M, const fb_params *params,
@@ -298,6 +310,28 @@ fb_status fb_unet_gradients(fb_ctx *ctx, const float *pair6, const float *target
                             int32_t B, int32_t h, int32_t w, float *grads, float *loss, void *stream);
 fb_status fb_unet_train_step(fb_ctx *ctx, const float *pair6, const float *target, const float *mask,
                              int32_t B, int32_t h, int32_t w, float lr, float *loss, void *stream);
+/* Guard of a seeded run.  With FB_LEARNED_SEED (and not FB_NO_GUARD), every
+ * pair of a plain (Eq. 1) pass that starts from offsets -- predicted by the
+ * network or given in its descriptor -- is raced at its coarsest level: the
+ * seeded start with params->iters iterations against the random start of
+ * Alg. 1 with plain_iters iterations.  If the seeded level's summed energy
+ * is the larger, the seed is rejected and the pair's result is the plain
+ * run exactly (random start, plain_iters iterations at every level);
+ * otherwise the seeded run's.  The launch sequence does not depend on the
+ * outcome (graph replay is unaffected).  Passes under FB_STYLE_LOSS,
+ * FB_TRACKING or FB_ALIGN, and the Eq. 8 pass of FB_ACCURATE_BLEND, take
+ * seeds unguarded.
+ * fb_guard_read waits for `stream` and returns, for the pairs of the last
+ * fb_blend_window / fb_interpolate / fb_patchmatch_batch call in the order
+ * that call planned them (the batch: descriptor order; the blend: target
+ * frame i ascending, then source j ascending; interpolation: frame, then
+ * left before right key), sums[2k] = the seeded and sums[2k+1] = the plain
+ * summed coarsest-level energy of pair k (both 0 for an unguarded pair), for
+ * at most max_pairs pairs (host array of 2 * max_pairs); *n_pairs receives
+ * the call's pair count.  Pair k's seed was rejected iff
+ * sums[2k] > sums[2k+1]. */
+fb_status fb_guard_read(fb_ctx *ctx, uint64_t *sums, int32_t max_pairs, int32_t *n_pairs, void *stream);
+
 /* The network input of one pair exactly as FB_LEARNED_SEED builds it: the
  * coarsest level (levels - 1) of both pyramids, padded to multiples of 8 by
  * repeating the last row / column, pair6 float [H8][W8][6] = pixels / 255. */

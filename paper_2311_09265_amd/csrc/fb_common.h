@@ -94,6 +94,18 @@ struct PMJob {
     const uint32_t *btab;
     const uint32_t *f_prev;    // Eq. 3 refresh: the field the level's previous refresh used
                                //   (nullptr: refresh every pixel)
+    // Guard of a seeded pair (its coarsest level raced against the plain
+    // random start): guard points at the pair's two summed coarsest-level
+    // energies (seeded, plain); the seed is rejected when the first is the
+    // larger.  Iteration launches: guard_when 1 runs the job only for a
+    // rejected seed, 2 only for a kept one, 0 always.  k_energy_sum: guard
+    // is the sum the job's energies e_in are added to.  k_guard_select: for
+    // a rejected seed, (f_alt, e_alt) is copied over (f_out, e_out).
+    uint64_t *guard;
+    const uint32_t *f_alt;
+    const uint32_t *e_alt;
+    int32_t guard_when;
+    int32_t guard_pad;
 };
 static_assert(sizeof(PMJob) % 8 == 0, "PMJob is copied as an array");
 
@@ -144,14 +156,23 @@ hipError_t launch_pm_start(const PMJob *jobs, int n_jobs, int total_tiles, int u
 // incumbent instead of reading e_in; bit kIterTrack: tracking candidates
 enum IterMode : int { kIterPlain = 0, kIterStyle = 1, kIterTrack = 2 };
 // tab_bytes: LDS for the largest bound table among the jobs (12 * max tab_n)
+// guarded: every job runs only for one outcome of the guard of seeded pairs
+// (guard_when != 0, plain mode): a fixed grid that skips the tiles of jobs
+// that do not run
 hipError_t launch_pm_iter(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
                           TileCfg cfg, int p, int iter, uint64_t seed, int mode, int tab_bytes,
-                          hipStream_t s);
+                          hipStream_t s, bool guarded = false);
 // S^ = Alg. 2 remap of src_sty through f_in, rounded, into sty_hat (border replicated)
 hipError_t launch_style_refresh(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
                                 TileCfg cfg, int p, hipStream_t s);
 hipError_t launch_pm_export(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
                             TileCfg cfg, hipStream_t s);
+// guard of seeded pairs: sum of each job's energies e_in into *guard; copy
+// of (f_alt, e_alt) over (f_out, e_out) for the jobs whose seed was rejected
+hipError_t launch_energy_sum(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
+                             TileCfg cfg, hipStream_t s);
+hipError_t launch_guard_select(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
+                               TileCfg cfg, hipStream_t s);
 
 hipError_t launch_remap_sum(const RemapFrame *frames, int n_frames, const RemapTerm *terms,
                             int h, int w, int pitch, int p, hipStream_t s);

@@ -196,10 +196,10 @@ struct TileCoord {
     bool active;
 };
 
+// flat tile t of a launch: its job, and this thread's pixel in it
 template <int TW, int TH>
-__device__ __forceinline__ TileCoord locate(const PMJob *__restrict__ jobs, int n_jobs,
-                                            int total_tiles, int uniform_tiles) {
-    const int t = xcd_tile((int)blockIdx.x, total_tiles);
+__device__ __forceinline__ TileCoord locate_tile(const PMJob *__restrict__ jobs, int n_jobs, int uniform_tiles,
+                                                 int t) {
     const int j = find_job(jobs, n_jobs, uniform_tiles, t);
     const int lt = t - jobs[j].tile_base;
     const int tx_n = jobs[j].tiles_x;
@@ -210,6 +210,12 @@ __device__ __forceinline__ TileCoord locate(const PMJob *__restrict__ jobs, int 
     tc.c = tx * TW + (int)threadIdx.x;
     tc.active = tc.r < jobs[j].h && tc.c < jobs[j].w;
     return tc;
+}
+
+template <int TW, int TH>
+__device__ __forceinline__ TileCoord locate(const PMJob *__restrict__ jobs, int n_jobs,
+                                            int total_tiles, int uniform_tiles) {
+    return locate_tile<TW, TH>(jobs, n_jobs, uniform_tiles, xcd_tile((int)blockIdx.x, total_tiles));
 }
 
 // The tile's padded target pixels with their patch border, (TH + 2P) rows of
@@ -301,20 +307,23 @@ k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unif
 // fetched.
 // With the style loss and p <= 2 the kernel is held to 5 waves per SIMD
 // (at most 96 VGPRs, no spills); larger patches keep the compiler's choice.
+// One tile (flat index `tile`) of an iteration launch, staged in the workgroup's
+// LDS arrays; every thread of the workgroup calls it with the same t.
 template <int P, int TW, int TH, int MODE>
-__global__ void __launch_bounds__(TW *TH, ((MODE & kIterStyle) && P <= 2) ? 5 : 1)
-k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles, int iter,
-          uint32_t k0, uint32_t k1) {
+__device__ __forceinline__ void pm_iter_tile(const PMJob *__restrict__ jobs, int n_jobs, int uniform_tiles,
+                                             int tile, int iter, uint32_t k0, uint32_t k1, uint32_t *s_tgt, uint32_t *s_f,
+                                             u32x4 *s_btab4) {
     constexpr bool STYLE = (MODE & kIterStyle) != 0, TRACK = (MODE & kIterTrack) != 0;
     constexpr int K = 2 * P + 1;
-    constexpr int SW = TW + 2 * P, SH = TH + 2 * P;  // target tile with its patch border
     constexpr int FW = TW + 2, FH = TH + 2;          // field tile with a 1-entry border
-    __shared__ uint32_t s_tgt[SH * SW];
-    __shared__ uint32_t s_f[FH * FW];
-    extern __shared__ u32x4 s_btab4[];  // the three 16-bit-pair arrays of the bound table
+    constexpr int SW = TW + 2 * P;                   // target tile row with its patch border
     const uint32_t *s_btab = reinterpret_cast<const uint32_t *>(s_btab4);
-    const TileCoord tc = locate<TW, TH>(jobs, n_jobs, total_tiles, uniform_tiles);
+    const TileCoord tc = locate_tile<TW, TH>(jobs, n_jobs, uniform_tiles, tile);
     const PMJob &J = jobs[tc.job];
+    if (J.guard_when != 0) {  // the same for the whole workgroup
+        const bool rejected = J.guard[0] > J.guard[1];
+        if (rejected != (J.guard_when == 1)) return;
+    }
     const int h = J.h, w = J.w, pitch = J.pitch, r = tc.r, c = tc.c;
     const int tab_n = J.tab_n;  // the same for the whole workgroup
     stage_target_tile<P, TW, TH>(s_tgt, J, tc);
@@ -495,6 +504,36 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
     gstore<uint32_t>(J.e_out, 4u * v, be);
 }
 
+template <int P, int TW, int TH, int MODE>
+__global__ void __launch_bounds__(TW *TH, ((MODE & kIterStyle) && P <= 2) ? 5 : 1)
+k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles, int iter,
+          uint32_t k0, uint32_t k1) {
+    __shared__ uint32_t s_tgt[(TH + 2 * P) * (TW + 2 * P)];  // target tile with its patch border
+    __shared__ uint32_t s_f[(TH + 2) * (TW + 2)];            // field tile with a 1-entry border
+    extern __shared__ u32x4 s_btab4[];  // the three 16-bit-pair arrays of the bound table
+    pm_iter_tile<P, TW, TH, MODE>(jobs, n_jobs, uniform_tiles, xcd_tile((int)blockIdx.x, total_tiles), iter, k0,
+                                  k1, s_tgt, s_f, s_btab4);
+}
+
+// An iteration launch whose jobs all run only for some outcome of the guard
+// of seeded pairs (guard_when != 0): a fixed grid walks the flat tiles and
+// skips the tiles of jobs that do not run, at the cost of a few scalar loads,
+// so a launch with nothing to do costs microseconds, not a workgroup per tile.
+template <int P, int TW, int TH>
+__global__ void __launch_bounds__(TW *TH)
+k_pm_iter_guarded(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles, int iter,
+                  uint32_t k0, uint32_t k1) {
+    __shared__ uint32_t s_tgt[(TH + 2 * P) * (TW + 2 * P)];
+    __shared__ uint32_t s_f[(TH + 2) * (TW + 2)];
+    extern __shared__ u32x4 s_btab4[];
+    for (int t = (int)blockIdx.x; t < total_tiles; t += (int)gridDim.x) {
+        const PMJob &J = jobs[find_job(jobs, n_jobs, uniform_tiles, t)];
+        if (J.guard_when != 0 && (J.guard[0] > J.guard[1]) != (J.guard_when == 1)) continue;
+        __syncthreads();  // the previous tile's LDS contents have been read
+        pm_iter_tile<P, TW, TH, kIterPlain>(jobs, n_jobs, uniform_tiles, t, iter, k0, k1, s_tgt, s_f, s_btab4);
+    }
+}
+
 // S^ of Eq. 3 for one iteration: the Alg. 2 remap of the source style level
 // through the field f_in, each channel's average rounded half up
 // ((2 sum + count) / (2 count)), as (R,G,B,0) pixels written into the padded
@@ -577,6 +616,38 @@ k_pm_export(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uni
     J.energy_abi[v] = J.e_in[v];
 }
 
+// Sum of the tile's energies e_in, added to *J.guard (64-bit, so the order of
+// the additions cannot change the result).
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW *TH)
+k_energy_sum(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles) {
+    __shared__ unsigned long long s_sum[TW * TH];
+    const TileCoord tc = locate<TW, TH>(jobs, n_jobs, total_tiles, uniform_tiles);
+    const PMJob &J = jobs[tc.job];
+    const int tid = (int)(threadIdx.y * TW + threadIdx.x);
+    s_sum[tid] = tc.active ? (unsigned long long)J.e_in[tc.r * J.w + tc.c] : 0ull;
+    __syncthreads();
+    for (int k = TW * TH / 2; k > 0; k >>= 1) {
+        if (tid < k) s_sum[tid] += s_sum[tid + k];
+        __syncthreads();
+    }
+    if (tid == 0) atomicAdd(reinterpret_cast<unsigned long long *>(J.guard), s_sum[0]);
+}
+
+// For a rejected seed, the plain run's field and energies replace the seeded
+// run's.
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW *TH)
+k_guard_select(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles) {
+    const TileCoord tc = locate<TW, TH>(jobs, n_jobs, total_tiles, uniform_tiles);
+    if (!tc.active) return;
+    const PMJob &J = jobs[tc.job];
+    if (!(J.guard[0] > J.guard[1])) return;
+    const int v = tc.r * J.w + tc.c;
+    J.f_out[v] = J.f_alt[v];
+    J.e_out[v] = J.e_alt[v];
+}
+
 // int32 [h][w][2] field -> packed; entries are clamped into the image so a
 // malformed field can never steer a later gather outside the padded image.
 __global__ void __launch_bounds__(256)
@@ -588,6 +659,7 @@ k_field_to_packed(const int32_t *__restrict__ abi, uint32_t *__restrict__ packed
 }
 
 constexpr TileCfg kTileCfgs[] = {{64, 4}, {32, 8}, {16, 16}, {64, 2}};
+constexpr int kGuardedGrid = 2048;  // workgroups of a guarded iteration launch (8 per CU)
 
 }  // namespace
 
@@ -626,10 +698,22 @@ hipError_t launch_pm_start(const PMJob *jobs, int n_jobs, int total_tiles, int u
 
 hipError_t launch_pm_iter(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
                           TileCfg cfg, int p, int iter, uint64_t seed, int mode, int tab_bytes,
-                          hipStream_t s) {
+                          hipStream_t s, bool guarded) {
     if (total_tiles <= 0) return hipSuccess;
     if (mode < 0 || mode > 3 || tab_bytes < 0 || tab_bytes > kBoundTabBytes) return hipErrorInvalidValue;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (guarded) {
+        if (mode != kIterPlain) return hipErrorInvalidValue;
+        const int grid = total_tiles < kGuardedGrid ? total_tiles : kGuardedGrid;
+#define FB_GITER2(P_, TW, TH)                                                                           \
+    hipLaunchKernelGGL((k_pm_iter_guarded<P_, TW, TH>), dim3(grid), dim3(TW, TH), (size_t)tab_bytes, s, \
+                       jobs, n_jobs, total_tiles, uniform_tiles, iter, k0, k1)
+#define FB_GITER(TW, TH) FB_P_SWITCH(p, FB_GITER2, TW, TH)
+        FB_TILE_SWITCH(cfg, FB_GITER)
+#undef FB_GITER
+#undef FB_GITER2
+        return hipGetLastError();
+    }
 #define FB_ITER3(P_, TW, TH, M_)                                                                   \
     hipLaunchKernelGGL((k_pm_iter<P_, TW, TH, M_>), dim3(total_tiles), dim3(TW, TH), (size_t)tab_bytes, \
                        s, jobs, n_jobs, total_tiles, uniform_tiles, iter, k0, k1)
@@ -667,6 +751,28 @@ hipError_t launch_pm_export(const PMJob *jobs, int n_jobs, int total_tiles, int 
                        n_jobs, total_tiles, uniform_tiles)
     FB_TILE_SWITCH(cfg, FB_EXPORT)
 #undef FB_EXPORT
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_sum(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
+                             TileCfg cfg, hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+#define FB_ESUM(TW, TH)                                                                       \
+    hipLaunchKernelGGL((k_energy_sum<TW, TH>), dim3(total_tiles), dim3(TW, TH), 0, s, jobs,   \
+                       n_jobs, total_tiles, uniform_tiles)
+    FB_TILE_SWITCH(cfg, FB_ESUM)
+#undef FB_ESUM
+    return hipGetLastError();
+}
+
+hipError_t launch_guard_select(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
+                               TileCfg cfg, hipStream_t s) {
+    if (total_tiles <= 0) return hipSuccess;
+#define FB_GSEL(TW, TH)                                                                       \
+    hipLaunchKernelGGL((k_guard_select<TW, TH>), dim3(total_tiles), dim3(TW, TH), 0, s, jobs, \
+                       n_jobs, total_tiles, uniform_tiles)
+    FB_TILE_SWITCH(cfg, FB_GSEL)
+#undef FB_GSEL
     return hipGetLastError();
 }
 

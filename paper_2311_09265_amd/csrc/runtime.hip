@@ -92,7 +92,8 @@ void assign_tiles(std::vector<PMJob> &jobs, TileCfg cfg, int *total, int *unifor
     *uniform = uni > 0 ? uni : 0;
 }
 
-enum LaunchKind { kLaunchStart, kLaunchIter, kLaunchStyleRefresh, kLaunchExport };
+enum LaunchKind { kLaunchStart, kLaunchIter, kLaunchStyleRefresh, kLaunchExport, kLaunchEnergySum,
+                  kLaunchGuardSelect };
 
 // LDS an iteration launch stages: the largest source bound table of its jobs
 int max_tab_bytes(const std::vector<PMJob> &jobs) {
@@ -118,9 +119,11 @@ void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cf
         break;
     case kLaunchIter: {
         const int tab_bytes = max_tab_bytes(jobs);
+        bool guarded = true;  // every job runs only for one outcome of the guard
+        for (const PMJob &j : jobs) guarded &= j.guard_when != 0;
         P.ops.push_back({FB_KERNEL_PM_ITER, [=](hipStream_t s, const uint8_t *tab) {
             return launch_pm_iter(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform,
-                                  cfg, p, iter, seed, mode, tab_bytes, s);
+                                  cfg, p, iter, seed, mode, tab_bytes, s, guarded);
         }});
         break;
     }
@@ -134,6 +137,16 @@ void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cf
         P.ops.push_back({FB_KERNEL_PM_EXPORT, [=](hipStream_t s, const uint8_t *tab) {
             return launch_pm_export(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform,
                                     cfg, s);
+        }});
+        break;
+    case kLaunchEnergySum:
+        P.ops.push_back({FB_KERNEL_OTHER, [=](hipStream_t s, const uint8_t *tab) {
+            return launch_energy_sum(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform, cfg, s);
+        }});
+        break;
+    case kLaunchGuardSelect:
+        P.ops.push_back({FB_KERNEL_OTHER, [=](hipStream_t s, const uint8_t *tab) {
+            return launch_guard_select(reinterpret_cast<const PMJob *>(tab + off), n, total, uniform, cfg, s);
         }});
         break;
     }
@@ -184,6 +197,21 @@ struct PairSpec {
     int partner = -1;                  // Eq. 10: the pair it is aligned with
     const uint8_t *partner_sty_pyr = nullptr;  // Eq. 10: the partner's source style pyramid
     int final_buf;             // filled by the planner
+    // guard of a seeded pair: its index among the call's guarded pairs (-1:
+    // none) and the plain run's ping-pong buffers at its coarsest level
+    int guard_slot = -1;
+    uint32_t *rf[2] = {nullptr, nullptr}, *re[2] = {nullptr, nullptr};
+};
+
+// The guard of the seeded pairs of one call: each pair with guard_slot >= 0
+// races its seeded coarsest level (iters iterations) against the plain random
+// start (plain_iters iterations); sums[2 g], sums[2 g + 1] receive the two
+// summed energies of guarded pair g.  A rejected pair continues as the plain
+// run (plain_iters iterations at every level).
+struct GuardPlan {
+    int plain_iters = 0;
+    uint64_t *sums = nullptr;
+    int n = 0;
 };
 
 PMJob job_geom(const PairSpec &ps, int l) {
@@ -237,18 +265,40 @@ std::string tune_key_of(const std::vector<PairSpec> &pairs, int p) {
 // fixed_target) the second patch is each pair's fixed T^-: no refresh.
 // Tracking (track) and the pairwise alignment loss (align, pairs with a
 // partner) read the fields the other pairs start the same iteration from.
+// With a guard (plain passes only), every guarded pair also runs the plain
+// random start at its coarsest level in its own buffers; the two levels'
+// energies are summed; a pair whose seed lost takes the plain field and runs
+// plain_iters iterations at the finer levels (launch jobs that only run for
+// a rejected or only for a kept seed), so the launch sequence is the same
+// whatever the outcome.
 void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, uint64_t seed,
                      TileCfg cfg, bool style = false, int alpha16 = 0, bool fixed_target = false,
-                     bool track = false, bool align = false) {
+                     bool track = false, bool align = false, const GuardPlan *guard = nullptr) {
     int kmax = 0;
     for (const PairSpec &ps : pairs) kmax = std::max(kmax, ps.L.levels);
-    std::vector<int> cur(pairs.size(), 0);
+    const bool guarded = guard && guard->n > 0;
+    const int plain_iters = guarded ? guard->plain_iters : iters;
+    const int it_common = std::min(iters, plain_iters), it_all = std::max(iters, plain_iters);
+    if (guarded) {
+        uint64_t *sums = guard->sums;
+        const long n4 = 4L * guard->n;  // two uint64 per pair, cleared as floats
+        sig_add(P, "gclr", (long long)(uintptr_t)sums, n4);
+        P.ops.push_back({FB_KERNEL_OTHER, [=](hipStream_t s, const uint8_t *) {
+            return launch_fill_zero(reinterpret_cast<float *>(sums), n4, s);
+        }});
+    }
+    std::vector<int> cur(pairs.size(), 0), rcur(pairs.size(), 0);
     for (int t = 0; t < kmax; ++t) {
         const int l = kmax - 1 - t;
         std::vector<size_t> active;
+        bool any_guard = false;
         for (size_t k = 0; k < pairs.size(); ++k)
-            if (pairs[k].L.levels > l) active.push_back(k);
+            if (pairs[k].L.levels > l) {
+                active.push_back(k);
+                any_guard |= pairs[k].guard_slot >= 0;
+            }
         if (active.empty()) continue;
+        auto gsum = [&](const PairSpec &ps) { return guard->sums + 2 * ps.guard_slot; };
         std::vector<PMJob> js;
         for (size_t k : active) {
             PairSpec &ps = pairs[k];
@@ -258,6 +308,14 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
                 j.mode = ps.seed_offsets ? kStartOffsets : kStartRandom;
                 j.aux_off = ps.seed_offsets;
                 dst = 0;
+                if (ps.guard_slot >= 0) {  // the plain run it races
+                    PMJob r = job_geom(ps, l);
+                    r.mode = kStartRandom;
+                    r.f_out = ps.rf[0];
+                    r.e_out = ps.re[0];
+                    rcur[k] = 0;
+                    js.push_back(r);
+                }
             } else {
                 j.mode = kStartUpsample;
                 j.f_in = ps.f[cur[k]];
@@ -268,10 +326,12 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
             j.f_out = ps.f[dst];
             j.e_out = ps.e[dst];
             cur[k] = dst;
+            rcur[k] = ps.guard_slot >= 0 && l < ps.L.levels - 1 ? dst : rcur[k];
             js.push_back(j);
         }
         add_pm_launch(P, kLaunchStart, js, cfg, p, seed, 0);
-        for (int it = 0; it < iters; ++it) {
+        const int its = any_guard ? it_all : iters;
+        for (int it = 0; it < its; ++it) {
             if (style && !fixed_target) {
                 js.clear();
                 for (size_t k : active) {
@@ -291,11 +351,52 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
             for (size_t k : active) {
                 PairSpec &ps = pairs[k];
                 PMJob j = job_geom(ps, l);
+                j.alpha16 = alpha16;
+                if (ps.guard_slot >= 0) {
+                    if (l == ps.L.levels - 1) {
+                        // coarsest level: the seeded run and the plain run, side by side
+                        if (it < plain_iters) {
+                            PMJob r = job_geom(ps, l);
+                            r.f_in = ps.rf[rcur[k]];
+                            r.e_in = ps.re[rcur[k]];
+                            r.f_out = ps.rf[rcur[k] ^ 1];
+                            r.e_out = ps.re[rcur[k] ^ 1];
+                            rcur[k] ^= 1;
+                            js_plain.push_back(r);
+                        }
+                        if (it >= iters) continue;
+                        j.f_in = ps.f[cur[k]];
+                        j.e_in = ps.e[cur[k]];
+                        j.f_out = ps.f[cur[k] ^ 1];
+                        j.e_out = ps.e[cur[k] ^ 1];
+                        cur[k] ^= 1;
+                    } else if (it < it_common) {
+                        j.f_in = ps.f[cur[k]];
+                        j.e_in = ps.e[cur[k]];
+                        j.f_out = ps.f[cur[k] ^ 1];
+                        j.e_out = ps.e[cur[k] ^ 1];
+                        cur[k] ^= 1;
+                        rcur[k] = cur[k];
+                    } else {
+                        // the longer of the two runs: rcur follows the plain run
+                        const bool plain_longer = plain_iters > iters;
+                        int &c = plain_longer ? rcur[k] : cur[k];
+                        j.f_in = ps.f[c];
+                        j.e_in = ps.e[c];
+                        j.f_out = ps.f[c ^ 1];
+                        j.e_out = ps.e[c ^ 1];
+                        j.guard = gsum(ps);
+                        j.guard_when = plain_longer ? 1 : 2;
+                        c ^= 1;
+                    }
+                    js_plain.push_back(j);
+                    continue;
+                }
+                if (it >= iters) continue;
                 j.f_in = fin[k];
                 j.e_in = ps.e[cur[k]];
                 j.f_out = ps.f[cur[k] ^ 1];
                 j.e_out = ps.e[cur[k] ^ 1];
-                j.alpha16 = alpha16;
                 if (track) {
                     j.trk_prev = ps.trk_prev >= 0 ? fin[ps.trk_prev] : nullptr;
                     j.trk_next = ps.trk_next >= 0 ? fin[ps.trk_next] : nullptr;
@@ -305,11 +406,14 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
                     j.pair_f = fin[ps.partner];
                     j.pair_sty = reinterpret_cast<const uint32_t *>(ps.partner_sty_pyr + ps.L.lv[l].px_off);
                 }
+                cur[k] ^= 1;
                 ((style || aligned) ? js_style : js_plain).push_back(j);
             }
-            for (size_t k : active) cur[k] ^= 1;
             const int tmode = track ? kIterTrack : kIterPlain;
-            if (l == 0 && it == iters - 1) {
+            // (a guarded plan is not tuned: rerunning one of its launches after
+            // the guarded ones could rewrite a field that a rejected or kept
+            // run ended in; it takes the shape tuned for its batch shape, if any)
+            if (l == 0 && it == its - 1 && !guarded) {
                 P.has_tune = true;
                 P.tune_jobs = js_style.empty() ? js_plain : js_style;
                 P.tune_iter = it;
@@ -318,6 +422,38 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
             add_pm_launch(P, kLaunchIter, js_style, cfg, p, seed, it, tmode | kIterStyle);
             add_pm_launch(P, kLaunchIter, js_plain, cfg, p, seed, it, tmode);
         }
+        if (!any_guard) continue;
+        // the race's outcome: the two sums at a pair's coarsest level; then a
+        // rejected pair's plain field replaces the seeded one wherever the two
+        // runs ended in different buffers
+        std::vector<PMJob> sums, sel;
+        for (size_t k : active) {
+            PairSpec &ps = pairs[k];
+            if (ps.guard_slot < 0) continue;
+            PMJob j = job_geom(ps, l);
+            j.guard = gsum(ps);
+            if (l == ps.L.levels - 1) {
+                PMJob a = job_geom(ps, l), b = job_geom(ps, l);
+                a.e_in = ps.e[cur[k]];
+                a.guard = gsum(ps);
+                b.e_in = ps.re[rcur[k]];
+                b.guard = gsum(ps) + 1;
+                sums.push_back(a);
+                sums.push_back(b);
+                j.f_alt = ps.rf[rcur[k]];
+                j.e_alt = ps.re[rcur[k]];
+            } else {
+                if (rcur[k] == cur[k]) continue;
+                j.f_alt = ps.f[rcur[k]];
+                j.e_alt = ps.e[rcur[k]];
+            }
+            j.f_out = ps.f[cur[k]];
+            j.e_out = ps.e[cur[k]];
+            rcur[k] = cur[k];
+            sel.push_back(j);
+        }
+        add_pm_launch(P, kLaunchEnergySum, sums, cfg, p, seed, 0);
+        add_pm_launch(P, kLaunchGuardSelect, sel, cfg, p, seed, 0);
     }
     std::vector<PMJob> ex;
     for (size_t k = 0; k < pairs.size(); ++k) {
@@ -371,12 +507,29 @@ bool fast_entry_valid(int k, int L) { return L == 0 || (k & ((1 << L) - 1)) == (
 
 }  // namespace
 
+// A slot of the ring of launch-descriptor tables.  A plan's table is copied
+// stream-ordered from the slot's pinned host image into its device buffer;
+// `done` is recorded after the plan's launches, so a slot is rewritten only
+// once the work that read it has finished (no device-wide synchronisation).
+struct TabSlot {
+    void *dev = nullptr;      // device copy
+    void *pinned = nullptr;   // pinned host staging buffer of the copy
+    size_t cap = 0;
+    std::vector<uint8_t> host;  // bytes currently in the slot
+    uint64_t gen = 0;           // 0: empty
+    hipEvent_t done = nullptr;  // recorded after the last launches that read the slot
+};
+constexpr int kTabRing = 8;
+
 struct fb_ctx {
     int device = 0;
-    Buf table;
-    std::vector<uint8_t> table_host;  // bytes currently in `table`
+    TabSlot tab[kTabRing];
+    int tab_last = 0;           // slot of the last plan
+    hipStream_t last_stream = nullptr;  // stream of the last plan
     uint64_t table_gen = 0;
-    Buf pyr, style, fe, tune_table, shat, tables;
+    Buf pyr, style, fe, tune_table, shat, tables, race, gsum;
+    std::vector<int> guard_map;  // last call: guard slot of each planned pair (-1: not guarded)
+    int guard_n = 0;
     std::map<std::string, int> tuned;
     int forced_cfg = -1;
     std::string graph_sig;
@@ -409,7 +562,48 @@ fb_status ensure(fb_ctx *ctx, Buf &b, size_t n) {
         return fail(FB_E_ALLOC, "device allocation of " + std::to_string(n) + " bytes failed");
     }
     b.n = n;
-    ctx->table_host.clear();  // pointers inside an uploaded table may now be stale
+    // pointers inside uploaded tables may now be stale
+    for (TabSlot &t : ctx->tab) t.gen = 0;
+    return FB_OK;
+}
+
+// The device table of plan P: a slot that already holds these bytes, else
+// the next slot of the ring, refilled with a stream-ordered copy once the
+// launches that last read it have finished.
+fb_status upload_table(fb_ctx *ctx, const Plan &P, hipStream_t s, int *slot) {
+    for (int i = 0; i < kTabRing; ++i) {
+        const int k = (ctx->tab_last + kTabRing - i) % kTabRing;
+        if (ctx->tab[k].gen && ctx->tab[k].host == P.table) {
+            // its copy may have been enqueued on another stream
+            FB_HIP(hipStreamWaitEvent(s, ctx->tab[k].done, 0));
+            *slot = k;
+            return FB_OK;
+        }
+    }
+    const int k = (ctx->tab_last + 1) % kTabRing;
+    TabSlot &t = ctx->tab[k];
+    t.gen = 0;
+    if (t.done) FB_HIP(hipEventSynchronize(t.done));
+    else FB_HIP(hipEventCreateWithFlags(&t.done, hipEventDisableTiming));
+    const size_t n = P.table.size();
+    if (t.cap < n) {
+        if (t.dev) FB_HIP(hipFree(t.dev));
+        if (t.pinned) FB_HIP(hipHostFree(t.pinned));
+        t.dev = t.pinned = nullptr;
+        t.cap = 0;
+        size_t cap = 4096;
+        while (cap < n) cap <<= 1;
+        if (hipMalloc(&t.dev, cap) != hipSuccess || hipHostMalloc(&t.pinned, cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(FB_E_ALLOC, "launch table of " + std::to_string(cap) + " bytes");
+        }
+        t.cap = cap;
+    }
+    std::memcpy(t.pinned, P.table.data(), n);
+    FB_HIP(hipMemcpyAsync(t.dev, t.pinned, n, hipMemcpyHostToDevice, s));
+    t.host = P.table;
+    t.gen = ++ctx->table_gen;
+    *slot = k;
     return FB_OK;
 }
 
@@ -466,20 +660,21 @@ fb_status autotune(fb_ctx *ctx, Plan &P, hipStream_t s, int p, uint64_t seed) {
 
 fb_status run_plan(fb_ctx *ctx, Plan &P, uint32_t flags, hipStream_t s, int p, uint64_t seed) {
     if (P.table.empty()) P.table.resize(256);
-    if (P.table != ctx->table_host || ctx->table.n < P.table.size()) {
-        fb_status st = ensure(ctx, ctx->table, P.table.size());
-        if (st) return st;
-        // the previous table may still be read by enqueued launches
-        FB_HIP(hipDeviceSynchronize());
-        FB_HIP(hipMemcpy(ctx->table.p, P.table.data(), P.table.size(), hipMemcpyHostToDevice));
-        ctx->table_host = P.table;
-        ++ctx->table_gen;
-    }
-    const uint8_t *tab = static_cast<const uint8_t *>(ctx->table.p);
+    // the context's workspace is shared by its calls: a call on another
+    // stream waits on the device for the previous call's launches
+    const TabSlot &prev = ctx->tab[ctx->tab_last];
+    if (prev.done && s != ctx->last_stream) FB_HIP(hipStreamWaitEvent(s, prev.done, 0));
+    ctx->last_stream = s;
+    int slot = 0;
+    fb_status st = upload_table(ctx, P, s, &slot);
+    if (st) return st;
+    ctx->tab_last = slot;
+    TabSlot &ts = ctx->tab[slot];
+    const uint8_t *tab = static_cast<const uint8_t *>(ts.dev);
     const bool tune = P.has_tune && ctx->forced_cfg < 0 && !(flags & FB_NO_AUTOTUNE) &&
                       !ctx->tuned.count(P.tune_key);
     if ((flags & FB_USE_GRAPH) && s != nullptr && !tune && !ctx->profiling) {
-        if (!ctx->graph_exec || ctx->graph_gen != ctx->table_gen || ctx->graph_sig != P.sig ||
+        if (!ctx->graph_exec || ctx->graph_gen != ts.gen || ctx->graph_sig != P.sig ||
             ctx->graph_stream != s) {
             if (ctx->graph_exec) FB_HIP(hipGraphExecDestroy(ctx->graph_exec));
             ctx->graph_exec = nullptr;
@@ -502,10 +697,11 @@ fb_status run_plan(fb_ctx *ctx, Plan &P, uint32_t flags, hipStream_t s, int p, u
                 return fail(FB_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
             }
             ctx->graph_sig = P.sig;
-            ctx->graph_gen = ctx->table_gen;
+            ctx->graph_gen = ts.gen;
             ctx->graph_stream = s;
         }
         FB_HIP(hipGraphLaunch(ctx->graph_exec, s));
+        FB_HIP(hipEventRecord(ts.done, s));
         return FB_OK;
     }
     for (Op &op : P.ops) {
@@ -527,6 +723,7 @@ fb_status run_plan(fb_ctx *ctx, Plan &P, uint32_t flags, hipStream_t s, int p, u
             FB_HIP(op.fn(s, tab));
         }
     }
+    FB_HIP(hipEventRecord(ts.done, s));
     if (tune) return autotune(ctx, P, s, p, seed);
     return FB_OK;
 }
@@ -556,8 +753,6 @@ constexpr int kUNetChunk = 512;  // pairs per network launch sequence (about 9 M
 // already carry seed offsets keep them.  Consecutive pairs with the same
 // coarsest size share network launches (up to kUNetChunk pairs).
 fb_status plan_learned_seeds(fb_ctx *ctx, Plan &P, std::vector<PairSpec> &pairs) {
-    if (!unet_loaded(ctx->unet))
-        return fail(FB_E_INVALID, "FB_LEARNED_SEED needs network parameters (fb_unet_load)");
     struct Group { size_t first, count; int H8, W8; };
     std::vector<Group> groups;
     size_t seed_elems = 0;
@@ -576,6 +771,8 @@ fb_status plan_learned_seeds(fb_ctx *ctx, Plan &P, std::vector<PairSpec> &pairs)
         seed_elems += (size_t)g.h * g.w * 2;
     }
     if (groups.empty()) return FB_OK;
+    if (!unet_loaded(ctx->unet))
+        return fail(FB_E_INVALID, "FB_LEARNED_SEED needs network parameters (fb_unet_load)");
     // the largest group shape bounds the workspace (bound without allocating later)
     size_t best = 0;
     for (const Group &gr : groups) {
@@ -623,6 +820,50 @@ fb_status plan_learned_seeds(fb_ctx *ctx, Plan &P, std::vector<PairSpec> &pairs)
     return FB_OK;
 }
 
+// The guard of the seeded pairs of a plain (Eq. 1) pass with FB_LEARNED_SEED
+// and without FB_NO_GUARD: every pair that starts from offsets gets a slot,
+// the plain run's buffers at its coarsest level and two summed energies.
+constexpr int kDefaultPlainIters = 6;
+
+fb_status prepare_guard(fb_ctx *ctx, std::vector<PairSpec> &pairs, const fb_params *prm, bool plain_pass,
+                        GuardPlan *g) {
+    g->n = 0;
+    ctx->guard_map.assign(pairs.size(), -1);
+    ctx->guard_n = 0;
+    if (!plain_pass || !(prm->flags & FB_LEARNED_SEED) || (prm->flags & FB_NO_GUARD)) return FB_OK;
+    size_t race_px = 0;
+    int n = 0;
+    for (const PairSpec &ps : pairs)
+        if (ps.seed_offsets) {
+            const LevelGeom &c = ps.L.lv[ps.L.levels - 1];
+            race_px += (size_t)c.h * c.w;
+            ++n;
+        }
+    if (!n) return FB_OK;
+    fb_status st;
+    if ((st = ensure(ctx, ctx->race, race_px * 16)) || (st = ensure(ctx, ctx->gsum, (size_t)n * 16))) return st;
+    uint32_t *base = static_cast<uint32_t *>(ctx->race.p);
+    size_t off = 0;
+    int slot = 0;
+    for (size_t k = 0; k < pairs.size(); ++k) {
+        PairSpec &ps = pairs[k];
+        if (!ps.seed_offsets) continue;
+        const LevelGeom &c = ps.L.lv[ps.L.levels - 1];
+        ps.guard_slot = slot;
+        ps.rf[0] = base + off;
+        ps.rf[1] = base + race_px + off;
+        ps.re[0] = base + 2 * race_px + off;
+        ps.re[1] = base + 3 * race_px + off;
+        off += (size_t)c.h * c.w;
+        ctx->guard_map[k] = slot++;
+    }
+    g->plain_iters = prm->plain_iters ? prm->plain_iters : kDefaultPlainIters;
+    g->sums = static_cast<uint64_t *>(ctx->gsum.p);
+    g->n = n;
+    ctx->guard_n = n;
+    return FB_OK;
+}
+
 fb_status check_unet_shape(int B, int h, int w) {
     if (B < 1 || h < 8 || w < 8 || h % 8 || w % 8)
         return fail(FB_E_SHAPE, "network input needs B >= 1 and h, w positive multiples of 8");
@@ -646,7 +887,8 @@ fb_status check_params(const fb_params *prm, bool need_levels) {
     if (need_levels && (prm->levels < 1 || prm->levels > kMaxLevels))
         return fail(FB_E_INVALID, "levels must be in [1, 16]");
     if (prm->iters < 0 || prm->iters > 0xFFFE) return fail(FB_E_INVALID, "iters must be in [0, 65534]");
-    if (prm->reserved != 0) return fail(FB_E_INVALID, "params->reserved must be 0");
+    if (prm->plain_iters < 0 || prm->plain_iters > 0xFFFE)
+        return fail(FB_E_INVALID, "plain_iters must be in [0, 65534]");
     if (prm->flags & (FB_STYLE_LOSS | FB_ACCURATE_BLEND | FB_ALIGN)) {
         if (prm->iters < 1) return fail(FB_E_INVALID, "FB_STYLE_LOSS, FB_ACCURATE_BLEND and FB_ALIGN need iters >= 1");
         const int amax = alpha16_max(prm->patch_radius);
@@ -755,8 +997,10 @@ fb_status blend_fast(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, 
     }
     if (params->flags & FB_LEARNED_SEED)
         if ((st = plan_learned_seeds(ctx, P, pairs))) return st;
+    GuardPlan gp;
+    if ((st = prepare_guard(ctx, pairs, params, true, &gp))) return st;
     const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
-    if (!pairs.empty()) plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg);
+    if (!pairs.empty()) plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg, false, 0, false, false, false, &gp);
 
     auto style_px = [&](int f) { return reinterpret_cast<const uint32_t *>(sty + (size_t)f * sbytes); };
     auto field = [&](int src, int tgt) {
@@ -870,8 +1114,10 @@ fb_status blend_accurate(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styl
         if ((st = plan_learned_seeds(ctx, P, first))) return st;
         for (size_t k = 0; k < first.size(); ++k) second[k].seed_offsets = first[k].seed_offsets;
     }
+    GuardPlan gp;  // the Eq. 1 pass is guarded; the Eq. 8 pass starts from the same seeds
+    if ((st = prepare_guard(ctx, first, params, true, &gp))) return st;
     const TileCfg cfg = choose_cfg(ctx, tune_key_of(first, p), params->flags);
-    if (!first.empty()) plan_patchmatch(P, first, params->iters, p, params->seed, cfg);
+    if (!first.empty()) plan_patchmatch(P, first, params->iters, p, params->seed, cfg, false, 0, false, false, false, &gp);
     // T^- of every frame, then its pyramid
     auto style_px = [&](int f) { return reinterpret_cast<const uint32_t *>(sty + (size_t)f * L.bytes); };
     std::vector<RemapTerm> terms;
@@ -936,8 +1182,14 @@ void fb_destroy(fb_ctx *ctx) {
     unet_destroy(ctx->unet);
     for (Buf *b : {&ctx->seeds, &ctx->unet_tab})
         if (b->p) (void)hipFree(b->p);
-    for (Buf *b : {&ctx->table, &ctx->pyr, &ctx->style, &ctx->fe, &ctx->tune_table})
+    for (Buf *b : {&ctx->pyr, &ctx->style, &ctx->fe, &ctx->tune_table, &ctx->shat, &ctx->tables, &ctx->race,
+                   &ctx->gsum})
         if (b->p) (void)hipFree(b->p);
+    for (TabSlot &t : ctx->tab) {
+        if (t.dev) (void)hipFree(t.dev);
+        if (t.pinned) (void)hipHostFree(t.pinned);
+        if (t.done) (void)hipEventDestroy(t.done);
+    }
     delete ctx;
 }
 
@@ -1181,8 +1433,10 @@ fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *sty
         }
     if (params->flags & FB_LEARNED_SEED)
         if ((st = plan_learned_seeds(ctx, P, pairs))) return st;
+    GuardPlan gp;
+    if ((st = prepare_guard(ctx, pairs, params, !style, &gp))) return st;
     const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
-    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg, style, params->alpha16);
+    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg, style, params->alpha16, false, false, false, &gp);
 
     std::vector<RemapTerm> terms;
     std::vector<RemapFrame> frames;
@@ -1294,8 +1548,10 @@ fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, i
         }
     if (params->flags & FB_LEARNED_SEED)
         if ((st = plan_learned_seeds(ctx, P, pairs))) return st;
+    GuardPlan gp;
+    if ((st = prepare_guard(ctx, pairs, params, !track && !align, &gp))) return st;
     const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
-    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg, false, params->alpha16, false, track, align);
+    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg, false, params->alpha16, false, track, align, &gp);
 
     std::vector<RemapTerm> terms;
     std::vector<RemapFrame> frames;
@@ -1375,9 +1631,31 @@ fb_status fb_patchmatch_batch(fb_ctx *ctx, const fb_pair_desc *pairs_in, int32_t
     Plan P;
     if (params->flags & FB_LEARNED_SEED)
         if ((st = plan_learned_seeds(ctx, P, pairs))) return st;
+    GuardPlan gp;
+    if ((st = prepare_guard(ctx, pairs, params, !style, &gp))) return st;
     const TileCfg cfg = choose_cfg(ctx, tune_key_of(pairs, p), params->flags);
-    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg, style, params->alpha16);
+    plan_patchmatch(P, pairs, params->iters, p, params->seed, cfg, style, params->alpha16, false, false, false, &gp);
     return run_plan(ctx, P, params->flags, static_cast<hipStream_t>(stream), p, params->seed);
+}
+
+fb_status fb_guard_read(fb_ctx *ctx, uint64_t *sums, int32_t max_pairs, int32_t *n_pairs, void *stream) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!sums || !n_pairs || max_pairs < 0) return fail(FB_E_INVALID, "null pointer or negative size");
+    const int n = (int)std::min<size_t>(ctx->guard_map.size(), (size_t)max_pairs);
+    std::vector<uint64_t> dev(2 * (size_t)ctx->guard_n);
+    if (ctx->guard_n) {
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        FB_HIP(hipMemcpyAsync(dev.data(), ctx->gsum.p, dev.size() * 8, hipMemcpyDeviceToHost, s));
+        FB_HIP(hipStreamSynchronize(s));
+    }
+    for (int k = 0; k < n; ++k) {
+        const int g = ctx->guard_map[k];
+        sums[2 * k] = g >= 0 ? dev[2 * g] : 0;
+        sums[2 * k + 1] = g >= 0 ? dev[2 * g + 1] : 0;
+    }
+    *n_pairs = (int32_t)ctx->guard_map.size();
+    return FB_OK;
 }
 
 int64_t fb_unet_param_count(void) { return unet_param_count(); }

@@ -28,6 +28,7 @@ FB_FAST_BLEND = 0x10
 FB_ACCURATE_BLEND = 0x20
 FB_TRACKING = 0x40
 FB_ALIGN = 0x80
+FB_NO_GUARD = 0x100
 STATUS = {0: "FB_OK", -1: "FB_E_INVALID", -2: "FB_E_SHAPE", -3: "FB_E_UNSUPPORTED",
           -4: "FB_E_ALLOC", -5: "FB_E_HIP"}
 
@@ -41,7 +42,7 @@ class FastBlendError(RuntimeError):
 class fb_params(ctypes.Structure):
     _fields_ = [("patch_radius", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64),
-                ("alpha16", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("alpha16", ctypes.c_int32), ("plain_iters", ctypes.c_int32)]
 
 
 class fb_pair_desc(ctypes.Structure):
@@ -65,7 +66,7 @@ _EXPORTS = ["fb_create", "fb_destroy", "fb_last_error", "fb_alpha16_max", "fb_nu
             "fb_pyramid_bytes", "fb_build_pyramid", "fb_nnf_init", "fb_patchmatch_level", "fb_remap",
             "fb_blend_window", "fb_interpolate", "fb_patchmatch_batch", "fb_profile_enable",
             "fb_profile_read", "fb_unet_param_count", "fb_unet_forward_flops", "fb_unet_load", "fb_unet_save",
-            "fb_unet_forward", "fb_unet_gradients", "fb_unet_train_step", "fb_unet_pair_input"]
+            "fb_unet_forward", "fb_unet_gradients", "fb_unet_train_step", "fb_unet_pair_input", "fb_guard_read"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -103,6 +104,7 @@ def load_library(path: str = LIB_PATH):
         "fb_unet_gradients": (i32, [vp, vp, vp, vp, i32, i32, i32, vp, vp, vp]),
         "fb_unet_train_step": (i32, [vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp]),
         "fb_unet_pair_input": (i32, [vp, vp, vp, i32, i32, i32, i32, vp, vp]),
+        "fb_guard_read": (i32, [vp, ctypes.POINTER(ctypes.c_uint64), i32, ctypes.POINTER(i32), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -144,9 +146,11 @@ def _check_pyr(pyr: torch.Tensor, name: str, h: int, w: int, levels: int, patch_
 
 
 def make_params(patch_radius: int = 2, levels: int = 3, iters: int = 6, seed: int = 0,
-                flags: int = 0, alpha16: int = 16) -> fb_params:
-    """alpha16: the guide weight of the Eq. 3 loss (FB_STYLE_LOSS), alpha = alpha16 / 16."""
-    return fb_params(patch_radius, levels, iters, flags, seed & 0xFFFFFFFFFFFFFFFF, alpha16, 0)
+                flags: int = 0, alpha16: int = 16, plain_iters: int = 0) -> fb_params:
+    """alpha16: the guide weight of the Eq. 3 loss (FB_STYLE_LOSS), alpha = alpha16 / 16.
+    plain_iters: with FB_LEARNED_SEED, the iterations per level of the plain run
+    a seed is raced against and falls back to (0: 6)."""
+    return fb_params(patch_radius, levels, iters, flags, seed & 0xFFFFFFFFFFFFFFFF, alpha16, plain_iters)
 
 
 def energy_u32(energy: torch.Tensor) -> torch.Tensor:
@@ -252,6 +256,20 @@ class Context:
         _check(load_library().fb_profile_read(self.handle, ctypes.byref(pr), 1 if reset else 0),
                "fb_profile_read")
         return {k: (int(pr.launches[i]), float(pr.milliseconds[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+    def fb_guard_read(self, stream_device: int = 0):
+        """(seeded, plain) summed coarsest-level energies of every pair of the
+        last blend / interpolation / batch call, as an int64 tensor [n][2]
+        (zeros for unguarded pairs); pair k's seed was rejected iff
+        [k, 0] > [k, 1].  Waits for the current stream."""
+        L = load_library()
+        n = ctypes.c_int32(0)
+        dummy = (ctypes.c_uint64 * 2)()
+        stream = ctypes.c_void_p(torch.cuda.current_stream(stream_device).cuda_stream)
+        _check(L.fb_guard_read(self.handle, dummy, 0, ctypes.byref(n), stream), "fb_guard_read")
+        buf = (ctypes.c_uint64 * max(2 * n.value, 2))()
+        _check(L.fb_guard_read(self.handle, buf, n.value, ctypes.byref(n), stream), "fb_guard_read")
+        return torch.tensor([int(x) for x in buf[:2 * n.value]], dtype=torch.int64).reshape(n.value, 2)
 
     # ---- tuning ---------------------------------------------------------
     def fb_set_tile_config(self, index: int):

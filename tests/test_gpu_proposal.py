@@ -57,24 +57,28 @@ def test_save_load_round_trip(ctx):
     assert torch.equal(back, flat)
 
 
-def test_gradients_match_oracle(ctx):
-    """Per-layer gradients within 2e-2 (rel-L2) of the bf16-emulating oracle.
-
-    With identical bf16 rounding points, GPU and oracle differ only through
-    accumulation order (fp32 vs fp64), which flips a bf16 rounding now and
-    then.  At 16x16 the 2x2 bottleneck leaves so few terms that the oracle
-    itself moves by ~4% between fp32 and fp64 accumulation; at 4 x 64x64
-    that noise floor is below 0.8% for every layer, so 2e-2 has margin."""
-    flat = net.init_params(13)
+@pytest.mark.parametrize("B,h,w,batch_seed,param_seed", [(2, 16, 16, 5, 13), (2, 16, 16, 7, 21), (4, 64, 64, 5, 13)])
+def test_gradients_match_oracle(ctx, B, h, w, batch_seed, param_seed):
+    """Per-layer gradients against the bf16-emulating oracle (fp64 sums), with
+    a tolerance derived from the oracle itself: with the same bf16 rounding
+    points, GPU and oracle differ only in how their sums are accumulated, and
+    the oracle moves by `spread` (rel-L2, per layer) when its own sums are
+    accumulated in fp32 instead of fp64 (a bf16 rounding that flips changes a
+    ReLU mask or a stored activation downstream).  The GPU must stay within
+    2 spread + 1e-3 of the fp64 oracle.  Cases include the 16x16 input, whose
+    bottleneck is 2x2."""
+    flat = net.init_params(param_seed)
     ctx.fb_unet_load(flat.cuda())
-    x, t, m = _batch(4, 64, 64, 5)
+    x, t, m = _batch(B, h, w, batch_seed)
     grads, loss = ctx.fb_unet_gradients(x.cuda(), t.cuda(), m.cuda())
     ref_loss, ref = net.loss_and_grads(flat, x, t, m, emulate_bf16=True)
+    _, ref32 = net.loss_and_grads(flat, x, t, m, emulate_bf16=True, acc=torch.float32)
     assert abs(float(loss.cpu()) - float(ref_loss)) <= 1e-3 * float(ref_loss)
     g = grads.cpu()
     for i, (a, b) in enumerate(net.layer_slices()):
+        spread = rel(ref32[a:b], ref[a:b])
         r = rel(g[a:b], ref[a:b])
-        assert r < 2e-2, (i, r)
+        assert r <= 2 * spread + 1e-3, (i, r, spread)
     # parameters are unchanged by a gradient evaluation
     assert torch.equal(ctx.fb_unet_save().cpu(), flat)
 
@@ -98,7 +102,7 @@ def test_learned_seed_patchmatch(ctx):
     bit-exact GPU/oracle NNFs through the offset-seed path; (b) the GPU
     network's rounded offsets agree with the oracle network's almost
     everywhere; (c) FB_LEARNED_SEED equals seeding with the GPU network's
-    offsets explicitly."""
+    offsets explicitly, without and with the guard of seeded runs."""
     flat = net.init_params(15) * 0.3
     ctx.fb_unet_load(flat.cuda())
     N, h, w, K, iters, seed = 3, 64, 96, 3, 2, 77
@@ -129,12 +133,14 @@ def test_learned_seed_patchmatch(ctx):
         F, E = oracle.patchmatch(guides[j], guides[i], 2, K, iters, seed, j * N + i, seed_offsets=ref_seed[k])
         assert np.array_equal(outs[k][0].cpu().numpy(), F)
         assert np.array_equal(outs[k][1].cpu().numpy().astype(np.uint32), E)
-    # (c) the learned-seed flag equals explicit seeding with the GPU network's offsets
-    lprm = fbm.make_params(2, K, iters, seed, fbm.FB_LEARNED_SEED)
-    learned = ctx.fb_patchmatch_batch(descs(None), lprm)
-    explicit = ctx.fb_patchmatch_batch(descs(gpu_seed), prm)
-    for (a, ea), (b, eb) in zip(learned, explicit):
-        assert torch.equal(a, b) and torch.equal(ea, eb)
+    # (c) the learned-seed flag equals explicit seeding with the GPU network's
+    # offsets: unguarded (FB_NO_GUARD) against the plain call, and guarded
+    # against the same explicit seeds under the flag (explicit seeds are raced too)
+    for flags, ref_flags in ((fbm.FB_LEARNED_SEED | fbm.FB_NO_GUARD, 0), (fbm.FB_LEARNED_SEED, fbm.FB_LEARNED_SEED)):
+        learned = ctx.fb_patchmatch_batch(descs(None), fbm.make_params(2, K, iters, seed, flags))
+        explicit = ctx.fb_patchmatch_batch(descs(gpu_seed), fbm.make_params(2, K, iters, seed, ref_flags))
+        for (a, ea), (b, eb) in zip(learned, explicit):
+            assert torch.equal(a, b) and torch.equal(ea, eb)
 
 
 def test_trained_proposal_gain(ctx):
