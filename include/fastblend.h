@@ -196,6 +196,23 @@ fb_status fb_patchmatch_level(fb_ctx *ctx, const void *src_pyr, const void *tgt_
                               const int32_t *nnf_coarse, int32_t *nnf, uint32_t *energy,
                               void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * call as fb_patchmatch_level, with the same arguments and bit-identical
+ * results, that allocates nothing.  Its working memory (the level's four
+ * ping-pong field and energy planes and the launch descriptors, 16 MiB +
+ * 1 KiB) is one fixed device array of the library per GPU, set up by
+ * fb_create and held until the process ends.  The level must have at most
+ * 1,048,576 pixels (h_l * w_l); larger levels return FB_E_UNSUPPORTED.  Every
+ * call on one GPU, from any context or stream, uses that GPU's array and
+ * leaves its contents behind: calls that overlap on one GPU race, so the
+ * caller serialises them.  It always uses the default tile shape (or the
+ * one fb_set_tile_config forces). */
+fb_status fb_patchmatch_level_noalloc(fb_ctx *ctx, const void *src_pyr, const void *tgt_pyr, int32_t h,
+                                      int32_t w, int32_t level, const fb_params *params, uint32_t pair_id,
+                                      const int32_t *nnf_coarse, int32_t *nnf, uint32_t *energy,
+                                      void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* (3) Memory-efficient remapping (Algorithm 2): out(v) = average over      */
 /* d in [-p,p]^2 with v+d inside the image of style(F(v+d) - d) / 255,     */

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1152,6 +1153,50 @@ fb_status blend_accurate(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styl
     return run_plan(ctx, P, params->flags, stream, p, params->seed);
 }
 
+// ---- working memory of fb_patchmatch_level_noalloc ----
+// A fixed array per GPU, so that entry point never allocates: the four
+// ping-pong planes (field and energy, 4 bytes per pixel each) of a level of
+// up to kNoAllocPixels pixels, then the launch descriptors.  Host code uses
+// the device address hipGetSymbolAddress gives for the current device (the
+// name itself is a host-side stand-in).
+constexpr size_t kNoAllocPixels = (size_t)1 << 20;
+constexpr int kNoAllocJobs = 4;
+constexpr size_t kNoAllocFieldBytes = 16 * kNoAllocPixels;
+constexpr size_t kNoAllocBytes = kNoAllocFieldBytes + ((kNoAllocJobs * sizeof(PMJob) + 255) & ~(size_t)255);
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices];  // device address of `scratch` on each device (set up by fb_create)
+
+// once per device, with that device current
+fb_status scratch_setup(int device) {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0 || device >= kMaxDevices) return fail(FB_E_UNSUPPORTED, "device index above 63");
+    if (g_scratch_ptr[device]) return FB_OK;
+    void *ptr = nullptr;
+    FB_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[device] = ptr;
+    return FB_OK;
+}
+
+struct NoAllocJobs {
+    PMJob j[kNoAllocJobs];
+};
+
+// the launch descriptors, written by a kernel from its argument (no copy from
+// host memory, no allocation)
+__global__ void __launch_bounds__(64) k_store_jobs(NoAllocJobs jobs, PMJob *dst, int n) {
+    const uint64_t *src = reinterpret_cast<const uint64_t *>(&jobs);
+    uint64_t *d = reinterpret_cast<uint64_t *>(dst);
+    const int words = n * (int)(sizeof(PMJob) / 8);
+    for (int i = (int)threadIdx.x; i < words; i += 64) d[i] = src[i];
+}
+
+}  // namespace
+
 // ============================== C ABI ==================================
 
 extern "C" {
@@ -1163,6 +1208,8 @@ fb_status fb_create(int32_t device, fb_ctx **out) {
     FB_HIP(hipGetDeviceCount(&n));
     if (device < 0 || device >= n) return fail(FB_E_INVALID, "no such device");
     FB_HIP(hipSetDevice(device));
+    fb_status st = scratch_setup(device);
+    if (st) return st;
     fb_ctx *c = new fb_ctx();
     c->device = device;
     *out = c;
@@ -1343,6 +1390,79 @@ fb_status fb_patchmatch_level(fb_ctx *ctx, const void *src_pyr, const void *tgt_
     j.energy_abi = energy;
     add_pm_launch(P, kLaunchExport, {j}, cfg, p, params->seed, 0);
     return run_plan(ctx, P, params->flags, static_cast<hipStream_t>(stream), p, params->seed);
+}
+
+fb_status fb_patchmatch_level_noalloc(fb_ctx *ctx, const void *src_pyr, const void *tgt_pyr, int32_t h,
+                                      int32_t w, int32_t level, const fb_params *params, uint32_t pair_id,
+                                      const int32_t *nnf_coarse, int32_t *nnf, uint32_t *energy,
+                                      void *stream) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!src_pyr || !tgt_pyr || !nnf || !energy) return fail(FB_E_INVALID, "null pointer");
+    if ((st = check_size(h, w)) || (st = check_params(params, false))) return st;
+    if (params->flags & FB_STYLE_LOSS)
+        return fail(FB_E_UNSUPPORTED, "FB_STYLE_LOSS is taken by fb_blend_window and fb_patchmatch_batch only");
+    if (level < 0 || level >= kMaxLevels - 1) return fail(FB_E_INVALID, "level must be in [0, 14]");
+    uint8_t *base = static_cast<uint8_t *>(g_scratch_ptr[ctx->device]);
+    if (!base) return fail(FB_E_INVALID, "the context's device has no working array");
+    const int p = params->patch_radius;
+    const PyrLayout L = pyr_layout(h, w, level + 2, p);  // level + 1 for the coarse size only
+    const size_t npx = (size_t)L.lv[level].h * L.lv[level].w;
+    if (npx > kNoAllocPixels)
+        return fail(FB_E_UNSUPPORTED, "fb_patchmatch_level_noalloc takes levels of at most 1048576 pixels");
+    uint32_t *f[2] = {reinterpret_cast<uint32_t *>(base), reinterpret_cast<uint32_t *>(base) + npx};
+    uint32_t *e[2] = {reinterpret_cast<uint32_t *>(base) + 2 * npx, reinterpret_cast<uint32_t *>(base) + 3 * npx};
+    PMJob *djobs = reinterpret_cast<PMJob *>(base + kNoAllocFieldBytes);
+    PairSpec ps{};
+    ps.src_pyr = static_cast<const uint8_t *>(src_pyr);
+    ps.tgt_pyr = static_cast<const uint8_t *>(tgt_pyr);
+    ps.L = L;
+    ps.pair_id = pair_id;
+    const TileCfg cfg = tile_cfg(ctx->forced_cfg >= 0 ? ctx->forced_cfg : 0);
+    const LevelGeom &g = L.lv[level];
+    const int tiles_x = (g.w + cfg.tw - 1) / cfg.tw;
+    const int total = tiles_x * ((g.h + cfg.th - 1) / cfg.th);
+    NoAllocJobs J;
+    std::memset(&J, 0, sizeof J);
+    // 0: start of the level; 1, 2: even and odd iterations; 3: export
+    for (int k = 0; k < kNoAllocJobs; ++k) {
+        J.j[k] = job_geom(ps, level);
+        J.j[k].tiles_x = tiles_x;
+        J.j[k].tile_base = 0;
+    }
+    if (nnf_coarse) {
+        J.j[0].mode = kStartUpsampleAbi;
+        J.j[0].aux_off = nnf_coarse;
+        J.j[0].hc = L.lv[level + 1].h;
+        J.j[0].wc = L.lv[level + 1].w;
+    } else {
+        J.j[0].mode = kStartCopyAbi;
+        J.j[0].aux_off = nnf;
+        J.j[0].e_abi = energy;
+    }
+    J.j[0].f_out = f[0];
+    J.j[0].e_out = e[0];
+    for (int k = 0; k < 2; ++k) {
+        J.j[1 + k].f_in = f[k];
+        J.j[1 + k].e_in = e[k];
+        J.j[1 + k].f_out = f[k ^ 1];
+        J.j[1 + k].e_out = e[k ^ 1];
+    }
+    const int fin = params->iters & 1;
+    J.j[3].f_in = f[fin];
+    J.j[3].e_in = e[fin];
+    J.j[3].nnf_abi = nnf;
+    J.j[3].energy_abi = energy;
+    const int tab_bytes = (J.j[1].tab_n * 12 + 15) & ~15;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_store_jobs, dim3(1), dim3(64), 0, s, J, djobs, kNoAllocJobs);
+    FB_HIP(hipGetLastError());
+    FB_HIP(launch_pm_start(djobs, 1, total, total, cfg, p, params->seed, s));
+    for (int it = 0; it < params->iters; ++it)
+        FB_HIP(launch_pm_iter(djobs + 1 + (it & 1), 1, total, total, cfg, p, it, params->seed, kIterPlain,
+                              tab_bytes, s));
+    FB_HIP(launch_pm_export(djobs + 3, 1, total, total, cfg, s));
+    return FB_OK;
 }
 
 fb_status fb_remap(fb_ctx *ctx, const uint8_t *style, const int32_t *nnf, int32_t h, int32_t w,

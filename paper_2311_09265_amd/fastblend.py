@@ -66,7 +66,8 @@ _EXPORTS = ["fb_create", "fb_destroy", "fb_last_error", "fb_alpha16_max", "fb_nu
             "fb_pyramid_bytes", "fb_build_pyramid", "fb_nnf_init", "fb_patchmatch_level", "fb_remap",
             "fb_blend_window", "fb_interpolate", "fb_patchmatch_batch", "fb_profile_enable",
             "fb_profile_read", "fb_unet_param_count", "fb_unet_forward_flops", "fb_unet_load", "fb_unet_save",
-            "fb_unet_forward", "fb_unet_gradients", "fb_unet_train_step", "fb_unet_pair_input", "fb_guard_read"]
+            "fb_unet_forward", "fb_unet_gradients", "fb_unet_train_step", "fb_unet_pair_input", "fb_guard_read",
+            "fb_patchmatch_level_noalloc"]
 
 
 def load_library(path: str = LIB_PATH):
@@ -90,6 +91,7 @@ def load_library(path: str = LIB_PATH):
         "fb_build_pyramid": (i32, [vp, vp, i32, i32, i32, i32, vp, vp]),
         "fb_nnf_init": (i32, [vp, vp, vp, i32, i32, i32, P, u32, vp, vp, vp, vp]),
         "fb_patchmatch_level": (i32, [vp, vp, vp, i32, i32, i32, P, u32, vp, vp, vp, vp]),
+        "fb_patchmatch_level_noalloc": (i32, [vp, vp, vp, i32, i32, i32, P, u32, vp, vp, vp, vp]),
         "fb_remap": (i32, [vp, vp, vp, i32, i32, i32, vp, vp]),
         "fb_blend_window": (i32, [vp, vp, vp, i32, i32, i32, i32, P, vp, vp]),
         "fb_interpolate": (i32, [vp, vp, i32, i32, i32, vp, vp, i32, P, vp, vp]),
@@ -323,6 +325,21 @@ class Context:
             _dev(nnf_coarse, "nnf_coarse", torch.int32, (hc, wc, 2)),
             _dev(nnf, "nnf", torch.int32, (hl, wl, 2)), _dev(energy, "energy", torch.int32, (hl, wl)),
             _stream(src_pyr)), "fb_patchmatch_level")
+        return nnf, energy
+
+    def fb_patchmatch_level_noalloc(self, src_pyr, tgt_pyr, h: int, w: int, level: int, params: fb_params,
+                                    pair_id: int, nnf: torch.Tensor, energy: torch.Tensor,
+                                    nnf_coarse: Optional[torch.Tensor] = None):
+        """fb_patchmatch_level without any allocation: the caller passes nnf and
+        energy (int32 [h_l][w_l][2] and [h_l][w_l]), updated in place."""
+        hl, wl = level_size(h, w, level)
+        hc, wc = level_size(h, w, level + 1)
+        _check(load_library().fb_patchmatch_level_noalloc(
+            self.handle, _dev(src_pyr, "src_pyr", torch.uint8), _dev(tgt_pyr, "tgt_pyr", torch.uint8),
+            h, w, level, ctypes.byref(params), pair_id,
+            _dev(nnf_coarse, "nnf_coarse", torch.int32, (hc, wc, 2)),
+            _dev(nnf, "nnf", torch.int32, (hl, wl, 2)), _dev(energy, "energy", torch.int32, (hl, wl)),
+            _stream(src_pyr)), "fb_patchmatch_level_noalloc")
         return nnf, energy
 
     # ---- remap / blend / interpolate --------------------------------------
