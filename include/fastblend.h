@@ -321,6 +321,16 @@ int64_t fb_unet_param_count(void);
 double fb_unet_forward_flops(int32_t B, int32_t h, int32_t w);
 fb_status fb_unet_load(fb_ctx *ctx, const float *params, void *stream);
 fb_status fb_unet_save(fb_ctx *ctx, float *params, void *stream);
+/* Training state, for checkpoint and resume: the parameters and Adam's first
+ * and second moments (each fb_unet_param_count() floats, the flat layout of
+ * fb_unet_load; device pointers) and Adam's step count (*step, host).
+ * fb_unet_save_state writes them (the step at once, the tensors stream-
+ * ordered); fb_unet_load_state sets them, so that later training steps equal
+ * those of the run that saved them. */
+fb_status fb_unet_save_state(fb_ctx *ctx, float *params, float *adam_m, float *adam_v, int64_t *step,
+                             void *stream);
+fb_status fb_unet_load_state(fb_ctx *ctx, const float *params, const float *adam_m, const float *adam_v,
+                             int64_t step, void *stream);
 fb_status fb_unet_forward(fb_ctx *ctx, const float *pair6, int32_t B, int32_t h, int32_t w,
                           float *offsets, void *stream);
 fb_status fb_unet_gradients(fb_ctx *ctx, const float *pair6, const float *target, const float *mask,

@@ -245,6 +245,8 @@ int64_t unet_param_count();
 bool unet_loaded(const UNet *u);
 hipError_t unet_load(UNet *u, const float *flat, hipStream_t s);
 hipError_t unet_save(UNet *u, float *flat, hipStream_t s);
+hipError_t unet_save_state(UNet *u, float *flat, float *m, float *v, int64_t *step, hipStream_t s);
+hipError_t unet_load_state(UNet *u, const float *flat, const float *m, const float *v, int64_t step, hipStream_t s);
 hipError_t unet_grads_flat(UNet *u, float *flat, hipStream_t s);
 // reserve: allocate (if needed) and bind the workspace for this shape;
 // shape: bind a shape that fits the reserved workspace, never allocating

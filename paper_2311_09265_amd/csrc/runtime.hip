@@ -1804,6 +1804,26 @@ fb_status fb_unet_save(fb_ctx *ctx, float *params, void *stream) {
     return FB_OK;
 }
 
+fb_status fb_unet_save_state(fb_ctx *ctx, float *params, float *adam_m, float *adam_v, int64_t *step,
+                             void *stream) {
+    fb_status st = unet_ctx(ctx);
+    if (st) return st;
+    if (!params || !adam_m || !adam_v || !step) return fail(FB_E_INVALID, "null pointer");
+    if (!unet_loaded(ctx->unet)) return fail(FB_E_INVALID, "no network parameters loaded");
+    FB_HIP(unet_save_state(ctx->unet, params, adam_m, adam_v, step, static_cast<hipStream_t>(stream)));
+    return FB_OK;
+}
+
+fb_status fb_unet_load_state(fb_ctx *ctx, const float *params, const float *adam_m, const float *adam_v,
+                             int64_t step, void *stream) {
+    fb_status st = unet_ctx(ctx);
+    if (st) return st;
+    if (!params || !adam_m || !adam_v) return fail(FB_E_INVALID, "null pointer");
+    if (step < 0 || step > 0x7FFFFFFF) return fail(FB_E_INVALID, "step must be in [0, 2^31 - 1]");
+    FB_HIP(unet_load_state(ctx->unet, params, adam_m, adam_v, step, static_cast<hipStream_t>(stream)));
+    return FB_OK;
+}
+
 fb_status fb_unet_forward(fb_ctx *ctx, const float *pair6, int32_t B, int32_t h, int32_t w, float *offsets,
                           void *stream) {
     fb_status st = unet_ctx(ctx);

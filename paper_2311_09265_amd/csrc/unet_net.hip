@@ -151,6 +151,33 @@ static hipError_t to_flat(UNet *u, const float *padded_base, float *flat, hipStr
 }
 
 hipError_t unet_save(UNet *u, float *flat, hipStream_t s) { return to_flat(u, u->w32, flat, s); }
+
+// training state: parameters, Adam moments (flat layout) and the step count
+hipError_t unet_save_state(UNet *u, float *flat, float *m, float *v, int64_t *step, hipStream_t s) {
+    hipError_t e;
+    if ((e = to_flat(u, u->w32, flat, s)) != hipSuccess || (e = to_flat(u, u->m32, m, s)) != hipSuccess ||
+        (e = to_flat(u, u->v32, v, s)) != hipSuccess)
+        return e;
+    *step = u->adam_t;
+    return hipSuccess;
+}
+
+hipError_t unet_load_state(UNet *u, const float *flat, const float *m, const float *v, int64_t step, hipStream_t s) {
+    hipError_t e = unet_load(u, flat, s);
+    if (e != hipSuccess) return e;
+    size_t foff = 0;
+    for (int i = 0; i < kNL; ++i) {
+        const LayerDef &l = kLayers[i];
+        if ((e = launch_param_layout(const_cast<float *>(m) + foff, u->m32 + u->w_off[i], l.cout_r, l.cin_r, l.cout,
+                                     l.cin, true, s)) != hipSuccess ||
+            (e = launch_param_layout(const_cast<float *>(v) + foff, u->v32 + u->w_off[i], l.cout_r, l.cin_r, l.cout,
+                                     l.cin, true, s)) != hipSuccess)
+            return e;
+        foff += 9 * (size_t)l.cout_r * l.cin_r + l.cout_r;
+    }
+    u->adam_t = (int)step;
+    return hipSuccess;
+}
 hipError_t unet_grads_flat(UNet *u, float *flat, hipStream_t s) { return to_flat(u, u->g32, flat, s); }
 
 // Carve the workspace for batch B at H x W (H and W multiples of 8).  With

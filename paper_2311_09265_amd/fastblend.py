@@ -66,7 +66,7 @@ _EXPORTS = ["fb_create", "fb_destroy", "fb_last_error", "fb_alpha16_max", "fb_nu
             "fb_pyramid_bytes", "fb_build_pyramid", "fb_nnf_init", "fb_patchmatch_level", "fb_remap",
             "fb_blend_window", "fb_interpolate", "fb_patchmatch_batch", "fb_profile_enable",
             "fb_profile_read", "fb_unet_param_count", "fb_unet_forward_flops", "fb_unet_load", "fb_unet_save",
-            "fb_unet_forward", "fb_unet_gradients", "fb_unet_train_step", "fb_unet_pair_input", "fb_guard_read",
+            "fb_unet_forward", "fb_unet_gradients", "fb_unet_train_step", "fb_unet_pair_input", "fb_guard_read", "fb_unet_save_state", "fb_unet_load_state",
             "fb_patchmatch_level_noalloc"]
 
 
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH):
         "fb_unet_train_step": (i32, [vp, vp, vp, vp, i32, i32, i32, ctypes.c_float, vp, vp]),
         "fb_unet_pair_input": (i32, [vp, vp, vp, i32, i32, i32, i32, vp, vp]),
         "fb_guard_read": (i32, [vp, ctypes.POINTER(ctypes.c_uint64), i32, ctypes.POINTER(i32), vp]),
+        "fb_unet_save_state": (i32, [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]),
+        "fb_unet_load_state": (i32, [vp, vp, vp, vp, ctypes.c_int64, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -198,6 +200,21 @@ class Context:
         n = load_library().fb_unet_param_count()
         _check(load_library().fb_unet_load(self.handle, _dev(params, "params", torch.float32, (n,)),
                                            _stream(params)), "fb_unet_load")
+
+    def fb_unet_save_state(self):
+        """(params, adam_m, adam_v) as fp32 GPU tensors and the Adam step count."""
+        n = load_library().fb_unet_param_count()
+        out = [torch.empty(n, dtype=torch.float32, device=self.device) for _ in range(3)]
+        step = ctypes.c_int64(0)
+        _check(load_library().fb_unet_save_state(self.handle, *[_dev(t, "state") for t in out], ctypes.byref(step),
+                                                 _stream(out[0])), "fb_unet_save_state")
+        return out[0], out[1], out[2], int(step.value)
+
+    def fb_unet_load_state(self, params: torch.Tensor, adam_m: torch.Tensor, adam_v: torch.Tensor, step: int):
+        n = load_library().fb_unet_param_count()
+        _check(load_library().fb_unet_load_state(
+            self.handle, _dev(params, "params", torch.float32, (n,)), _dev(adam_m, "adam_m", torch.float32, (n,)),
+            _dev(adam_v, "adam_v", torch.float32, (n,)), int(step), _stream(params)), "fb_unet_load_state")
 
     def fb_unet_save(self) -> torch.Tensor:
         n = load_library().fb_unet_param_count()

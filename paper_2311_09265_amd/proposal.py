@@ -124,22 +124,71 @@ def prepare(ctx, pairs, chunk: int = 64):
 
 
 # ------------------------------------------------------------- training ----
-def train(ctx, x, t, m, steps: int = 6000, batch: int = 32, lr: float = 1e-3, seed: int = 0, log_every: int = 500):
+CHECKPOINT_VERSION = 1
+
+
+def save_checkpoint(ctx, path, step: int, steps: int, batch: int, lr: float, seed: int, gen):
+    """Everything training needs to continue exactly: the parameters and Adam
+    moments (flat fp32), Adam's step count, the minibatch generator's state,
+    the loop position and the schedule's arguments (version-tagged npz)."""
+    params, m, v, adam_step = ctx.fb_unet_save_state()
+    meta = {"version": CHECKPOINT_VERSION, "step": int(step), "steps": int(steps), "batch": int(batch),
+            "lr": float(lr), "seed": int(seed), "adam_step": int(adam_step)}
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, params=params.cpu().numpy(), adam_m=m.cpu().numpy(), adam_v=v.cpu().numpy(),
+             rng=gen.get_state().numpy(), meta=np.frombuffer(json.dumps(meta).encode(), np.uint8))
+    os.replace(tmp, path)
+
+
+def load_checkpoint(ctx, path, gen):
+    """Restore a checkpoint written by save_checkpoint into the context and the
+    generator; returns its meta (step, steps, batch, lr, seed)."""
+    import torch
+    with np.load(path, allow_pickle=False) as z:
+        meta = json.loads(bytes(z["meta"]).decode())
+        if meta.get("version") != CHECKPOINT_VERSION:
+            raise ValueError("checkpoint version %r, expected %d" % (meta.get("version"), CHECKPOINT_VERSION))
+        dev = ctx.device
+        ctx.fb_unet_load_state(torch.from_numpy(z["params"]).to(dev), torch.from_numpy(z["adam_m"]).to(dev),
+                               torch.from_numpy(z["adam_v"]).to(dev), meta["adam_step"])
+        gen.set_state(torch.from_numpy(np.array(z["rng"])))
+    return meta
+
+
+def train(ctx, x, t, m, steps: int = 6000, batch: int = 32, lr: float = 1e-3, seed: int = 0, log_every: int = 500,
+          ckpt: str = None, ckpt_every: int = 0, resume: bool = False, stop_after: int = None):
     """Adam on random minibatches, cosine-decayed learning rate; returns the
-    mean training loss of every log_every steps."""
+    mean training loss of every log_every steps.  With ckpt, a checkpoint is
+    written every ckpt_every steps (and at the end); resume=True continues
+    from it (the same parameters, Adam state, minibatch stream and schedule,
+    so the result equals an uninterrupted run).  stop_after ends the loop
+    after that many steps of this call (for a planned interruption)."""
     import torch
     g = torch.Generator().manual_seed(seed)
     n = x.shape[0]
     hist, losses = [], []
-    for step in range(steps):
+    start = 0
+    if resume:
+        meta = load_checkpoint(ctx, ckpt, g)
+        if (meta["steps"], meta["batch"], meta["lr"], meta["seed"]) != (steps, batch, float(lr), seed):
+            raise ValueError("checkpoint was written by a run with other arguments: %s" % meta)
+        start = meta["step"]
+    done = 0
+    for step in range(start, steps):
         idx = torch.randint(0, n, (batch,), generator=g).to(x.device)
         cur_lr = lr * 0.5 * (1 + np.cos(np.pi * step / steps))
         losses.append(ctx.fb_unet_train_step(x[idx].contiguous(), t[idx].contiguous(), m[idx].contiguous(),
                                              float(cur_lr)))
-        if (step + 1) % log_every == 0 or step + 1 == steps:
+        done += 1
+        last = step + 1 == steps or (stop_after is not None and done == stop_after)
+        if (step + 1) % log_every == 0 or last:
             hist.append(float(torch.cat(losses).mean().cpu()))
             losses = []
             log("step %d loss %.4f" % (step + 1, hist[-1]))
+        if ckpt and ((ckpt_every and (step + 1) % ckpt_every == 0) or last):
+            save_checkpoint(ctx, ckpt, step + 1, steps, batch, lr, seed, g)
+        if last:
+            break
     return hist
 
 

@@ -169,3 +169,33 @@ def test_trained_proposal_gain(ctx):
     learned2 = mean_energy(2, fbm.FB_LEARNED_SEED)
     assert learned2 < 0.5 * plain2, (learned2, plain2)
     assert learned2 <= plain6, (learned2, plain6)
+
+
+def test_training_state_round_trip_and_resume(ctx, tmp_path):
+    """Checkpoint and resume: the saved state (parameters, Adam moments, step)
+    loads back unchanged, and a training run interrupted after 4 of 10 steps
+    and resumed in a fresh context from its checkpoint ends with the same
+    parameters, bit for bit, as the run that was never interrupted."""
+    from paper_2311_09265_amd import proposal
+    flat = net.init_params(31)
+    x, t, m = _batch(8, 32, 32, 4)
+    x, t, m = x.cuda(), t.cuda(), m.cuda()
+    kw = dict(steps=10, batch=4, lr=1e-3, seed=3, log_every=100)
+    ctx.fb_unet_load(flat.cuda())
+    proposal.train(ctx, x, t, m, **kw)
+    ref = ctx.fb_unet_save().cpu()
+    p, mm, vv, step = ctx.fb_unet_save_state()
+    assert step == 10 and float(vv.abs().sum()) > 0
+    ctx.fb_unet_load_state(p, mm, vv, step)
+    p2, m2, v2, s2 = ctx.fb_unet_save_state()
+    assert s2 == 10 and torch.equal(p2, p) and torch.equal(m2, mm) and torch.equal(v2, vv)
+    ck = str(tmp_path / "ckpt.npz")
+    ctx.fb_unet_load(flat.cuda())
+    proposal.train(ctx, x, t, m, ckpt=ck, stop_after=4, **kw)
+    fresh = fbm.Context(0)
+    try:
+        proposal.train(fresh, x, t, m, ckpt=ck, resume=True, **kw)
+        got = fresh.fb_unet_save().cpu()
+    finally:
+        fresh.close()
+    assert torch.equal(got, ref)
