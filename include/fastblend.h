@@ -65,6 +65,11 @@ typedef enum {
  * iterations (see fb_params and fb_guard_read); FB_NO_GUARD takes every seed
  * as it is. */
 #define FB_NO_GUARD 0x100u
+/* FB_USE_GRAPH: when capturing the launch sequence fails (begin, end or
+ * instantiation of the capture), the call runs the same launches eagerly and
+ * returns FB_OK; fb_graph_fallbacks counts such calls.  FB_DEBUG_FAIL_CAPTURE
+ * makes the instantiation report failure, to exercise that path. */
+#define FB_DEBUG_FAIL_CAPTURE 0x80000000u
 /* Guide + style loss, Eq. 3 (Section 3.4): alpha ||G_j[u] - G_i[v]||^2 +
  * ||S_j[u] - S^_i[v]||^2, where S^_i is the source style S_j remapped (Alg. 2)
  * through the current field, refreshed at the start of every iteration (the
@@ -150,6 +155,18 @@ int32_t fb_alpha16_max(int32_t patch_radius);
  * Results never depend on the tile shape. */
 int32_t fb_num_tile_configs(void);
 fb_status fb_set_tile_config(fb_ctx *ctx, int32_t index);
+/* Autotuning results can be kept across processes.  fb_tuning_export
+ * writes the context's tuned shapes as text, one "batch shape key=index"
+ * line each (the key names the patch radius and the run of pair sizes of a
+ * batch), NUL-terminated into buf (host) when cap exceeds the text's length,
+ * and returns that length (-1 for a NULL context).  fb_tuning_import adds the
+ * lines of such a text to the context (FB_E_INVALID for a malformed line or
+ * an index outside [0, fb_num_tile_configs())); a batch shape it holds is not
+ * timed again.  The indices are only meaningful for the same library build
+ * and device.  fb_autotune_runs counts the batch shapes the context has timed. */
+int64_t fb_tuning_export(fb_ctx *ctx, char *buf, int64_t cap);
+fb_status fb_tuning_import(fb_ctx *ctx, const char *text);
+int64_t fb_autotune_runs(fb_ctx *ctx);
 
 /* ---------------------------------------------------------------------- */
 /* Image pyramid (Algorithm 1, "resize images S, T" for each level).       */
@@ -293,6 +310,7 @@ typedef struct {
     double milliseconds[FB_KERNEL_KINDS];
 } fb_profile;
 
+int64_t fb_graph_fallbacks(fb_ctx *ctx);
 fb_status fb_profile_enable(fb_ctx *ctx, int32_t on);
 fb_status fb_profile_read(fb_ctx *ctx, fb_profile *out, int32_t reset);
 

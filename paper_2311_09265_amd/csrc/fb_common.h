@@ -100,8 +100,10 @@ struct PMJob {
     // larger.  Iteration launches: guard_when 1 runs the job only for a
     // rejected seed, 2 only for a kept one, 0 always.  k_energy_sum: guard
     // is the sum the job's energies e_in are added to.  k_guard_select: for
-    // a rejected seed, (f_alt, e_alt) is copied over (f_out, e_out).
+    // a rejected seed, (f_alt, e_alt) is copied over (f_out, e_out) and
+    // *guard_any is set.
     uint64_t *guard;
+    uint64_t *guard_any;       // nonzero once any seed of the call was rejected
     const uint32_t *f_alt;
     const uint32_t *e_alt;
     int32_t guard_when;

@@ -517,8 +517,9 @@ k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unifo
 
 // An iteration launch whose jobs all run only for some outcome of the guard
 // of seeded pairs (guard_when != 0): a fixed grid walks the flat tiles and
-// skips the tiles of jobs that do not run, at the cost of a few scalar loads,
-// so a launch with nothing to do costs microseconds, not a workgroup per tile.
+// skips the tiles of jobs that do not run, at the cost of a few scalar loads;
+// when the jobs run only for rejected seeds and no seed of the call was
+// rejected, every workgroup returns after one load.
 template <int P, int TW, int TH>
 __global__ void __launch_bounds__(TW *TH)
 k_pm_iter_guarded(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles, int iter,
@@ -526,6 +527,8 @@ k_pm_iter_guarded(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, i
     __shared__ uint32_t s_tgt[(TH + 2 * P) * (TW + 2 * P)];
     __shared__ uint32_t s_f[(TH + 2) * (TW + 2)];
     extern __shared__ u32x4 s_btab4[];
+    // the launch's jobs all run only for a rejected seed: none was rejected
+    if (jobs[0].guard_when == 1 && *jobs[0].guard_any == 0) return;
     for (int t = (int)blockIdx.x; t < total_tiles; t += (int)gridDim.x) {
         const PMJob &J = jobs[find_job(jobs, n_jobs, uniform_tiles, t)];
         if (J.guard_when != 0 && (J.guard[0] > J.guard[1]) != (J.guard_when == 1)) continue;
@@ -646,6 +649,7 @@ k_guard_select(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int 
     const int v = tc.r * J.w + tc.c;
     J.f_out[v] = J.f_alt[v];
     J.e_out[v] = J.e_alt[v];
+    if (v == 0) *J.guard_any = 1;
 }
 
 // int32 [h][w][2] field -> packed; entries are clamped into the image so a

@@ -282,7 +282,7 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
     const int it_common = std::min(iters, plain_iters), it_all = std::max(iters, plain_iters);
     if (guarded) {
         uint64_t *sums = guard->sums;
-        const long n4 = 4L * guard->n;  // two uint64 per pair, cleared as floats
+        const long n4 = 4L * guard->n + 2;  // two uint64 per pair and the any-rejected word, cleared as floats
         sig_add(P, "gclr", (long long)(uintptr_t)sums, n4);
         P.ops.push_back({FB_KERNEL_OTHER, [=](hipStream_t s, const uint8_t *) {
             return launch_fill_zero(reinterpret_cast<float *>(sums), n4, s);
@@ -300,6 +300,7 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
             }
         if (active.empty()) continue;
         auto gsum = [&](const PairSpec &ps) { return guard->sums + 2 * ps.guard_slot; };
+        uint64_t *gany = guarded ? guard->sums + 2 * guard->n : nullptr;
         std::vector<PMJob> js;
         for (size_t k : active) {
             PairSpec &ps = pairs[k];
@@ -387,6 +388,7 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
                         j.f_out = ps.f[c ^ 1];
                         j.e_out = ps.e[c ^ 1];
                         j.guard = gsum(ps);
+                        j.guard_any = gany;
                         j.guard_when = plain_longer ? 1 : 2;
                         c ^= 1;
                     }
@@ -433,6 +435,7 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
             if (ps.guard_slot < 0) continue;
             PMJob j = job_geom(ps, l);
             j.guard = gsum(ps);
+            j.guard_any = gany;
             if (l == ps.L.levels - 1) {
                 PMJob a = job_geom(ps, l), b = job_geom(ps, l);
                 a.e_in = ps.e[cur[k]];
@@ -532,6 +535,9 @@ struct fb_ctx {
     std::vector<int> guard_map;  // last call: guard slot of each planned pair (-1: not guarded)
     int guard_n = 0;
     std::map<std::string, int> tuned;
+    int64_t autotune_runs = 0;
+    int64_t graph_fallbacks = 0;  // captures that failed and ran eagerly instead
+    std::string graph_fallback_reason;
     int forced_cfg = -1;
     std::string graph_sig;
     uint64_t graph_gen = ~0ull;
@@ -656,6 +662,7 @@ fb_status autotune(fb_ctx *ctx, Plan &P, hipStream_t s, int p, uint64_t seed) {
     FB_HIP(hipEventDestroy(e0));
     FB_HIP(hipEventDestroy(e1));
     ctx->tuned[P.tune_key] = best;
+    ++ctx->autotune_runs;
     return FB_OK;
 }
 
@@ -679,31 +686,48 @@ fb_status run_plan(fb_ctx *ctx, Plan &P, uint32_t flags, hipStream_t s, int p, u
             ctx->graph_stream != s) {
             if (ctx->graph_exec) FB_HIP(hipGraphExecDestroy(ctx->graph_exec));
             ctx->graph_exec = nullptr;
-            hipGraph_t g = nullptr;
-            FB_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            for (Op &op : P.ops) {
-                hipError_t e = op.fn(s, tab);
-                if (e != hipSuccess) {
-                    hipGraph_t dummy = nullptr;
-                    (void)hipStreamEndCapture(s, &dummy);
-                    if (dummy) (void)hipGraphDestroy(dummy);
-                    return fail(FB_E_HIP, std::string("launch during capture: ") + hipGetErrorString(e));
+            // A launch that fails is an error in any mode; a failure of the
+            // capture itself (begin, end, instantiate) falls back to running
+            // the same launches eagerly.
+            const char *stage = "hipStreamBeginCapture";
+            hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                for (Op &op : P.ops) {
+                    const hipError_t le = op.fn(s, tab);
+                    if (le != hipSuccess) {
+                        hipGraph_t dummy = nullptr;
+                        (void)hipStreamEndCapture(s, &dummy);
+                        if (dummy) (void)hipGraphDestroy(dummy);
+                        return fail(FB_E_HIP, std::string("launch during capture: ") + hipGetErrorString(le));
+                    }
+                }
+                hipGraph_t g = nullptr;
+                stage = "hipStreamEndCapture";
+                e = hipStreamEndCapture(s, &g);
+                if (e == hipSuccess) {
+                    stage = "hipGraphInstantiate";
+                    // FB_DEBUG_FAIL_CAPTURE: report this step as failed (tests of the fallback)
+                    e = (flags & FB_DEBUG_FAIL_CAPTURE) ? hipErrorNotSupported
+                                                         : hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
                 }
             }
-            FB_HIP(hipStreamEndCapture(s, &g));
-            hipError_t e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
             if (e != hipSuccess) {
+                (void)hipGetLastError();
                 ctx->graph_exec = nullptr;
-                return fail(FB_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+                ++ctx->graph_fallbacks;
+                ctx->graph_fallback_reason = std::string(stage) + ": " + hipGetErrorString(e);
+            } else {
+                ctx->graph_sig = P.sig;
+                ctx->graph_gen = ts.gen;
+                ctx->graph_stream = s;
             }
-            ctx->graph_sig = P.sig;
-            ctx->graph_gen = ts.gen;
-            ctx->graph_stream = s;
         }
-        FB_HIP(hipGraphLaunch(ctx->graph_exec, s));
-        FB_HIP(hipEventRecord(ts.done, s));
-        return FB_OK;
+        if (ctx->graph_exec) {
+            FB_HIP(hipGraphLaunch(ctx->graph_exec, s));
+            FB_HIP(hipEventRecord(ts.done, s));
+            return FB_OK;
+        }
     }
     for (Op &op : P.ops) {
         if (ctx->profiling) {
@@ -842,7 +866,7 @@ fb_status prepare_guard(fb_ctx *ctx, std::vector<PairSpec> &pairs, const fb_para
         }
     if (!n) return FB_OK;
     fb_status st;
-    if ((st = ensure(ctx, ctx->race, race_px * 16)) || (st = ensure(ctx, ctx->gsum, (size_t)n * 16))) return st;
+    if ((st = ensure(ctx, ctx->race, race_px * 16)) || (st = ensure(ctx, ctx->gsum, (size_t)n * 16 + 8))) return st;
     uint32_t *base = static_cast<uint32_t *>(ctx->race.p);
     size_t off = 0;
     int slot = 0;
@@ -1263,6 +1287,42 @@ fb_status fb_profile_read(fb_ctx *ctx, fb_profile *out, int32_t reset) {
 }
 
 int32_t fb_num_tile_configs(void) { return n_tile_cfgs(); }
+
+int64_t fb_autotune_runs(fb_ctx *ctx) { return ctx ? ctx->autotune_runs : -1; }
+
+int64_t fb_graph_fallbacks(fb_ctx *ctx) { return ctx ? ctx->graph_fallbacks : -1; }
+
+int64_t fb_tuning_export(fb_ctx *ctx, char *buf, int64_t cap) {
+    if (!ctx) return -1;
+    std::string text;
+    for (const auto &kv : ctx->tuned) text += kv.first + "=" + std::to_string(kv.second) + "\n";
+    if (buf && cap > (int64_t)text.size()) std::memcpy(buf, text.c_str(), text.size() + 1);
+    return (int64_t)text.size();
+}
+
+fb_status fb_tuning_import(fb_ctx *ctx, const char *text) {
+    if (!ctx || !text) return fail(FB_E_INVALID, "null pointer");
+    std::map<std::string, int> got;
+    const char *p = text;
+    while (*p) {
+        const char *eol = std::strchr(p, '\n');
+        const std::string line(p, eol ? (size_t)(eol - p) : std::strlen(p));
+        p = eol ? eol + 1 : p + line.size();
+        if (line.empty()) continue;
+        const size_t eq = line.rfind('=');
+        if (eq == std::string::npos || eq == 0 || eq + 1 >= line.size())
+            return fail(FB_E_INVALID, "tuning line without key=index: " + line);
+        int idx = 0;
+        for (size_t k = eq + 1; k < line.size(); ++k) {
+            if (line[k] < '0' || line[k] > '9' || idx > 1000) return fail(FB_E_INVALID, "bad tile index: " + line);
+            idx = idx * 10 + (line[k] - '0');
+        }
+        if (idx >= n_tile_cfgs()) return fail(FB_E_INVALID, "no such tile config: " + line);
+        got[line.substr(0, eq)] = idx;
+    }
+    for (const auto &kv : got) ctx->tuned[kv.first] = kv.second;
+    return FB_OK;
+}
 
 fb_status fb_set_tile_config(fb_ctx *ctx, int32_t index) {
     if (!ctx) return fail(FB_E_INVALID, "ctx is NULL");

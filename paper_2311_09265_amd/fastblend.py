@@ -29,6 +29,7 @@ FB_ACCURATE_BLEND = 0x20
 FB_TRACKING = 0x40
 FB_ALIGN = 0x80
 FB_NO_GUARD = 0x100
+FB_DEBUG_FAIL_CAPTURE = 0x80000000
 STATUS = {0: "FB_OK", -1: "FB_E_INVALID", -2: "FB_E_SHAPE", -3: "FB_E_UNSUPPORTED",
           -4: "FB_E_ALLOC", -5: "FB_E_HIP"}
 
@@ -67,6 +68,7 @@ _EXPORTS = ["fb_create", "fb_destroy", "fb_last_error", "fb_alpha16_max", "fb_nu
             "fb_blend_window", "fb_interpolate", "fb_patchmatch_batch", "fb_profile_enable",
             "fb_profile_read", "fb_unet_param_count", "fb_unet_forward_flops", "fb_unet_load", "fb_unet_save",
             "fb_unet_forward", "fb_unet_gradients", "fb_unet_train_step", "fb_unet_pair_input", "fb_guard_read", "fb_unet_save_state", "fb_unet_load_state",
+            "fb_tuning_export", "fb_tuning_import", "fb_autotune_runs", "fb_graph_fallbacks",
             "fb_patchmatch_level_noalloc"]
 
 
@@ -108,6 +110,10 @@ def load_library(path: str = LIB_PATH):
         "fb_unet_pair_input": (i32, [vp, vp, vp, i32, i32, i32, i32, vp, vp]),
         "fb_guard_read": (i32, [vp, ctypes.POINTER(ctypes.c_uint64), i32, ctypes.POINTER(i32), vp]),
         "fb_unet_save_state": (i32, [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]),
+        "fb_tuning_export": (ctypes.c_int64, [vp, ctypes.c_char_p, ctypes.c_int64]),
+        "fb_tuning_import": (i32, [vp, ctypes.c_char_p]),
+        "fb_autotune_runs": (ctypes.c_int64, [vp]),
+        "fb_graph_fallbacks": (ctypes.c_int64, [vp]),
         "fb_unet_load_state": (i32, [vp, vp, vp, vp, ctypes.c_int64, vp]),
     }
     for name, (res, args) in sig.items():
@@ -291,6 +297,45 @@ class Context:
         return torch.tensor([int(x) for x in buf[:2 * n.value]], dtype=torch.int64).reshape(n.value, 2)
 
     # ---- tuning ---------------------------------------------------------
+    def tuning_export(self) -> str:
+        L = load_library()
+        n = L.fb_tuning_export(self.handle, None, 0)
+        buf = ctypes.create_string_buffer(n + 1)
+        L.fb_tuning_export(self.handle, buf, n + 1)
+        return buf.value.decode()
+
+    def tuning_import(self, text: str):
+        _check(load_library().fb_tuning_import(self.handle, text.encode()), "fb_tuning_import")
+
+    def tuning_save(self, path: str):
+        """The tuned tile shapes as JSON, keyed by batch shape, with the device
+        and the library's tile-shape count they hold for."""
+        import json
+        L = load_library()
+        entries = dict(line.rsplit("=", 1) for line in self.tuning_export().splitlines() if line)
+        doc = {"format": 1, "device": torch.cuda.get_device_properties(self.device).gcnArchName,
+               "tile_configs": int(L.fb_num_tile_configs()), "entries": {k: int(v) for k, v in entries.items()}}
+        with open(path, "w") as f:
+            json.dump(doc, f, indent=1, sort_keys=True)
+
+    def tuning_load(self, path: str) -> bool:
+        """Load a file written by tuning_save; False (nothing loaded) if it was
+        written for another device or library."""
+        import json
+        with open(path) as f:
+            doc = json.load(f)
+        if (doc.get("format") != 1 or doc.get("device") != torch.cuda.get_device_properties(self.device).gcnArchName
+                or doc.get("tile_configs") != load_library().fb_num_tile_configs()):
+            return False
+        self.tuning_import("".join("%s=%d\n" % (k, v) for k, v in doc["entries"].items()))
+        return True
+
+    def fb_autotune_runs(self) -> int:
+        return int(load_library().fb_autotune_runs(self.handle))
+
+    def fb_graph_fallbacks(self) -> int:
+        return int(load_library().fb_graph_fallbacks(self.handle))
+
     def fb_set_tile_config(self, index: int):
         _check(load_library().fb_set_tile_config(self.handle, index), "fb_set_tile_config")
 

@@ -73,3 +73,56 @@ def test_plans_alternate_across_streams():
             assert float(np.abs(out.cpu().numpy().astype(np.float64) - refs[k]).max()) <= 1e-5, k
     finally:
         ctx.close()
+
+
+def test_failed_graph_capture_runs_eagerly():
+    """FB_USE_GRAPH with a capture that fails (forced with
+    FB_DEBUG_FAIL_CAPTURE) runs the launches eagerly: the call succeeds, the
+    blend equals the eager one, and the fallback is counted; a normal graph
+    call afterwards replays a captured graph again."""
+    g, s = _small_workload(5, 40, 56, 13)
+    ctx = fbm.Context(0)
+    try:
+        ref = ctx.fb_blend_window(g, s, 2, fbm.make_params(2, 2, 2, 17))
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.default_stream())
+        with torch.cuda.stream(side):
+            got = ctx.fb_blend_window(g, s, 2, fbm.make_params(2, 2, 2, 17,
+                                                               fbm.FB_USE_GRAPH | fbm.FB_DEBUG_FAIL_CAPTURE))
+            side.synchronize()
+            assert ctx.fb_graph_fallbacks() == 1
+            assert torch.equal(got, ref)
+            for _ in range(2):
+                again = ctx.fb_blend_window(g, s, 2, fbm.make_params(2, 2, 2, 17, fbm.FB_USE_GRAPH))
+                side.synchronize()
+                assert torch.equal(again, ref)
+        assert ctx.fb_graph_fallbacks() == 1
+    finally:
+        ctx.close()
+
+
+def test_tuning_results_persist_across_contexts(tmp_path):
+    """A batch shape tuned by one context and saved is not timed again by a
+    context that loads the file, and the results are the same."""
+    g, s = _small_workload(4, 48, 64, 21)
+    prm = fbm.make_params(2, 2, 2, 5)
+    a = fbm.Context(0)
+    try:
+        ra = a.fb_blend_window(g, s, 1, prm)
+        assert a.fb_autotune_runs() == 1
+        path = str(tmp_path / "tuning.json")
+        a.tuning_save(path)
+        text = a.tuning_export()
+    finally:
+        a.close()
+    b = fbm.Context(0)
+    try:
+        assert b.tuning_load(path)
+        assert b.tuning_export() == text
+        rb = b.fb_blend_window(g, s, 1, prm)
+        assert b.fb_autotune_runs() == 0
+        assert torch.equal(ra, rb)
+        with pytest.raises(fbm.FastBlendError):
+            b.tuning_import("p2;48x64*6=99\n")
+    finally:
+        b.close()
