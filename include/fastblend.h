@@ -181,6 +181,20 @@ size_t fb_pyramid_bytes(int32_t h, int32_t w, int32_t levels, int32_t patch_radi
 fb_status fb_build_pyramid(fb_ctx *ctx, const uint8_t *rgb, int32_t h, int32_t w,
                            int32_t levels, int32_t patch_radius, void *pyr, void *stream);
 
+/* Frames with their own row stride.  Every call that takes a frame as a
+ * contiguous uint8 [h][w][3] (or a video as [N][h][w][3]) has a variant for
+ * frames whose rows are not packed -- crops of larger images, rows padded for
+ * alignment, frames scattered in memory: row r of a frame starts at
+ * rgb + r * row_stride_bytes (device pointer), and row_stride_bytes >= 3 w
+ * (else FB_E_INVALID).  Results equal those of the contiguous calls on the
+ * same pixels. */
+typedef struct {
+    const uint8_t *rgb;
+    int64_t row_stride_bytes;
+} fb_frame;
+fb_status fb_build_pyramid_strided(fb_ctx *ctx, const uint8_t *rgb, int32_t h, int32_t w, int64_t row_stride_bytes,
+                                   int32_t levels, int32_t patch_radius, void *pyr, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* (1) NNF initialisation at pyramid level `level` (Algorithm 1, "randomly  */
 /* initialize F"; "initialize error matrix E").  src_pyr / tgt_pyr come     */
@@ -250,6 +264,10 @@ fb_status fb_remap(fb_ctx *ctx, const uint8_t *style, const int32_t *nnf, int32_
 fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, int32_t n_frames,
                           int32_t h, int32_t w, int32_t radius_M, const fb_params *params,
                           float *out, void *stream);
+/* the same with guides and styles as host arrays of n_frames fb_frame */
+fb_status fb_blend_window_frames(fb_ctx *ctx, const fb_frame *guides, const fb_frame *styles, int32_t n_frames,
+                                 int32_t h, int32_t w, int32_t radius_M, const fb_params *params, float *out,
+                                 void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* (5) Keyframe interpolation, Eq. 9: keyframes pass through (style / 255); */
@@ -261,6 +279,10 @@ fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *sty
 fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, int32_t h, int32_t w,
                          const int32_t *key_idx, const uint8_t *key_styles, int32_t n_keys,
                          const fb_params *params, float *out, void *stream);
+/* the same with guides (n_frames) and key styles (n_keys) as host arrays of fb_frame */
+fb_status fb_interpolate_frames(fb_ctx *ctx, const fb_frame *guides, int32_t n_frames, int32_t h, int32_t w,
+                                const int32_t *key_idx, const fb_frame *key_styles, int32_t n_keys,
+                                const fb_params *params, float *out, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Batched PatchMatch (Section 3.2, "we store images in batches"): the      */

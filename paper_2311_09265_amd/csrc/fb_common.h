@@ -142,8 +142,16 @@ struct RemapFrame {
     int32_t out_kind;
 };
 
+// One uint8 RGB input frame: row r starts at rgb + r * row_stride bytes.
+struct FrameRef {
+    const uint8_t *rgb;
+    int64_t row_stride;
+};
+
 // ---- launchers (stream-ordered, no synchronisation) ----
-hipError_t launch_pack_rgbx(const uint8_t *rgb, size_t rgb_stride, int n, int h, int w, int p,
+// frame f of the n packed is frames[f] (a device table), or `single` when
+// frames is nullptr (n = 1)
+hipError_t launch_pack_rgbx(const FrameRef *frames, FrameRef single, int n, int h, int w, int p,
                             uint8_t *dst, size_t dst_stride, size_t px_off, int pitch,
                             hipStream_t s);
 hipError_t launch_downsample(const uint8_t *base, size_t stride, int n, const LevelGeom &in,

@@ -60,16 +60,17 @@ size_t padded_image_bytes(int h, int w, int p, int32_t *pitch_out) {
 
 namespace {
 
-// RGB8 [h][w][3] -> padded (R,G,B,0) pixels; one thread per padded pixel.
+// RGB8 rows of h x w -> padded (R,G,B,0) pixels; one thread per padded pixel.
 __global__ void __launch_bounds__(256)
-k_pack_rgbx(const uint8_t *__restrict__ rgb, size_t rgb_stride, int h, int w, int p,
+k_pack_rgbx(const FrameRef *__restrict__ frames, FrameRef single, int h, int w, int p,
             uint8_t *__restrict__ dst, size_t dst_stride, size_t px_off, int pitch) {
     const int C = blockIdx.x * blockDim.x + threadIdx.x;
     const int R = blockIdx.y;
     const int f = blockIdx.z;
     if (C >= w + 2 * p) return;
+    const FrameRef fr = frames ? frames[f] : single;
     const int r = clampi(R - p, 0, h - 1), c = clampi(C - p, 0, w - 1);
-    const uint8_t *s = rgb + (size_t)f * rgb_stride + ((size_t)r * w + c) * 3;
+    const uint8_t *s = fr.rgb + (size_t)r * (size_t)fr.row_stride + (size_t)c * 3;
     const uint32_t px = (uint32_t)s[0] | ((uint32_t)s[1] << 8) | ((uint32_t)s[2] << 16);
     uint32_t *d = reinterpret_cast<uint32_t *>(dst + (size_t)f * dst_stride + px_off);
     d[(size_t)R * pitch + C] = px;
@@ -161,11 +162,11 @@ hipError_t launch_bound_tables(uint8_t *base, size_t stride, int n, const PyrLay
     return hipSuccess;
 }
 
-hipError_t launch_pack_rgbx(const uint8_t *rgb, size_t rgb_stride, int n, int h, int w, int p,
+hipError_t launch_pack_rgbx(const FrameRef *frames, FrameRef single, int n, int h, int w, int p,
                             uint8_t *dst, size_t dst_stride, size_t px_off, int pitch,
                             hipStream_t s) {
     dim3 grid((w + 2 * p + 255) / 256, h + 2 * p, n);
-    hipLaunchKernelGGL(k_pack_rgbx, grid, dim3(256), 0, s, rgb, rgb_stride, h, w, p, dst,
+    hipLaunchKernelGGL(k_pack_rgbx, grid, dim3(256), 0, s, frames, single, h, w, p, dst,
                        dst_stride, px_off, pitch);
     return hipGetLastError();
 }

@@ -153,18 +153,28 @@ void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cf
     }
 }
 
-// Pyramids of n frames (uint8 [n][h][w][3], contiguous) into dst[f * stride].
-// Pyramids whose frames are never a PatchMatch source (styles, T^-) skip the
-// bound tables (tables = false).
-void plan_pyramids(Plan &P, const uint8_t *rgb, int n, int h, int w, const PyrLayout &L,
+// Frames of a call: n uint8 RGB frames, each with its own pointer and row
+// stride (the contiguous calls pass [n][h][w][3]).
+typedef std::vector<FrameRef> Frames;
+
+Frames contiguous_frames(const uint8_t *base, int n, int h, int w) {
+    Frames f((size_t)n);
+    for (int k = 0; k < n; ++k) f[k] = FrameRef{base + (size_t)k * h * w * 3, (int64_t)w * 3};
+    return f;
+}
+
+// Pyramids of the frames into dst[f * stride].  Pyramids whose frames are
+// never a PatchMatch source (styles, T^-) skip the bound tables (tables =
+// false).
+void plan_pyramids(Plan &P, const Frames &frames, int h, int w, const PyrLayout &L,
                    uint8_t *dst, size_t stride, bool tables = true) {
-    const int p = L.p;
-    const size_t rgb_stride = (size_t)h * w * 3;
-    sig_add(P, tables ? "pyr" : "pyr-nt", (long long)(uintptr_t)rgb, n, ((long long)h << 32) | w,
+    const int p = L.p, n = (int)frames.size();
+    const size_t foff = table_append(P, frames.data(), frames.size());
+    sig_add(P, tables ? "pyr" : "pyr-nt", (long long)foff, n, ((long long)h << 32) | w,
             (long long)(uintptr_t)dst + L.levels);
-    P.ops.push_back({FB_KERNEL_PYRAMID, [=](hipStream_t s, const uint8_t *) {
-        hipError_t e = launch_pack_rgbx(rgb, rgb_stride, n, h, w, p, dst, stride, L.lv[0].px_off,
-                                        L.lv[0].pitch, s);
+    P.ops.push_back({FB_KERNEL_PYRAMID, [=](hipStream_t s, const uint8_t *tab) {
+        hipError_t e = launch_pack_rgbx(reinterpret_cast<const FrameRef *>(tab + foff), FrameRef{}, n, h, w, p, dst,
+                                        stride, L.lv[0].px_off, L.lv[0].pitch, s);
         for (int l = 1; l < L.levels && e == hipSuccess; ++l)
             e = launch_downsample(dst, stride, n, L.lv[l - 1], L.lv[l], p, s);
         if (e == hipSuccess && tables) e = launch_bound_tables(dst, stride, n, L, s);
@@ -172,14 +182,15 @@ void plan_pyramids(Plan &P, const uint8_t *rgb, int n, int h, int w, const PyrLa
     }});
 }
 
-// Padded 4-byte pixels of n style frames.
-void plan_style_pack(Plan &P, const uint8_t *rgb, int n, int h, int w, int p, uint8_t *dst,
-                     size_t stride, int pitch) {
-    const size_t rgb_stride = (size_t)h * w * 3;
-    sig_add(P, "sty", (long long)(uintptr_t)rgb, n, ((long long)h << 32) | w,
-            (long long)(uintptr_t)dst);
-    P.ops.push_back({FB_KERNEL_PYRAMID, [=](hipStream_t s, const uint8_t *) {
-        return launch_pack_rgbx(rgb, rgb_stride, n, h, w, p, dst, stride, 0, pitch, s);
+// Padded 4-byte pixels of the style frames.
+void plan_style_pack(Plan &P, const Frames &frames, int h, int w, int p, uint8_t *dst, size_t stride,
+                     int pitch) {
+    const int n = (int)frames.size();
+    const size_t foff = table_append(P, frames.data(), frames.size());
+    sig_add(P, "sty", (long long)foff, n, ((long long)h << 32) | w, (long long)(uintptr_t)dst);
+    P.ops.push_back({FB_KERNEL_PYRAMID, [=](hipStream_t s, const uint8_t *tab) {
+        return launch_pack_rgbx(reinterpret_cast<const FrameRef *>(tab + foff), FrameRef{}, n, h, w, p, dst, stride,
+                                0, pitch, s);
     }});
 }
 
@@ -949,7 +960,7 @@ fb_status begin(fb_ctx *ctx) {
 // window's length.  All NNFs the tables and queries use run as one batch;
 // table column L is one remap launch (its entries add the column L - 1
 // entry and the frames of the new block), the output one more.
-fb_status blend_fast(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, int N, int h, int w, int M,
+fb_status blend_fast(fb_ctx *ctx, const Frames &guides, const Frames &styles, int N, int h, int w, int M,
                      const fb_params *params, float *out, hipStream_t stream) {
     fb_status st;
     const int p = params->patch_radius, K = params->levels;
@@ -1005,8 +1016,8 @@ fb_status blend_fast(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, 
     float *tab = static_cast<float *>(ctx->tables.p);
 
     Plan P;
-    plan_pyramids(P, guides, N, h, w, Lp, pyr, Lp.bytes);
-    plan_style_pack(P, styles, N, h, w, p, sty, sbytes, pitch);
+    plan_pyramids(P, guides, h, w, Lp, pyr, Lp.bytes);
+    plan_style_pack(P, styles, h, w, p, sty, sbytes, pitch);
     std::vector<PairSpec> pairs;
     for (size_t k = 0; k < n_pairs; ++k) {
         PairSpec ps{};
@@ -1082,7 +1093,7 @@ fb_status blend_fast(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, 
 // uint8 (one remap launch), and its pyramid; every NNF estimated again under
 // Eq. 8 against its target frame's T^- (the style iteration kernel, no
 // refresh); the window mean of the styles remapped with the new NNFs.
-fb_status blend_accurate(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, int N, int h, int w, int M,
+fb_status blend_accurate(fb_ctx *ctx, const Frames &guides, const Frames &styles, int N, int h, int w, int M,
                          const fb_params *params, float *out, hipStream_t stream) {
     fb_status st;
     const int p = params->patch_radius, K = params->levels;
@@ -1107,8 +1118,8 @@ fb_status blend_accurate(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styl
     uint32_t *fe = static_cast<uint32_t *>(ctx->fe.p);
 
     Plan P;
-    plan_pyramids(P, guides, N, h, w, L, pyr, L.bytes);
-    plan_pyramids(P, styles, N, h, w, L, sty, L.bytes, false);
+    plan_pyramids(P, guides, h, w, L, pyr, L.bytes);
+    plan_pyramids(P, styles, h, w, L, sty, L.bytes, false);
     // fields and energies of pair k in pass q (0: Eq. 1, 1: Eq. 8), n pairs,
     // in slices of npx entries of fe: f[0] at q n + k, f[1] at 2n + q n + k,
     // e[0] at 4n + q n + k, e[1] at 6n + q n + k
@@ -1159,7 +1170,7 @@ fb_status blend_accurate(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styl
         frames.push_back(fr);
     }
     add_remap_launch(P, frames, terms, h, w, pitch, p);
-    plan_pyramids(P, tbar_in, N, h, w, L, tbar, L.bytes, false);
+    plan_pyramids(P, contiguous_frames(tbar_in, N, h, w), h, w, L, tbar, L.bytes, false);
     if (!second.empty()) plan_patchmatch(P, second, params->iters, p, params->seed, cfg, true, params->alpha16, true);
     terms.clear();
     frames.clear();
@@ -1338,16 +1349,22 @@ size_t fb_pyramid_bytes(int32_t h, int32_t w, int32_t levels, int32_t patch_radi
 
 fb_status fb_build_pyramid(fb_ctx *ctx, const uint8_t *rgb, int32_t h, int32_t w, int32_t levels,
                            int32_t patch_radius, void *pyr, void *stream) {
+    return fb_build_pyramid_strided(ctx, rgb, h, w, (int64_t)w * 3, levels, patch_radius, pyr, stream);
+}
+
+fb_status fb_build_pyramid_strided(fb_ctx *ctx, const uint8_t *rgb, int32_t h, int32_t w, int64_t row_stride_bytes,
+                                   int32_t levels, int32_t patch_radius, void *pyr, void *stream) {
     fb_status st = begin(ctx);
     if (st) return st;
     if (!rgb || !pyr) return fail(FB_E_INVALID, "null pointer");
     if ((st = check_size(h, w))) return st;
+    if (row_stride_bytes < (int64_t)w * 3) return fail(FB_E_INVALID, "row_stride_bytes must be at least 3 w");
     if (levels < 1 || levels > kMaxLevels) return fail(FB_E_INVALID, "levels must be in [1, 16]");
     if (!valid_p(patch_radius)) return fail(FB_E_UNSUPPORTED, "patch_radius must be in [1, 4]");
     const PyrLayout L = pyr_layout(h, w, levels, patch_radius);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    FB_HIP(launch_pack_rgbx(rgb, 0, 1, h, w, patch_radius, static_cast<uint8_t *>(pyr), 0,
-                            L.lv[0].px_off, L.lv[0].pitch, s));
+    FB_HIP(launch_pack_rgbx(nullptr, FrameRef{rgb, row_stride_bytes}, 1, h, w, patch_radius,
+                            static_cast<uint8_t *>(pyr), 0, L.lv[0].px_off, L.lv[0].pitch, s));
     for (int l = 1; l < levels; ++l)
         FB_HIP(launch_downsample(static_cast<uint8_t *>(pyr), 0, 1, L.lv[l - 1], L.lv[l],
                                  patch_radius, s));
@@ -1540,7 +1557,7 @@ fb_status fb_remap(fb_ctx *ctx, const uint8_t *style, const int32_t *nnf, int32_
     uint8_t *sty = static_cast<uint8_t *>(ctx->style.p);
     uint32_t *f = static_cast<uint32_t *>(ctx->fe.p);
     Plan P;
-    plan_style_pack(P, style, 1, h, w, p, sty, sbytes, pitch);
+    plan_style_pack(P, contiguous_frames(style, 1, h, w), h, w, p, sty, sbytes, pitch);
     sig_add(P, "f2p", (long long)(uintptr_t)nnf, h, w, (long long)(uintptr_t)f);
     P.ops.push_back({FB_KERNEL_OTHER, [=](hipStream_t s, const uint8_t *) {
         return launch_field_to_packed(nnf, f, h, w, s);
@@ -1551,12 +1568,14 @@ fb_status fb_remap(fb_ctx *ctx, const uint8_t *style, const int32_t *nnf, int32_
     return run_plan(ctx, P, 0, static_cast<hipStream_t>(stream), p, 0);
 }
 
-fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, int32_t n_frames,
-                          int32_t h, int32_t w, int32_t radius_M, const fb_params *params,
-                          float *out, void *stream) {
+}  // extern "C"
+
+static fb_status blend_window_impl(fb_ctx *ctx, const Frames &guides, const Frames &styles, int32_t n_frames,
+                                   int32_t h, int32_t w, int32_t radius_M, const fb_params *params,
+                                   float *out, void *stream) {
     fb_status st = begin(ctx);
     if (st) return st;
-    if (!guides || !styles || !out) return fail(FB_E_INVALID, "null pointer");
+    if (!out) return fail(FB_E_INVALID, "null pointer");
     if ((st = check_size(h, w)) || (st = check_params(params, true))) return st;
     if (n_frames < 1) return fail(FB_E_INVALID, "n_frames must be >= 1");
     if (radius_M < 0) return fail(FB_E_INVALID, "radius_M must be >= 0");
@@ -1587,9 +1606,9 @@ fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *sty
     uint8_t *shat = static_cast<uint8_t *>(ctx->shat.p);
 
     Plan P;
-    plan_pyramids(P, guides, N, h, w, L, pyr, L.bytes);
-    if (style) plan_pyramids(P, styles, N, h, w, L, sty, L.bytes, false);
-    else plan_style_pack(P, styles, N, h, w, p, sty, sbytes, pitch);
+    plan_pyramids(P, guides, h, w, L, pyr, L.bytes);
+    if (style) plan_pyramids(P, styles, h, w, L, sty, L.bytes, false);
+    else plan_style_pack(P, styles, h, w, p, sty, sbytes, pitch);
     std::vector<PairSpec> pairs;
     pairs.reserve(n_pairs);
     for (int i = 0; i < N; ++i)
@@ -1640,12 +1659,12 @@ fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *sty
     return run_plan(ctx, P, params->flags, static_cast<hipStream_t>(stream), p, params->seed);
 }
 
-fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, int32_t h, int32_t w,
-                         const int32_t *key_idx, const uint8_t *key_styles, int32_t n_keys,
-                         const fb_params *params, float *out, void *stream) {
+static fb_status interpolate_impl(fb_ctx *ctx, const Frames &guides, int32_t n_frames, int32_t h, int32_t w,
+                                  const int32_t *key_idx, const Frames &key_styles, int32_t n_keys,
+                                  const fb_params *params, float *out, void *stream) {
     fb_status st = begin(ctx);
     if (st) return st;
-    if (!guides || !key_idx || !key_styles || !out) return fail(FB_E_INVALID, "null pointer");
+    if (!key_idx || !out) return fail(FB_E_INVALID, "null pointer");
     if ((st = check_size(h, w)) || (st = check_params(params, true))) return st;
     if (params->flags & (FB_STYLE_LOSS | FB_FAST_BLEND | FB_ACCURATE_BLEND))
         return fail(FB_E_UNSUPPORTED, "fb_interpolate takes FB_TRACKING and FB_ALIGN, not the blend's loss or modes");
@@ -1684,9 +1703,9 @@ fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, i
     uint32_t *fe = static_cast<uint32_t *>(ctx->fe.p);
 
     Plan P;
-    plan_pyramids(P, guides, N, h, w, L, pyr, L.bytes);
-    if (align) plan_pyramids(P, key_styles, n_keys, h, w, L, sty, L.bytes, false);
-    else plan_style_pack(P, key_styles, n_keys, h, w, p, sty, sbytes, pitch);
+    plan_pyramids(P, guides, h, w, L, pyr, L.bytes);
+    if (align) plan_pyramids(P, key_styles, h, w, L, sty, L.bytes, false);
+    else plan_style_pack(P, key_styles, h, w, p, sty, sbytes, pitch);
     std::vector<PairSpec> pairs;
     std::vector<int> pair_key;
     for (int i = 0; i < N; ++i) {
@@ -1759,6 +1778,61 @@ fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, i
     }
     add_remap_launch(P, frames, terms, h, w, pitch, p);
     return run_plan(ctx, P, params->flags, static_cast<hipStream_t>(stream), p, params->seed);
+}
+
+static fb_status frames_of(const fb_frame *in, int32_t n, int32_t w, Frames *out) {
+    if (!in) return fail(FB_E_INVALID, "null pointer");
+    if (n < 1) return fail(FB_E_INVALID, "need at least one frame");
+    out->resize((size_t)n);
+    for (int32_t k = 0; k < n; ++k) {
+        if (!in[k].rgb) return fail(FB_E_INVALID, "null frame pointer");
+        if (in[k].row_stride_bytes < (int64_t)w * 3) return fail(FB_E_INVALID, "row_stride_bytes must be at least 3 w");
+        (*out)[k] = FrameRef{in[k].rgb, in[k].row_stride_bytes};
+    }
+    return FB_OK;
+}
+
+extern "C" {
+
+fb_status fb_blend_window(fb_ctx *ctx, const uint8_t *guides, const uint8_t *styles, int32_t n_frames,
+                          int32_t h, int32_t w, int32_t radius_M, const fb_params *params,
+                          float *out, void *stream) {
+    if (!ctx) return fail(FB_E_INVALID, "ctx is NULL");
+    if (!guides || !styles) return fail(FB_E_INVALID, "null pointer");
+    if (n_frames < 1 || h < 1 || w < 1) return fail(FB_E_INVALID, "n_frames and image sizes must be positive");
+    return blend_window_impl(ctx, contiguous_frames(guides, n_frames, h, w), contiguous_frames(styles, n_frames, h, w),
+                             n_frames, h, w, radius_M, params, out, stream);
+}
+
+fb_status fb_blend_window_frames(fb_ctx *ctx, const fb_frame *guides, const fb_frame *styles, int32_t n_frames,
+                                 int32_t h, int32_t w, int32_t radius_M, const fb_params *params, float *out,
+                                 void *stream) {
+    if (!ctx) return fail(FB_E_INVALID, "ctx is NULL");
+    Frames g, s;
+    fb_status st;
+    if ((st = frames_of(guides, n_frames, w, &g)) || (st = frames_of(styles, n_frames, w, &s))) return st;
+    return blend_window_impl(ctx, g, s, n_frames, h, w, radius_M, params, out, stream);
+}
+
+fb_status fb_interpolate(fb_ctx *ctx, const uint8_t *guides, int32_t n_frames, int32_t h, int32_t w,
+                         const int32_t *key_idx, const uint8_t *key_styles, int32_t n_keys,
+                         const fb_params *params, float *out, void *stream) {
+    if (!ctx) return fail(FB_E_INVALID, "ctx is NULL");
+    if (!guides || !key_styles) return fail(FB_E_INVALID, "null pointer");
+    if (n_frames < 1 || n_keys < 1 || h < 1 || w < 1)
+        return fail(FB_E_INVALID, "need n_frames >= 1, n_keys >= 1 and positive image sizes");
+    return interpolate_impl(ctx, contiguous_frames(guides, n_frames, h, w), n_frames, h, w, key_idx,
+                            contiguous_frames(key_styles, n_keys, h, w), n_keys, params, out, stream);
+}
+
+fb_status fb_interpolate_frames(fb_ctx *ctx, const fb_frame *guides, int32_t n_frames, int32_t h, int32_t w,
+                                const int32_t *key_idx, const fb_frame *key_styles, int32_t n_keys,
+                                const fb_params *params, float *out, void *stream) {
+    if (!ctx) return fail(FB_E_INVALID, "ctx is NULL");
+    Frames g, k;
+    fb_status st;
+    if ((st = frames_of(guides, n_frames, w, &g)) || (st = frames_of(key_styles, n_keys, w, &k))) return st;
+    return interpolate_impl(ctx, g, n_frames, h, w, key_idx, k, n_keys, params, out, stream);
 }
 
 fb_status fb_patchmatch_batch(fb_ctx *ctx, const fb_pair_desc *pairs_in, int32_t n_pairs,

@@ -54,6 +54,10 @@ class fb_pair_desc(ctypes.Structure):
                 ("src_style_pyr", ctypes.c_void_p)]
 
 
+class fb_frame(ctypes.Structure):
+    _fields_ = [("rgb", ctypes.c_void_p), ("row_stride_bytes", ctypes.c_int64)]
+
+
 KERNEL_KINDS = ["pyramid", "pm_start", "pm_iter", "pm_export", "remap", "other", "unet", "style"]
 
 
@@ -69,6 +73,7 @@ _EXPORTS = ["fb_create", "fb_destroy", "fb_last_error", "fb_alpha16_max", "fb_nu
             "fb_profile_read", "fb_unet_param_count", "fb_unet_forward_flops", "fb_unet_load", "fb_unet_save",
             "fb_unet_forward", "fb_unet_gradients", "fb_unet_train_step", "fb_unet_pair_input", "fb_guard_read", "fb_unet_save_state", "fb_unet_load_state",
             "fb_tuning_export", "fb_tuning_import", "fb_autotune_runs", "fb_graph_fallbacks",
+            "fb_build_pyramid_strided", "fb_blend_window_frames", "fb_interpolate_frames",
             "fb_patchmatch_level_noalloc"]
 
 
@@ -111,6 +116,11 @@ def load_library(path: str = LIB_PATH):
         "fb_guard_read": (i32, [vp, ctypes.POINTER(ctypes.c_uint64), i32, ctypes.POINTER(i32), vp]),
         "fb_unet_save_state": (i32, [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]),
         "fb_tuning_export": (ctypes.c_int64, [vp, ctypes.c_char_p, ctypes.c_int64]),
+        "fb_build_pyramid_strided": (i32, [vp, vp, i32, i32, ctypes.c_int64, i32, i32, vp, vp]),
+        "fb_blend_window_frames": (i32, [vp, ctypes.POINTER(fb_frame), ctypes.POINTER(fb_frame), i32, i32, i32, i32,
+                                         P, vp, vp]),
+        "fb_interpolate_frames": (i32, [vp, ctypes.POINTER(fb_frame), i32, i32, i32, vp, ctypes.POINTER(fb_frame), i32,
+                                        P, vp, vp]),
         "fb_tuning_import": (i32, [vp, ctypes.c_char_p]),
         "fb_autotune_runs": (ctypes.c_int64, [vp]),
         "fb_graph_fallbacks": (ctypes.c_int64, [vp]),
@@ -146,6 +156,29 @@ def _dev(t: Optional[torch.Tensor], name: str, dtype=None, shape=None):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _as_frames(t: torch.Tensor, name: str, n: int, h: int, w: int):
+    """fb_frame array of a uint8 [n][h][w][3] GPU tensor whose pixels are
+    packed (strides 3, 1) and whose rows and frames may have any stride."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.uint8:
+        raise TypeError("%s must be a uint8 GPU tensor" % name)
+    if tuple(t.shape) != (n, h, w, 3):
+        raise ValueError("%s must have shape %s, got %s" % (name, (n, h, w, 3), tuple(t.shape)))
+    sf, sr, sc, sch = t.stride()
+    if sc != 3 or sch != 1 or sr < 3 * w:
+        raise ValueError("%s: pixels must be packed RGB (strides (.., .., 3, 1)) with rows of at least 3 w bytes" % name)
+    base = t.data_ptr()
+    arr = (fb_frame * n)()
+    for k in range(n):
+        arr[k] = fb_frame(base + k * sf, sr)
+    return arr
+
+
+def _frames(t: torch.Tensor, name: str, n: int, h: int, w: int):
+    """None for a contiguous uint8 [n][h][w][3] GPU tensor, else its fb_frame array."""
+    arr = _as_frames(t, name, n, h, w)
+    return None if t.is_contiguous() else arr
 
 
 def _check_pyr(pyr: torch.Tensor, name: str, h: int, w: int, levels: int, patch_radius: int):
@@ -341,14 +374,20 @@ class Context:
 
     # ---- pyramid --------------------------------------------------------
     def fb_build_pyramid(self, rgb: torch.Tensor, levels: int, patch_radius: int = 2) -> torch.Tensor:
+        """rgb: uint8 [h][w][3] on the GPU, contiguous or with a row stride."""
         h, w = rgb.shape[:2]
-        _dev(rgb, "rgb", torch.uint8, (h, w, 3))
+        fr = _frames(rgb.unsqueeze(0), "rgb", 1, h, w)
         nbytes = load_library().fb_pyramid_bytes(h, w, levels, patch_radius)
         if nbytes == 0:
             raise ValueError("invalid pyramid parameters")
         pyr = torch.empty(nbytes, dtype=torch.uint8, device=rgb.device)
-        _check(load_library().fb_build_pyramid(self.handle, _dev(rgb, "rgb"), h, w, levels, patch_radius,
-                                               _dev(pyr, "pyr"), _stream(rgb)), "fb_build_pyramid")
+        if fr is None:
+            _check(load_library().fb_build_pyramid(self.handle, _dev(rgb, "rgb"), h, w, levels, patch_radius,
+                                                   _dev(pyr, "pyr"), _stream(rgb)), "fb_build_pyramid")
+        else:
+            _check(load_library().fb_build_pyramid_strided(self.handle, ctypes.c_void_p(fr[0].rgb), h, w,
+                                                           fr[0].row_stride_bytes, levels, patch_radius,
+                                                           _dev(pyr, "pyr"), _stream(rgb)), "fb_build_pyramid_strided")
         return pyr
 
     # ---- per-pair PatchMatch ------------------------------------------------
@@ -415,27 +454,46 @@ class Context:
 
     def fb_blend_window(self, guides: torch.Tensor, styles: torch.Tensor, radius_M: int,
                         params: fb_params, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """guides, styles: uint8 [N][h][w][3] on the GPU, contiguous or views
+        with packed pixels and any row / frame strides (then the fb_frame call)."""
         n, h, w = guides.shape[:3]
         if out is None:
             out = torch.empty((n, h, w, 3), dtype=torch.float32, device=guides.device)
-        _check(load_library().fb_blend_window(
-            self.handle, _dev(guides, "guides", torch.uint8, (n, h, w, 3)),
-            _dev(styles, "styles", torch.uint8, (n, h, w, 3)), n, h, w, radius_M, ctypes.byref(params),
-            _dev(out, "out", torch.float32, (n, h, w, 3)), _stream(guides)), "fb_blend_window")
+        fg, fs = _frames(guides, "guides", n, h, w), _frames(styles, "styles", n, h, w)
+        if fg is None and fs is None:
+            _check(load_library().fb_blend_window(
+                self.handle, _dev(guides, "guides", torch.uint8, (n, h, w, 3)),
+                _dev(styles, "styles", torch.uint8, (n, h, w, 3)), n, h, w, radius_M, ctypes.byref(params),
+                _dev(out, "out", torch.float32, (n, h, w, 3)), _stream(guides)), "fb_blend_window")
+        else:
+            fg = _as_frames(guides, "guides", n, h, w)
+            fs = _as_frames(styles, "styles", n, h, w)
+            _check(load_library().fb_blend_window_frames(
+                self.handle, fg, fs, n, h, w, radius_M, ctypes.byref(params),
+                _dev(out, "out", torch.float32, (n, h, w, 3)), _stream(guides)), "fb_blend_window_frames")
         return out
 
     def fb_interpolate(self, guides: torch.Tensor, key_idx: Sequence[int], key_styles: torch.Tensor,
                        params: fb_params, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         n, h, w = guides.shape[:3]
-        keys = (ctypes.c_int32 * len(key_idx))(*[int(k) for k in key_idx])
+        nk = len(key_idx)
+        keys = (ctypes.c_int32 * nk)(*[int(k) for k in key_idx])
         if out is None:
             out = torch.empty((n, h, w, 3), dtype=torch.float32, device=guides.device)
-        _check(load_library().fb_interpolate(
-            self.handle, _dev(guides, "guides", torch.uint8, (n, h, w, 3)), n, h, w,
-            ctypes.cast(keys, ctypes.c_void_p),
-            _dev(key_styles, "key_styles", torch.uint8, (len(key_idx), h, w, 3)), len(key_idx),
-            ctypes.byref(params), _dev(out, "out", torch.float32, (n, h, w, 3)), _stream(guides)),
-            "fb_interpolate")
+        fg, fk = _frames(guides, "guides", n, h, w), _frames(key_styles, "key_styles", nk, h, w)
+        if fg is None and fk is None:
+            _check(load_library().fb_interpolate(
+                self.handle, _dev(guides, "guides", torch.uint8, (n, h, w, 3)), n, h, w,
+                ctypes.cast(keys, ctypes.c_void_p),
+                _dev(key_styles, "key_styles", torch.uint8, (nk, h, w, 3)), nk,
+                ctypes.byref(params), _dev(out, "out", torch.float32, (n, h, w, 3)), _stream(guides)),
+                "fb_interpolate")
+        else:
+            fg = _as_frames(guides, "guides", n, h, w)
+            fk = _as_frames(key_styles, "key_styles", nk, h, w)
+            _check(load_library().fb_interpolate_frames(
+                self.handle, fg, n, h, w, ctypes.cast(keys, ctypes.c_void_p), fk, nk, ctypes.byref(params),
+                _dev(out, "out", torch.float32, (n, h, w, 3)), _stream(guides)), "fb_interpolate_frames")
         return out
 
     def fb_patchmatch_batch(self, pairs: Sequence[dict], params: fb_params):

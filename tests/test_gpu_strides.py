@@ -1,0 +1,86 @@
+"""GPU tests of frames with their own row stride (fb_frame calls): crops of
+larger images and frames with different padded row strides give exactly the
+results of the same pixels passed contiguously."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2311_09265_amd import fastblend as fbm
+from paper_2311_09265_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = fbm.Context(0)
+    yield c
+    c.close()
+
+
+def _canvas(N, H, W, seed):
+    return torch.from_numpy(synth.sprite_video(N, H, W, seed, n_sprites=3, side=(8, 24))).cuda()
+
+
+def test_cropped_views_equal_contiguous(ctx):
+    """Guides and styles as crops (row stride of the larger canvas, frame
+    stride of the canvas): pyramids byte for byte, blend and interpolation
+    bit-identical to the contiguous copies."""
+    N, h, w = 5, 40, 52
+    G = _canvas(N, h + 9, w + 17, 3)
+    S = _canvas(N, h + 9, w + 17, 4)
+    g, s = G[:, 4:4 + h, 7:7 + w], S[:, 4:4 + h, 7:7 + w]
+    assert not g.is_contiguous()
+    gc, sc = g.contiguous(), s.contiguous()
+    prm = fbm.make_params(2, 2, 3, 0xFB5EED31)
+    # pyramids of a cropped frame serve PatchMatch exactly as those of its copy
+    # (buffers are compared through their use: their padding bytes are unset)
+    for l in (1, 3):
+        pm = [ctx.fb_patchmatch_batch([dict(src_pyr=ctx.fb_build_pyramid(a[2], l), tgt_pyr=ctx.fb_build_pyramid(a[3], l),
+                                            h=h, w=w, levels=l, pair_id=11)], fbm.make_params(2, l, 3, 7))[0]
+              for a in (g, gc)]
+        assert torch.equal(pm[0][0], pm[1][0]) and torch.equal(pm[0][1], pm[1][1])
+    assert torch.equal(ctx.fb_blend_window(g, s, 2, prm), ctx.fb_blend_window(gc, sc, 2, prm))
+    sprm = fbm.make_params(2, 2, 2, 0xFB5EED31, fbm.FB_STYLE_LOSS, 16)
+    assert torch.equal(ctx.fb_blend_window(g, s, 1, sprm), ctx.fb_blend_window(gc, sc, 1, sprm))
+    keys = [0, 4]
+    iprm = fbm.make_params(2, 2, 3, 0xFB5EED32, fbm.FB_TRACKING)
+    assert torch.equal(ctx.fb_interpolate(g, keys, s[keys], iprm), ctx.fb_interpolate(gc, keys, sc[keys], iprm))
+
+
+def test_frames_with_different_row_strides(ctx):
+    """Each frame its own allocation with its own padded row stride, through
+    the C ABI's fb_frame array; an undersized stride is refused."""
+    N, h, w, M = 4, 36, 44, 1
+    g = _canvas(N, h, w, 8)
+    s = _canvas(N, h, w, 9)
+    keep = []
+
+    def frames(x):
+        arr = (fbm.fb_frame * N)()
+        for k in range(N):
+            stride = 3 * w + 16 * k + 4
+            buf = torch.zeros((h, stride), dtype=torch.uint8, device="cuda")
+            buf[:, :3 * w] = x[k].reshape(h, 3 * w)
+            keep.append(buf)
+            arr[k] = fbm.fb_frame(buf.data_ptr(), stride)
+        return arr
+    prm = fbm.make_params(2, 2, 3, 0xFB5EED33)
+    out = torch.empty((N, h, w, 3), dtype=torch.float32, device="cuda")
+    L = fbm.load_library()
+    torch.cuda.synchronize()
+    st = L.fb_blend_window_frames(ctx.handle, frames(g), frames(s), N, h, w, M, ctypes.byref(prm),
+                                  ctypes.c_void_p(out.data_ptr()), None)
+    assert st == 0, L.fb_last_error()
+    torch.cuda.synchronize()
+    ref = ctx.fb_blend_window(g, s, M, prm)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    bad = frames(g)
+    bad[1] = fbm.fb_frame(bad[1].rgb, 3 * w - 1)
+    assert L.fb_blend_window_frames(ctx.handle, bad, frames(s), N, h, w, M, ctypes.byref(prm),
+                                    ctypes.c_void_p(out.data_ptr()), None) == -1
+    assert b"row_stride_bytes" in L.fb_last_error()
