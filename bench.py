@@ -164,8 +164,9 @@ def bench_learned(ctx, fbm, g, s, out, M, p, levels, seed, wpath, args, pairs, N
     ms_unguarded = (time.perf_counter() - t0) / args.steps * 1e3
     log("learned without the guard: %.2f ms/step" % ms_unguarded)
     guard = {"rule": "each seeded pair's coarsest level (seeded start, %d iterations) is raced against the "
-                     "plain random start (6 iterations); a seed whose summed energy is the larger is rejected "
-                     "and the pair's result is plain@6 exactly" % args.learned_iters,
+                     "plain random start with one iteration more (%d); a seed whose summed energy is the larger "
+                     "is rejected and the pair's result is plain@6 exactly" % (args.learned_iters,
+                                                                                min(args.learned_iters + 1, 6)),
              "pairs": int(gs.shape[0]), "rejected": rejected,
              "firing_rate": round(rejected / max(int(gs.shape[0]), 1), 4),
              "seeded_over_plain_coarse_energy_mean": round(float((gs[:, 0].double() / gs[:, 1].double()).mean()), 4),

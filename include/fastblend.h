@@ -61,9 +61,8 @@ typedef enum {
 #define FB_NO_AUTOTUNE 0x2u  /* use the default tile shape, skip the autotuner    */
 #define FB_LEARNED_SEED 0x4u /* seed the coarsest level with the proposal network */
 /* With FB_LEARNED_SEED, a seeded pair of a plain (Eq. 1) pass is raced, at
- * its coarsest level, against the plain random start with plain_iters
- * iterations (see fb_params and fb_guard_read); FB_NO_GUARD takes every seed
- * as it is. */
+ * its coarsest level, against the plain random start (see fb_guard_read);
+ * FB_NO_GUARD takes every seed as it is. */
 #define FB_NO_GUARD 0x100u
 /* FB_USE_GRAPH: when capturing the launch sequence fails (begin, end or
  * instantiation of the capture), the call runs the same launches eagerly and
@@ -127,8 +126,8 @@ typedef struct {
     uint64_t seed;         /* key of the Philox4x32-10 draws                   */
     int32_t alpha16;       /* FB_STYLE_LOSS: guide weight alpha = alpha16 / 16 */
     int32_t plain_iters;   /* FB_LEARNED_SEED: iterations per level of the     */
-                           /* plain run a seed is raced against and falls back */
-                           /* to; 0 selects 6; 0 <= plain_iters <= 65534       */
+                           /* plain run a rejected seed falls back to; 0       */
+                           /* selects 6; 0 <= plain_iters <= 65534             */
 } fb_params;
 
 typedef struct fb_ctx fb_ctx;
@@ -381,10 +380,11 @@ fb_status fb_unet_train_step(fb_ctx *ctx, const float *pair6, const float *targe
  * pair of a plain (Eq. 1) pass that starts from offsets -- predicted by the
  * network or given in its descriptor -- is raced at its coarsest level: the
  * seeded start with params->iters iterations against the random start of
- * Alg. 1 with plain_iters iterations.  If the seeded level's summed energy
- * is the larger, the seed is rejected and the pair's result is the plain
- * run exactly (random start, plain_iters iterations at every level);
- * otherwise the seeded run's.  The launch sequence does not depend on the
+ * Alg. 1 with one iteration more, min(iters + 1, plain_iters): a seed must
+ * be worth at least an iteration.  If the seeded level's summed energy is
+ * the larger, the seed is rejected and the pair's result is the plain run
+ * exactly (random start, plain_iters iterations at every level); otherwise
+ * the seeded run's.  The launch sequence does not depend on the
  * outcome (graph replay is unaffected).  Passes under FB_STYLE_LOSS,
  * FB_TRACKING or FB_ALIGN, and the Eq. 8 pass of FB_ACCURATE_BLEND, take
  * seeds unguarded.

@@ -231,10 +231,10 @@ def patchmatch_raced(S, T, p: int, levels: int, iters: int, plain_iters: int, se
                      seed_offsets):
     """Seeded NNF(S, T) under the guard of a seeded run: at the coarsest level
     the seeded start with `iters` iterations races the random start with
-    `plain_iters` iterations; if the seeded level's summed energy is the
-    larger, the whole result is the plain run (plain_iters iterations per
-    level), else the seeded run.  Returns (F, E, rejected, (seeded sum,
-    plain sum))."""
+    min(iters + 1, plain_iters) iterations; if the seeded level's summed
+    energy is the larger, the whole result is the plain run (plain_iters
+    iterations per level), else the seeded run.  Returns (F, E, rejected,
+    (seeded sum, plain sum))."""
     S, T = _img(S), _img(T)
     h, w = S.shape[:2]
     F = np.zeros((h, w, 2), np.int32)

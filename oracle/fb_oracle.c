@@ -274,11 +274,13 @@ int fbo_patchmatch(const uint8_t *S0, const uint8_t *T0, int h, int w, int p, in
 /* Guard of a seeded run (a project addition: the learned proposal replaces  */
 /* Alg. 1's random initialisation, and Alg. 1 itself has no such rule).  At  */
 /* the coarsest level the seeded start followed by `iters` iterations races  */
-/* the random start followed by `plain_iters` iterations; sums[0], sums[1]   */
-/* are the two levels' summed energies (64-bit).  If the seeded sum is the   */
-/* larger, the seed is rejected and the result is the plain run (random      */
-/* start, plain_iters iterations at every level); otherwise it is the seeded */
-/* run (iters iterations at every level).  *rejected: 1 if plain was taken.  */
+/* the random start followed by one more iteration, race = min(iters + 1,    */
+/* plain_iters) iterations: a seed must be worth at least an iteration.      */
+/* sums[0], sums[1] are the two levels' summed energies (64-bit).  If the    */
+/* seeded sum is the larger, the seed is rejected and the result is the      */
+/* plain run (random start, plain_iters iterations at every level);          */
+/* otherwise it is the seeded run (iters iterations at every level).         */
+/* *rejected: 1 if plain was taken.                                          */
 /* ------------------------------------------------------------------------ */
 static uint64_t sum_u32(const uint32_t *E, size_t n)
 {
@@ -335,8 +337,9 @@ int fbo_patchmatch_raced(const uint8_t *S0, const uint8_t *T0, int h, int w, int
 {
     if (!seed_off || iters < 0 || plain_iters < 0 || levels < 1 || levels > 16 || h < 1 || w < 1 || p < 0)
         return FBO_E_INVALID;
+    const int race = iters + 1 < plain_iters ? iters + 1 : plain_iters;
     int st = coarse_energy(S0, T0, h, w, p, levels, iters, seed, pair_id, seed_off, &sums[0]);
-    if (st == FBO_OK) st = coarse_energy(S0, T0, h, w, p, levels, plain_iters, seed, pair_id, NULL, &sums[1]);
+    if (st == FBO_OK) st = coarse_energy(S0, T0, h, w, p, levels, race, seed, pair_id, NULL, &sums[1]);
     if (st != FBO_OK) return st;
     *rejected = sums[0] > sums[1];
     if (*rejected) return patchmatch_impl(S0, T0, h, w, p, levels, plain_iters, seed, pair_id, NULL, F, E);

@@ -100,8 +100,8 @@ struct PMJob {
     // larger.  Iteration launches: guard_when 1 runs the job only for a
     // rejected seed, 2 only for a kept one, 0 always.  k_energy_sum: guard
     // is the sum the job's energies e_in are added to.  k_guard_select: for
-    // a rejected seed, (f_alt, e_alt) is copied over (f_out, e_out) and
-    // *guard_any is set.
+    // a rejected seed, (f_alt, e_alt) is copied over (f_out, e_out).
+    // k_guard_decide: a rejected seed sets *guard_any.
     uint64_t *guard;
     uint64_t *guard_any;       // nonzero once any seed of the call was rejected
     const uint32_t *f_alt;
@@ -183,6 +183,8 @@ hipError_t launch_energy_sum(const PMJob *jobs, int n_jobs, int total_tiles, int
                              TileCfg cfg, hipStream_t s);
 hipError_t launch_guard_select(const PMJob *jobs, int n_jobs, int total_tiles, int uniform_tiles,
                                TileCfg cfg, hipStream_t s);
+// one thread per raced pair: sets *guard_any when the pair's seed is rejected
+hipError_t launch_guard_decide(const PMJob *jobs, int n_jobs, hipStream_t s);
 
 hipError_t launch_remap_sum(const RemapFrame *frames, int n_frames, const RemapTerm *terms,
                             int h, int w, int pitch, int p, hipStream_t s);

@@ -528,6 +528,7 @@ k_pm_iter_guarded(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, i
     __shared__ uint32_t s_f[(TH + 2) * (TW + 2)];
     extern __shared__ u32x4 s_btab4[];
     // the launch's jobs all run only for a rejected seed: none was rejected
+    // (the word is set by k_guard_decide before any such launch)
     if (jobs[0].guard_when == 1 && *jobs[0].guard_any == 0) return;
     for (int t = (int)blockIdx.x; t < total_tiles; t += (int)gridDim.x) {
         const PMJob &J = jobs[find_job(jobs, n_jobs, uniform_tiles, t)];
@@ -649,7 +650,16 @@ k_guard_select(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int 
     const int v = tc.r * J.w + tc.c;
     J.f_out[v] = J.f_alt[v];
     J.e_out[v] = J.e_alt[v];
-    if (v == 0) *J.guard_any = 1;
+}
+
+// The race's outcome of every raced pair: a rejected seed sets the call's
+// any-rejected word (launches that only rejected seeds need skip at once
+// while it is 0).
+__global__ void __launch_bounds__(64) k_guard_decide(const PMJob *__restrict__ jobs, int n) {
+    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= n) return;
+    const PMJob &J = jobs[k];
+    if (J.guard[0] > J.guard[1]) *J.guard_any = 1;
 }
 
 // int32 [h][w][2] field -> packed; entries are clamped into the image so a
@@ -777,6 +787,12 @@ hipError_t launch_guard_select(const PMJob *jobs, int n_jobs, int total_tiles, i
                        n_jobs, total_tiles, uniform_tiles)
     FB_TILE_SWITCH(cfg, FB_GSEL)
 #undef FB_GSEL
+    return hipGetLastError();
+}
+
+hipError_t launch_guard_decide(const PMJob *jobs, int n_jobs, hipStream_t s) {
+    if (n_jobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_guard_decide, dim3((n_jobs + 63) / 64), dim3(64), 0, s, jobs, n_jobs);
     return hipGetLastError();
 }
 

@@ -153,6 +153,18 @@ void add_pm_launch(Plan &P, LaunchKind kind, std::vector<PMJob> jobs, TileCfg cf
     }
 }
 
+// The guard's decision: one thread per raced pair sets the call's any-rejected
+// word when the pair's seeded sum exceeds its plain sum.
+void add_guard_decide(Plan &P, const std::vector<PMJob> &dec) {
+    if (dec.empty()) return;
+    const size_t off = table_append(P, dec.data(), dec.size());
+    const int n = (int)dec.size();
+    sig_add(P, "gdec", (long long)off, n);
+    P.ops.push_back({FB_KERNEL_OTHER, [=](hipStream_t s, const uint8_t *tab) {
+        return launch_guard_decide(reinterpret_cast<const PMJob *>(tab + off), n, s);
+    }});
+}
+
 // Frames of a call: n uint8 RGB frames, each with its own pointer and row
 // stride (the contiguous calls pass [n][h][w][3]).
 typedef std::vector<FrameRef> Frames;
@@ -217,9 +229,10 @@ struct PairSpec {
 
 // The guard of the seeded pairs of one call: each pair with guard_slot >= 0
 // races its seeded coarsest level (iters iterations) against the plain random
-// start (plain_iters iterations); sums[2 g], sums[2 g + 1] receive the two
-// summed energies of guarded pair g.  A rejected pair continues as the plain
-// run (plain_iters iterations at every level).
+// start (min(iters + 1, plain_iters) iterations); sums[2 g], sums[2 g + 1]
+// receive the two summed energies of guarded pair g, and sums[2 n] is set
+// when any seed is rejected.  A rejected pair continues as the plain run
+// (plain_iters iterations at every level).
 struct GuardPlan {
     int plain_iters = 0;
     uint64_t *sums = nullptr;
@@ -278,11 +291,12 @@ std::string tune_key_of(const std::vector<PairSpec> &pairs, int p) {
 // Tracking (track) and the pairwise alignment loss (align, pairs with a
 // partner) read the fields the other pairs start the same iteration from.
 // With a guard (plain passes only), every guarded pair also runs the plain
-// random start at its coarsest level in its own buffers; the two levels'
-// energies are summed; a pair whose seed lost takes the plain field and runs
-// plain_iters iterations at the finer levels (launch jobs that only run for
-// a rejected or only for a kept seed), so the launch sequence is the same
-// whatever the outcome.
+// random start at its coarsest level in its own buffers; once both runs of
+// the race are done the two levels' energies are summed; the plain run's
+// later iterations there, and plain_iters iterations at the finer levels,
+// run only for a rejected seed, which then takes the plain field (launch
+// jobs that only run for a rejected or only for a kept seed), so the launch
+// sequence is the same whatever the outcome.
 void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, uint64_t seed,
                      TileCfg cfg, bool style = false, int alpha16 = 0, bool fixed_target = false,
                      bool track = false, bool align = false, const GuardPlan *guard = nullptr) {
@@ -291,6 +305,10 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
     const bool guarded = guard && guard->n > 0;
     const int plain_iters = guarded ? guard->plain_iters : iters;
     const int it_common = std::min(iters, plain_iters), it_all = std::max(iters, plain_iters);
+    // the race: the plain start gets one iteration more than the seed; the
+    // decision is taken once both runs of the race are done, and the plain
+    // run's remaining coarsest-level iterations run only for a rejected seed
+    const int race_iters = std::min(iters + 1, plain_iters), it_dec = std::max(iters, race_iters);
     if (guarded) {
         uint64_t *sums = guard->sums;
         const long n4 = 4L * guard->n + 2;  // two uint64 per pair and the any-rejected word, cleared as floats
@@ -303,11 +321,12 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
     for (int t = 0; t < kmax; ++t) {
         const int l = kmax - 1 - t;
         std::vector<size_t> active;
-        bool any_guard = false;
+        bool any_guard = false, any_race = false;
         for (size_t k = 0; k < pairs.size(); ++k)
             if (pairs[k].L.levels > l) {
                 active.push_back(k);
                 any_guard |= pairs[k].guard_slot >= 0;
+                any_race |= pairs[k].guard_slot >= 0 && l == pairs[k].L.levels - 1;
             }
         if (active.empty()) continue;
         auto gsum = [&](const PairSpec &ps) { return guard->sums + 2 * ps.guard_slot; };
@@ -344,7 +363,31 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
         }
         add_pm_launch(P, kLaunchStart, js, cfg, p, seed, 0);
         const int its = any_guard ? it_all : iters;
+        // the race's outcome for the pairs at their coarsest level: both
+        // summed energies, then the any-rejected word
+        bool decided = false;
+        auto decide = [&]() {
+            std::vector<PMJob> sums, dec;
+            for (size_t k : active) {
+                PairSpec &ps = pairs[k];
+                if (ps.guard_slot < 0 || l != ps.L.levels - 1) continue;
+                PMJob a = job_geom(ps, l), b = job_geom(ps, l), d = job_geom(ps, l);
+                a.e_in = ps.e[cur[k]];
+                a.guard = gsum(ps);
+                b.e_in = ps.re[rcur[k]];
+                b.guard = gsum(ps) + 1;
+                d.guard = gsum(ps);
+                d.guard_any = gany;
+                sums.push_back(a);
+                sums.push_back(b);
+                dec.push_back(d);
+            }
+            add_pm_launch(P, kLaunchEnergySum, sums, cfg, p, seed, 0);
+            add_guard_decide(P, dec);
+            decided = true;
+        };
         for (int it = 0; it < its; ++it) {
+            if (any_race && it == it_dec) decide();
             if (style && !fixed_target) {
                 js.clear();
                 for (size_t k : active) {
@@ -374,6 +417,11 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
                             r.e_in = ps.re[rcur[k]];
                             r.f_out = ps.rf[rcur[k] ^ 1];
                             r.e_out = ps.re[rcur[k] ^ 1];
+                            if (it >= race_iters) {  // past the race: only a rejected seed needs it
+                                r.guard = gsum(ps);
+                                r.guard_any = gany;
+                                r.guard_when = 1;
+                            }
                             rcur[k] ^= 1;
                             js_plain.push_back(r);
                         }
@@ -437,10 +485,10 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
             add_pm_launch(P, kLaunchIter, js_plain, cfg, p, seed, it, tmode);
         }
         if (!any_guard) continue;
-        // the race's outcome: the two sums at a pair's coarsest level; then a
-        // rejected pair's plain field replaces the seeded one wherever the two
-        // runs ended in different buffers
-        std::vector<PMJob> sums, sel;
+        if (any_race && !decided) decide();
+        // a rejected pair's plain field replaces the seeded one wherever the
+        // two runs ended in different buffers
+        std::vector<PMJob> sel;
         for (size_t k : active) {
             PairSpec &ps = pairs[k];
             if (ps.guard_slot < 0) continue;
@@ -448,13 +496,6 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
             j.guard = gsum(ps);
             j.guard_any = gany;
             if (l == ps.L.levels - 1) {
-                PMJob a = job_geom(ps, l), b = job_geom(ps, l);
-                a.e_in = ps.e[cur[k]];
-                a.guard = gsum(ps);
-                b.e_in = ps.re[rcur[k]];
-                b.guard = gsum(ps) + 1;
-                sums.push_back(a);
-                sums.push_back(b);
                 j.f_alt = ps.rf[rcur[k]];
                 j.e_alt = ps.re[rcur[k]];
             } else {
@@ -467,7 +508,6 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
             rcur[k] = cur[k];
             sel.push_back(j);
         }
-        add_pm_launch(P, kLaunchEnergySum, sums, cfg, p, seed, 0);
         add_pm_launch(P, kLaunchGuardSelect, sel, cfg, p, seed, 0);
     }
     std::vector<PMJob> ex;

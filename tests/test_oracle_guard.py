@@ -2,9 +2,10 @@
 the learned seed; the paper's Alg. 1 starts from random fields).
 
 The rule: at the coarsest level the seeded start followed by `iters`
-iterations races the random start followed by `plain_iters` iterations.  If
-the seeded level's summed energy is the larger, the seed is rejected and the
-whole result is the plain run; otherwise it is the seeded run.  The guard is
+iterations races the random start followed by one more iteration,
+min(iters + 1, plain_iters).  If the seeded level's summed energy is the
+larger, the seed is rejected and the whole result is the plain run
+(plain_iters iterations at every level); otherwise it is the seeded run.  The guard is
 checked against that rule restated here on top of the pinned init and single
 iteration, and by its behaviour: a seed that is the pair's true motion is
 kept, a random seed is rejected, and a rejected run is the plain run exactly.
@@ -47,7 +48,7 @@ def test_guard_follows_its_rule(orc, levels, iters, plain_iters, amp):
     off = np.random.default_rng(amp).integers(-amp, amp + 1, (hc, wc, 2)).astype(np.int32)
     F, E, rej, sums = orc.patchmatch_raced(S, T, 2, levels, iters, plain_iters, 77, 5, off)
     ss = _coarse_sum(orc, S, T, 2, levels, iters, 77, 5, off)
-    sp = _coarse_sum(orc, S, T, 2, levels, plain_iters, 77, 5, None)
+    sp = _coarse_sum(orc, S, T, 2, levels, min(iters + 1, plain_iters), 77, 5, None)
     assert sums == (ss, sp)
     assert rej == (ss > sp)
     if rej:
@@ -92,9 +93,10 @@ def test_guard_rejects_a_random_seed_for_the_plain_run(orc):
 
 def test_guard_with_equal_sums_keeps_the_seed(orc):
     """Ties go to the seed (strict '>'): seeding with the plain run's own
-    coarsest-level field and running as many iterations reproduces the plain
-    coarse level exactly (the random start is only the draw at the start), so
-    both sums are equal."""
+    coarsest-level field and running as many iterations as the race gives the
+    plain start (plain_iters = iters, so the race runs iters) reproduces the
+    plain coarse level exactly (the random start is only the draw at the
+    start), so both sums are equal."""
     S, T = _pair()
     levels, it = 2, 3
     l = levels - 1
