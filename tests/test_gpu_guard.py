@@ -160,3 +160,34 @@ def test_guarded_graph_replay_matches_eager(ctx):
             side.synchronize()
             for (a, ea), (b, eb) in zip(got, eager):
                 assert torch.equal(a, b) and torch.equal(ea, eb), rep
+
+
+def test_guarded_mixed_sizes_and_levels_match_oracle(ctx):
+    """Pairs of different sizes and level counts in one batch, so that their
+    races are decided at different passes (a 3-level pair's coarsest pass
+    comes before a 2-level pair's): every pair equals the oracle's guarded
+    run, rejected and kept alike."""
+    seed, iters, plain = 0xFB5EED55, 2, 5
+    specs = [(48, 64, 2, "random", 21), (96, 128, 3, "converged", 22), (96, 128, 3, "random", 23),
+             (48, 64, 2, "converged", 24), (72, 100, 3, "zero", 25)]
+    descs, refs = [], []
+    for k, (h, w, levels, kind, vs) in enumerate(specs):
+        v = _video(2, h, w, vs)
+        g = torch.from_numpy(v).cuda()
+        hc, wc = fbm.level_size(h, w, levels - 1)
+        if kind == "converged":
+            off = _converged_seed(v[0], v[1], levels, plain, seed, k)
+        else:
+            off = _seeds(kind, hc, wc, np.random.default_rng(k))
+        descs.append(dict(src_pyr=ctx.fb_build_pyramid(g[0], levels), tgt_pyr=ctx.fb_build_pyramid(g[1], levels),
+                          h=h, w=w, levels=levels, pair_id=k, seed_offsets=torch.from_numpy(off).cuda()))
+        refs.append(oracle.patchmatch_raced(v[0], v[1], 2, levels, iters, plain, seed, k, off))
+    outs = ctx.fb_patchmatch_batch(descs, fbm.make_params(2, 3, iters, seed, fbm.FB_LEARNED_SEED, plain_iters=plain))
+    sums = ctx.fb_guard_read()
+    rejected = []
+    for k, ((nnf, en), (F, E, rej, (ss, sp))) in enumerate(zip(outs, refs)):
+        assert (int(sums[k, 0]), int(sums[k, 1])) == (ss, sp), k
+        assert np.array_equal(nnf.cpu().numpy(), F), k
+        assert np.array_equal(fbm.energy_u32(en).cpu().numpy(), E.astype(np.int64)), k
+        rejected.append(rej)
+    assert rejected[0] and rejected[2] and not rejected[1] and not rejected[3]
