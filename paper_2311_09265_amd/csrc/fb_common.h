@@ -212,10 +212,12 @@ constexpr int kConvHaloMax = 1024; // input pixels (with border) one workgroup m
 // whether the LDS kernel takes images of this shape (else a single-tensor
 // input goes to the direct kernel and a split input is refused)
 bool conv_lds_fits(int B, int H, int W);
-// out: [px][ostride], channels [0, ostride) of the cout computed ones
+// out: [px][ostride], channels [0, ostride) of the cout computed ones;
+// pool_out (optional, bf16 output only, ostride == cout): also the 2x2
+// average pooling of out, [H/2][W/2][cout]
 hipError_t launch_conv3x3_in(const ConvIn &X, int B, int H, int W, int cin, const uint16_t *wt,
                              const float *bias, void *out, int cout, int ostride, bool relu, bool out_f32,
-                             hipStream_t s);
+                             hipStream_t s, uint16_t *pool_out = nullptr);
 hipError_t launch_conv3x3(const uint16_t *in, int B, int H, int W, int cin, const uint16_t *wt,
                           const float *bias, void *out, int cout, int ostride, bool relu, bool out_f32,
                           hipStream_t s);

@@ -36,6 +36,13 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// two floats to packed bf16 (low half: a), rounded to nearest even like f32_to_bf16
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    typedef float f32x2_t __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+    const bf16x2_t h = __builtin_convertvector((f32x2_t){a, b}, bf16x2_t);
+    return __builtin_bit_cast(uint32_t, h);
+}
 
 __device__ __forceinline__ bf16x4 load_bf16x4(const uint16_t *p) {
     const uint2 u = *reinterpret_cast<const uint2 *>(p);
@@ -132,19 +139,34 @@ k_conv3x3(const uint16_t *__restrict__ in, int B, int H, int W, int cin,
 // ---------------------------------------------------------------------------
 // Forward / data-gradient convolution on v_mfma_f32_32x32x16_bf16, staged
 // through LDS.  A workgroup takes kConvTile consecutive pixels of one image
-// (4 waves x 2 row blocks of 32 pixels: M) and 32 NBW output channels (N).
+// (4 waves x 2 blocks of 32 pixels) and 32 NBW output channels; a matrix-core
+// instruction multiplies 32 output channels' weights (A, M) by 32 pixels (B,
+// N), so each lane ends up with 16 channels of one pixel.
 // For every 16-channel slice of the input (K) it stages in LDS the input rows
 // the tile touches, with a zero border (the halo), and the slice's weights of
-// all 9 taps; every tap then reads its A and B fragments from LDS as
-// contiguous 1 KB blocks, so each input element is fetched from memory once
-// per slice instead of once per tap.  Input channels [0, ca) may come from a
-// half-resolution tensor upsampled 2x (nearest): the decoder's
-// upsample-and-concatenate is read in place instead of materialised.
+// all 9 taps; every tap then reads its A and B fragments from LDS, so each
+// input element is fetched from memory once per slice instead of once per
+// tap.  Input channels [0, ca) may come from a half-resolution tensor
+// upsampled 2x (nearest): the decoder's upsample-and-concatenate is read in
+// place instead of materialised.
+//
+// LDS holds each staged 16-channel row as two planes of 8 channels (16 B), so
+// the 32 lanes that read one fragment half read 32 consecutive 16-byte words
+// (no bank conflicts).  The results go back through LDS too: each 32-channel
+// block of the tile is written there as bf16 (8 bytes per lane and store) and
+// copied out with 16-byte stores; with POOL the same copy also writes the
+// tile's 2x2 average pooling (the tile then covers whole row pairs).  Tiles
+// are assigned XCD by XCD (xcd_item), so the halo rows two neighbouring tiles
+// share are read from memory once.
 //
 // 32x32x16 bf16 lane layout (wave64):
 //   A (32 x 16): lane l holds A[l % 32][8 (l / 32) + j], j = 0..7
 //   B (16 x 32): lane l holds B[8 (l / 32) + j][l % 32]
 //   D (32 x 32): lane l holds D[8 (i / 4) + 4 (l / 32) + i % 4][l % 32], i = 0..15
+// With A = weights [output channel][input channel] and B = pixels [input
+// channel][pixel], the two operands are the same 16-byte LDS words a lane
+// would load for the pixel-major product, and each output value is the same
+// sum of the same products.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -158,36 +180,64 @@ __device__ __forceinline__ bf16x8 as_bf16x8(uint4 u) {
     return c.b;
 }
 
-template <int NBW, int HE, bool RELU>
+// Consecutive workgroups are dispatched round-robin over the 8 XCDs.  Give
+// each XCD one contiguous range of the launch's work items, so tiles that
+// share halo rows run on one XCD close in time and the shared rows are read
+// from its L2 instead of from memory twice.  A bijection on [0, total).
+__device__ __forceinline__ int xcd_item(int b, int total) {
+    const int q = total >> 3, r = total & 7;
+    const int x = b & 7, s = b >> 3;
+    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+}
+
+// floor(n / d) for 0 <= n < 2^24 and 0 < d < 2^24: a float estimate from the
+// reciprocal, corrected by one step either way (the estimate is within one)
+__device__ __forceinline__ int div_small(int n, int d, float rd) {
+    int q = (int)((float)n * rd);
+    const int r = n - q * d;
+    q += (r >= d) - (r < 0);
+    return q;
+}
+
+// bf16 pixel stride of the output tile in LDS: 16 bytes of padding put the
+// two pixels one store instruction writes (4 apart) on different banks
+constexpr int kConvOutStride = 32 + 8;
+
+template <int NBW, int HE, bool RELU, bool POOL>
 __global__ void __launch_bounds__(256)
 k_conv3x3_lds(ConvIn X, int H, int W, int cin, int tiles_per_img, const uint16_t *__restrict__ wt,
-              const float *__restrict__ bias, uint16_t *__restrict__ out, int cout, int ostride) {
+              const float *__restrict__ bias, uint16_t *__restrict__ out, int cout,
+              uint16_t *__restrict__ pool_out) {
     // HE: halo pixels staged per thread (the halo has at most 256 HE pixels)
     constexpr int NT = 32 * NBW;
     constexpr int WE = (9 * NT + 255) / 256;  // weight rows staged per thread
     extern __shared__ uint4 lds[];
-    uint4 *s_w = lds;               // [9][NT][2]: 16 channels of one weight row
-    uint4 *s_in = lds + 9 * NT * 2; // [halo pixels][2]: 16 channels of one pixel
+    uint4 *s_w = lds;               // [2][9][NT]: channel halves of one weight row
+    uint4 *s_in = lds + 9 * NT * 2; // [2][halo pixels]: channel halves of one pixel
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int img = blockIdx.x / tiles_per_img;
+    // work item: tile-major, the output-channel blocks of one tile adjacent
+    const int item = xcd_item((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
+    const int tile = item / (int)gridDim.y, cblk0 = item - tile * (int)gridDim.y;
+    const int img = tile / tiles_per_img;
     const int HW = H * W, WP = W + 2;
-    const int p0 = (blockIdx.x - img * tiles_per_img) * kConvTile;
+    const int p0 = (tile - img * tiles_per_img) * kConvTile;
     const int p1 = min(p0 + kConvTile, HW);
     const int ya = p0 / W - 1;                           // first halo row
     const int halo = ((p1 - 1) / W + 1 - ya + 1) * WP;  // <= 256 HE (checked by the host)
-    const int co0 = blockIdx.y * NT;
+    const int co0 = cblk0 * NT;
     const int half = lane >> 5;
     const int cb = cin - X.ca;
 
     // what this thread stages: halo pixels tid + 256 k (source pixel index in
     // a and in b, or -1 for the zero border) and weight rows tid + 256 k
+    const float rWP = 1.0f / (float)WP, rW = 1.0f / (float)W;
     int src_a[HE], src_b[HE];
 #pragma unroll
     for (int k = 0; k < HE; ++k) {
         const int i = tid + 256 * k;
         src_a[k] = src_b[k] = -1;
         if (i < halo) {
-            const int hy = i / WP, hx = i - hy * WP;
+            const int hy = div_small(i, WP, rWP), hx = i - hy * WP;
             const int y = ya + hy, x = hx - 1;
             if (y >= 0 && y < H && x >= 0 && x < W) {
                 src_b[k] = (img * H + y) * W + x;
@@ -232,7 +282,7 @@ k_conv3x3_lds(ConvIn X, int H, int W, int cin, int tiles_per_img, const uint16_t
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
         const int p = min(p0 + 64 * wave + 32 * mb + (lane & 31), p1 - 1);
-        const int y = p / W;
+        const int y = div_small(p, W, rW);
         hidx[mb] = (y - ya) * WP + (p - y * W) + 1;
     }
     f32x16 acc[2][NBW];
@@ -243,6 +293,8 @@ k_conv3x3_lds(ConvIn X, int H, int W, int cin, int tiles_per_img, const uint16_t
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[mb][nb][i] = 0.f;
 
+    const uint4 *a_plane = s_in + half * halo;
+    const uint4 *b_plane = s_w + half * 9 * NT;
     fetch(0);
     for (int c0 = 0; c0 < cin; c0 += 16) {
         __syncthreads();  // the previous slice's fragments have been read
@@ -250,16 +302,16 @@ k_conv3x3_lds(ConvIn X, int H, int W, int cin, int tiles_per_img, const uint16_t
         for (int k = 0; k < HE; ++k) {
             const int i = tid + 256 * k;
             if (i < halo) {
-                s_in[2 * i] = r_in[k][0];
-                s_in[2 * i + 1] = r_in[k][1];
+                s_in[i] = r_in[k][0];
+                s_in[halo + i] = r_in[k][1];
             }
         }
 #pragma unroll
         for (int k = 0; k < WE; ++k) {
             const int i = tid + 256 * k;
             if (i < 9 * NT) {
-                s_w[2 * i] = r_w[k][0];
-                s_w[2 * i + 1] = r_w[k][1];
+                s_w[i] = r_w[k][0];
+                s_w[9 * NT + i] = r_w[k][1];
             }
         }
         __syncthreads();
@@ -269,31 +321,97 @@ k_conv3x3_lds(ConvIn X, int H, int W, int cin, int tiles_per_img, const uint16_t
             const int toff = (tap / 3 - 1) * WP + (tap % 3 - 1);
             bf16x8 a[2], b[NBW];
 #pragma unroll
-            for (int mb = 0; mb < 2; ++mb) a[mb] = as_bf16x8(s_in[2 * (hidx[mb] + toff) + half]);
+            for (int mb = 0; mb < 2; ++mb) a[mb] = as_bf16x8(a_plane[hidx[mb] + toff]);
 #pragma unroll
-            for (int nb = 0; nb < NBW; ++nb) b[nb] = as_bf16x8(s_w[2 * (tap * NT + 32 * nb + (lane & 31)) + half]);
+            for (int nb = 0; nb < NBW; ++nb) b[nb] = as_bf16x8(b_plane[tap * NT + 32 * nb + (lane & 31)]);
 #pragma unroll
             for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
                 for (int nb = 0; nb < NBW; ++nb)
-                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mb], b[nb], acc[mb][nb], 0, 0, 0);
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[nb], a[mb], acc[mb][nb], 0, 0, 0);
         }
     }
+
+    // epilogue, one 32-channel block at a time: bias, ReLU, bf16 into the LDS
+    // tile [pixel][kConvOutStride], then 16-byte stores of whole pixels
+    uint16_t *s_o = reinterpret_cast<uint16_t *>(lds);
+    const int np = p1 - p0;
 #pragma unroll
     for (int nb = 0; nb < NBW; ++nb) {
-        const int co = co0 + 32 * nb + (lane & 31);
-        if (co >= ostride) continue;
-        const float bv = bias ? bias[co] : 0.f;
+        const int cblk = co0 + 32 * nb;
+        if (cblk >= cout) break;  // uniform
+        const int nch = min(32, cout - cblk) >> 3;  // 8-channel chunks of the block that exist
+        float bb[4][4];  // bias of the 16 channels this lane holds
 #pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
+        for (int g = 0; g < 4; ++g) {
+            const int c = cblk + 8 * g + 4 * half;
+            const float4 b4 = bias && c < cout ? *reinterpret_cast<const float4 *>(bias + c) : make_float4(0.f, 0.f, 0.f, 0.f);
+            bb[g][0] = b4.x;
+            bb[g][1] = b4.y;
+            bb[g][2] = b4.z;
+            bb[g][3] = b4.w;
+        }
+        __syncthreads();  // the fragments (or the previous block) have been read
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int p = p0 + 64 * wave + 32 * mb + 8 * (i >> 2) + 4 * half + (i & 3);
-                if (p >= p1) continue;
-                float v = acc[mb][nb][i] + bv;
-                if (RELU) v = fmaxf(v, 0.f);
-                out[((size_t)img * HW + p) * ostride + co] = f32_to_bf16(v);
+        for (int mb = 0; mb < 2; ++mb) {
+            const int pl = 64 * wave + 32 * mb + (lane & 31);
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                // channels cblk + 8 g + 4 half + j, j = 0..3, of pixel pl
+                const int c4 = 8 * g + 4 * half;
+                float v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    v[j] = acc[mb][nb][4 * g + j] + bb[g][j];
+                    if (RELU) v[j] = fmaxf(v[j], 0.f);
+                }
+                *reinterpret_cast<uint2 *>(s_o + pl * kConvOutStride + c4) =
+                    make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
             }
+        }
+        __syncthreads();
+        // 4 chunks of 8 channels per pixel, the block's 32 channels of 256 pixels
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = tid + 256 * k, pl = c >> 2, part = c & 3;
+            if (pl < np && part < nch)
+                *reinterpret_cast<uint4 *>(out + ((size_t)img * HW + p0 + pl) * cout + cblk + 8 * part) =
+                    *reinterpret_cast<const uint4 *>(s_o + pl * kConvOutStride + 8 * part);
+        }
+        if (POOL) {
+            // the tile is rows [p0 / W, p1 / W) of even count starting even:
+            // np / 4 pooled pixels x 4 chunks of 8 channels
+            const int Wo = W >> 1;
+            const int q = tid >> 2, part = tid & 3;
+            if (tid < np && part < nch) {
+                const int qy = q / Wo, qx = q - qy * Wo;
+                const int l00 = 2 * qy * W + 2 * qx;
+                const uint16_t *r0 = s_o + l00 * kConvOutStride + 8 * part;
+                const uint16_t *r1 = r0 + W * kConvOutStride;
+                const uint4 u00 = *reinterpret_cast<const uint4 *>(r0);
+                const uint4 u01 = *reinterpret_cast<const uint4 *>(r0 + kConvOutStride);
+                const uint4 u10 = *reinterpret_cast<const uint4 *>(r1);
+                const uint4 u11 = *reinterpret_cast<const uint4 *>(r1 + kConvOutStride);
+                const uint32_t *w00 = &u00.x, *w01 = &u01.x, *w10 = &u10.x, *w11 = &u11.x;
+                uint32_t o[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    uint32_t r = 0;
+#pragma unroll
+                    for (int h2 = 0; h2 < 2; ++h2) {
+                        const int sh = 16 * h2;
+                        // the sum in the order of the separate pooling kernel
+                        const float sum = bf16_to_f32((uint16_t)(w00[j] >> sh)) + bf16_to_f32((uint16_t)(w01[j] >> sh)) +
+                                          bf16_to_f32((uint16_t)(w10[j] >> sh)) + bf16_to_f32((uint16_t)(w11[j] >> sh));
+                        r |= (uint32_t)f32_to_bf16(0.25f * sum) << sh;
+                    }
+                    o[j] = r;
+                }
+                const int py = p0 / W / 2 + qy;
+                *reinterpret_cast<uint4 *>(pool_out + (((size_t)img * (H >> 1) + py) * Wo + qx) * cout + cblk +
+                                           8 * part) = make_uint4(o[0], o[1], o[2], o[3]);
+            }
+        }
     }
 }
 
@@ -302,23 +420,26 @@ k_conv3x3_lds(ConvIn X, int H, int W, int cin, int tiles_per_img, const uint16_t
 // fp32 out [px][2].  v_mfma_f32_16x16x32_bf16 covers all 32 input channels of
 // one tap for 16 pixels (M) and 16 output channels (N, the first 2 real), so
 // a tap is one matrix-core instruction per 16 pixels.  The tile's input rows
-// with a zero border are staged in LDS once (all 32 channels); the weights of
-// all taps stay in registers.
+// with a zero border are staged in LDS once (all 32 channels, as four planes
+// of 8 channels, so the 16 lanes of one fragment quarter read consecutive
+// 16-byte words); the weights of all taps stay in registers.
 //
 // 16x16x32 bf16 lane layout (wave64):
 //   A (16 x 32): lane l holds A[l % 16][8 (l / 16) + j], j = 0..7
 //   B (32 x 16): lane l holds B[8 (l / 16) + j][l % 16]
 //   D (16 x 16): lane l holds D[4 (l / 16) + j][l % 16], j = 0..3
 // ---------------------------------------------------------------------------
+template <int HE>  // halo pixels staged per thread (the halo has at most 256 HE pixels)
 __global__ void __launch_bounds__(256)
 k_head3x3(const uint16_t *__restrict__ in, int H, int W, int tiles_per_img, const uint16_t *__restrict__ wt,
           int cout_pad, const float *__restrict__ bias, float *__restrict__ out) {
-    constexpr int CIN = 32, HE = kConvHaloMax / 256;
-    extern __shared__ uint4 lds[];  // [halo pixels][4]: 32 channels of one pixel
+    constexpr int CIN = 32;
+    extern __shared__ uint4 lds[];  // [4][halo pixels]: the four 8-channel quarters of a pixel
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int img = blockIdx.x / tiles_per_img;
+    const int tile = xcd_item((int)blockIdx.x, (int)gridDim.x);
+    const int img = tile / tiles_per_img;
     const int HW = H * W, WP = W + 2;
-    const int p0 = (blockIdx.x - img * tiles_per_img) * kConvTile;
+    const int p0 = (tile - img * tiles_per_img) * kConvTile;
     const int p1 = min(p0 + kConvTile, HW);
     const int ya = p0 / W - 1;
     const int halo = ((p1 - 1) / W + 1 - ya + 1) * WP;
@@ -348,7 +469,7 @@ k_head3x3(const uint16_t *__restrict__ in, int H, int W, int tiles_per_img, cons
         const int i = tid + 256 * k;
         if (i < halo) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) lds[4 * i + j] = v[k][j];
+            for (int j = 0; j < 4; ++j) lds[j * halo + i] = v[k][j];
         }
     }
     __syncthreads();
@@ -368,7 +489,7 @@ k_head3x3(const uint16_t *__restrict__ in, int H, int W, int tiles_per_img, cons
         const int toff = (tap / 3 - 1) * WP + (tap % 3 - 1);
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb)
-            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(lds[4 * (hc[mb] + toff) + kq]), b[tap],
+            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(lds[kq * halo + hc[mb] + toff]), b[tap],
                                                               acc[mb], 0, 0, 0);
     }
     if (co < 2) {
@@ -764,8 +885,12 @@ hipError_t launch_head3x3(const uint16_t *in, int B, int H, int W, int cin, cons
     if (cin != 32 || cout_pad < 16 || halo > kConvHaloMax || (long)B * H * W >= (1L << 31))
         return hipErrorInvalidValue;
     const int tiles = (H * W + kConvTile - 1) / kConvTile;
-    hipLaunchKernelGGL(k_head3x3, dim3((unsigned)(B * tiles)), dim3(256), (size_t)halo * 4 * sizeof(uint4), s, in,
-                       H, W, tiles, wt, cout_pad, bias, out);
+    const int he = std::max(2, (halo + 255) / 256);
+    const dim3 grid((unsigned)(B * tiles));
+    const size_t lds = (size_t)halo * 4 * sizeof(uint4);
+    if (he == 2) hipLaunchKernelGGL(k_head3x3<2>, grid, dim3(256), lds, s, in, H, W, tiles, wt, cout_pad, bias, out);
+    else if (he == 3) hipLaunchKernelGGL(k_head3x3<3>, grid, dim3(256), lds, s, in, H, W, tiles, wt, cout_pad, bias, out);
+    else hipLaunchKernelGGL(k_head3x3<4>, grid, dim3(256), lds, s, in, H, W, tiles, wt, cout_pad, bias, out);
     return hipGetLastError();
 }
 
@@ -775,34 +900,48 @@ bool conv_lds_fits(int B, int H, int W) {
 
 hipError_t launch_conv3x3_in(const ConvIn &X, int B, int H, int W, int cin, const uint16_t *wt,
                              const float *bias, void *out, int cout, int ostride, bool relu, bool out_f32,
-                             hipStream_t s) {
+                             hipStream_t s, uint16_t *pool_out) {
     if (cin % 16 || cout % 16 || ostride < 1 || ostride > cout || X.ca % 16 || X.ca > cin || (X.ca < cin && !X.b) || (X.a_half && (H % 2 || W % 2)))
         return hipErrorInvalidValue;
+    if (pool_out && (out_f32 || ostride != cout || H % 2 || W % 2)) return hipErrorInvalidValue;
     const int nbw = cout <= 32 ? 1 : (cout <= 64 ? 2 : 3);
     const int halo = conv_halo_px(H, W);
-    const size_t lds = ((size_t)9 * 32 * nbw + halo) * 2 * sizeof(uint4);
-    if (!conv_lds_fits(B, H, W) || out_f32) {
-        // wide images (and fp32 output): the direct kernel, which needs the input in one tensor
+    // staged fragments, or the epilogue's output tile if that is larger
+    const size_t lds = std::max(((size_t)9 * 32 * nbw + halo) * 2 * sizeof(uint4),
+                                (size_t)kConvTile * kConvOutStride * sizeof(uint16_t));
+    if (!conv_lds_fits(B, H, W) || out_f32 || ostride != cout) {
+        // wide images, fp32 output or a partial channel range: the direct
+        // kernel, which needs the input in one tensor
         if (X.ca != cin || X.a_half) return hipErrorInvalidValue;
-        return launch_conv3x3(X.a, B, H, W, cin, wt, bias, out, cout, ostride, relu, out_f32, s);
+        hipError_t e = launch_conv3x3(X.a, B, H, W, cin, wt, bias, out, cout, ostride, relu, out_f32, s);
+        if (e != hipSuccess || !pool_out) return e;
+        return launch_pool2(static_cast<const uint16_t *>(out), B, H, W, cout, pool_out, s);
     }
+    // the pooling is fused when every tile covers whole row pairs
+    const bool fuse_pool = pool_out && kConvTile % (2 * W) == 0;
     const int tiles = (H * W + kConvTile - 1) / kConvTile;
     const int he = std::max(2, (halo + 255) / 256);
     dim3 grid((unsigned)(B * tiles), (unsigned)((cout + 32 * nbw - 1) / (32 * nbw)));
     uint16_t *o = static_cast<uint16_t *>(out);
-#define FB_CONVL(NB, HE)                                                                                        \
-    if (relu) hipLaunchKernelGGL((k_conv3x3_lds<NB, HE, true>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, o, cout, ostride); \
-    else hipLaunchKernelGGL((k_conv3x3_lds<NB, HE, false>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, o, cout, ostride);
-#define FB_CONVL_HE(NB) \
-    if (he == 2) { FB_CONVL(NB, 2) } else if (he == 3) { FB_CONVL(NB, 3) } else { FB_CONVL(NB, 4) }
-    switch (nbw) {
-    case 1: FB_CONVL_HE(1) break;
-    case 2: FB_CONVL_HE(2) break;
-    default: FB_CONVL_HE(3) break;
+    uint16_t *po = fuse_pool ? pool_out : nullptr;
+#define FB_CONVL(NB, HE, POOL)                                                                                        \
+    if (relu) hipLaunchKernelGGL((k_conv3x3_lds<NB, HE, true, POOL>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, o, cout, po); \
+    else hipLaunchKernelGGL((k_conv3x3_lds<NB, HE, false, POOL>), grid, dim3(256), lds, s, X, H, W, cin, tiles, wt, bias, o, cout, po);
+#define FB_CONVL_HE(NB, POOL) \
+    if (he == 2) { FB_CONVL(NB, 2, POOL) } else if (he == 3) { FB_CONVL(NB, 3, POOL) } else { FB_CONVL(NB, 4, POOL) }
+#define FB_CONVL_NB(POOL) \
+    switch (nbw) { \
+    case 1: FB_CONVL_HE(1, POOL) break; \
+    case 2: FB_CONVL_HE(2, POOL) break; \
+    default: FB_CONVL_HE(3, POOL) break; \
     }
+    if (fuse_pool) { FB_CONVL_NB(true) } else { FB_CONVL_NB(false) }
+#undef FB_CONVL_NB
 #undef FB_CONVL_HE
 #undef FB_CONVL
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !pool_out || fuse_pool) return e;
+    return launch_pool2(o, B, H, W, cout, pool_out, s);
 }
 
 hipError_t launch_conv3x3(const uint16_t *in, int B, int H, int W, int cin, const uint16_t *wt,

@@ -257,7 +257,8 @@ static bool upcat_input(int i, int *deep, int *skip) {
 }
 
 // keep_cat: the decoder's concatenated input is materialised anyway
-static hipError_t conv_fwd(UNet *u, int i, bool keep_cat, hipStream_t s) {
+// pool: also write the 2x2 average pooling of the output to that tensor
+static hipError_t conv_fwd(UNet *u, int i, bool keep_cat, hipStream_t s, int pool = -1) {
     const LayerDef &l = kLayers[i];
     const int sh = kTShift[kLIn[i]], H = u->H >> sh, W = u->W >> sh;
     const float *bias = u->w32 + u->w_off[i] + 9 * (size_t)l.cout * l.cin;
@@ -278,20 +279,17 @@ static hipError_t conv_fwd(UNet *u, int i, bool keep_cat, hipStream_t s) {
                                  true, s);
     }
     return launch_conv3x3_in(X, u->B, H, W, l.cin, u->w16 + u->w16_off[i], bias, out, l.cout, l.cout, l.relu, false,
-                             s);
+                             s, pool >= 0 ? u->act[pool] : nullptr);
 }
 
 hipError_t unet_forward(UNet *u, hipStream_t s, bool keep_cat) {
     const int B = u->B, H = u->H, W = u->W;
     FB_TRY(conv_fwd(u, 0, keep_cat, s));
-    FB_TRY(conv_fwd(u, 1, keep_cat, s));
-    FB_TRY(launch_pool2(u->act[E1], B, H, W, 32, u->act[P1], s));
+    FB_TRY(conv_fwd(u, 1, keep_cat, s, P1));
     FB_TRY(conv_fwd(u, 2, keep_cat, s));
-    FB_TRY(conv_fwd(u, 3, keep_cat, s));
-    FB_TRY(launch_pool2(u->act[E2], B, H / 2, W / 2, 48, u->act[P2], s));
+    FB_TRY(conv_fwd(u, 3, keep_cat, s, P2));
     FB_TRY(conv_fwd(u, 4, keep_cat, s));
-    FB_TRY(conv_fwd(u, 5, keep_cat, s));
-    FB_TRY(launch_pool2(u->act[E3], B, H / 4, W / 4, 96, u->act[P3], s));
+    FB_TRY(conv_fwd(u, 5, keep_cat, s, P3));
     FB_TRY(conv_fwd(u, 6, keep_cat, s));
     FB_TRY(conv_fwd(u, 7, keep_cat, s));
     if (keep_cat) FB_TRY(launch_upcat(u->act[BT], u->act[E3], B, H / 4, W / 4, 192, 96, u->act[C3], s));
