@@ -251,6 +251,11 @@ fb_status fb_patchmatch_level_noalloc(fb_ctx *ctx, const void *src_pyr, const vo
 /* ---------------------------------------------------------------------- */
 fb_status fb_remap(fb_ctx *ctx, const uint8_t *style, const int32_t *nnf, int32_t h, int32_t w,
                    int32_t patch_radius, float *out, void *stream);
+/* The same with the style frame's own row stride (see fb_frame above):     */
+/* row r of the style starts at style + r * row_stride_bytes, which must be */
+/* at least 3 w (else FB_E_INVALID).                                        */
+fb_status fb_remap_strided(fb_ctx *ctx, const uint8_t *style, int64_t row_stride_bytes, const int32_t *nnf,
+                           int32_t h, int32_t w, int32_t patch_radius, float *out, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* (4) Sliding-window blending, Eq. 2 (balanced mode, guide loss Eq. 1):    */

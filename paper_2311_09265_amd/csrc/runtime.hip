@@ -1584,10 +1584,16 @@ fb_status fb_patchmatch_level_noalloc(fb_ctx *ctx, const void *src_pyr, const vo
 
 fb_status fb_remap(fb_ctx *ctx, const uint8_t *style, const int32_t *nnf, int32_t h, int32_t w,
                    int32_t patch_radius, float *out, void *stream) {
+    return fb_remap_strided(ctx, style, (int64_t)w * 3, nnf, h, w, patch_radius, out, stream);
+}
+
+fb_status fb_remap_strided(fb_ctx *ctx, const uint8_t *style, int64_t row_stride_bytes, const int32_t *nnf,
+                           int32_t h, int32_t w, int32_t patch_radius, float *out, void *stream) {
     fb_status st = begin(ctx);
     if (st) return st;
     if (!style || !nnf || !out) return fail(FB_E_INVALID, "null pointer");
     if ((st = check_size(h, w))) return st;
+    if (row_stride_bytes < (int64_t)w * 3) return fail(FB_E_INVALID, "row_stride_bytes must be at least 3 w");
     if (!valid_p(patch_radius)) return fail(FB_E_UNSUPPORTED, "patch_radius must be in [1, 4]");
     const int p = patch_radius;
     int32_t pitch = 0;
@@ -1597,7 +1603,7 @@ fb_status fb_remap(fb_ctx *ctx, const uint8_t *style, const int32_t *nnf, int32_
     uint8_t *sty = static_cast<uint8_t *>(ctx->style.p);
     uint32_t *f = static_cast<uint32_t *>(ctx->fe.p);
     Plan P;
-    plan_style_pack(P, contiguous_frames(style, 1, h, w), h, w, p, sty, sbytes, pitch);
+    plan_style_pack(P, Frames{FrameRef{style, row_stride_bytes}}, h, w, p, sty, sbytes, pitch);
     sig_add(P, "f2p", (long long)(uintptr_t)nnf, h, w, (long long)(uintptr_t)f);
     P.ops.push_back({FB_KERNEL_OTHER, [=](hipStream_t s, const uint8_t *) {
         return launch_field_to_packed(nnf, f, h, w, s);

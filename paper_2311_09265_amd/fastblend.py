@@ -73,7 +73,7 @@ _EXPORTS = ["fb_create", "fb_destroy", "fb_last_error", "fb_alpha16_max", "fb_nu
             "fb_profile_read", "fb_unet_param_count", "fb_unet_forward_flops", "fb_unet_load", "fb_unet_save",
             "fb_unet_forward", "fb_unet_gradients", "fb_unet_train_step", "fb_unet_pair_input", "fb_guard_read", "fb_unet_save_state", "fb_unet_load_state",
             "fb_tuning_export", "fb_tuning_import", "fb_autotune_runs", "fb_graph_fallbacks",
-            "fb_build_pyramid_strided", "fb_blend_window_frames", "fb_interpolate_frames",
+            "fb_build_pyramid_strided", "fb_blend_window_frames", "fb_interpolate_frames", "fb_remap_strided",
             "fb_patchmatch_level_noalloc"]
 
 
@@ -117,6 +117,7 @@ def load_library(path: str = LIB_PATH):
         "fb_unet_save_state": (i32, [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]),
         "fb_tuning_export": (ctypes.c_int64, [vp, ctypes.c_char_p, ctypes.c_int64]),
         "fb_build_pyramid_strided": (i32, [vp, vp, i32, i32, ctypes.c_int64, i32, i32, vp, vp]),
+        "fb_remap_strided": (i32, [vp, vp, ctypes.c_int64, vp, i32, i32, i32, vp, vp]),
         "fb_blend_window_frames": (i32, [vp, ctypes.POINTER(fb_frame), ctypes.POINTER(fb_frame), i32, i32, i32, i32,
                                          P, vp, vp]),
         "fb_interpolate_frames": (i32, [vp, ctypes.POINTER(fb_frame), i32, i32, i32, vp, ctypes.POINTER(fb_frame), i32,
@@ -445,11 +446,18 @@ class Context:
 
     # ---- remap / blend / interpolate --------------------------------------
     def fb_remap(self, style: torch.Tensor, nnf: torch.Tensor, patch_radius: int = 2) -> torch.Tensor:
+        """style: uint8 [h][w][3] on the GPU, contiguous or with a row stride."""
         h, w = style.shape[:2]
         out = torch.empty((h, w, 3), dtype=torch.float32, device=style.device)
-        _check(load_library().fb_remap(self.handle, _dev(style, "style", torch.uint8, (h, w, 3)),
-                                       _dev(nnf, "nnf", torch.int32, (h, w, 2)), h, w, patch_radius,
-                                       _dev(out, "out"), _stream(style)), "fb_remap")
+        fr = _frames(style.unsqueeze(0), "style", 1, h, w)
+        if fr is None:
+            _check(load_library().fb_remap(self.handle, _dev(style, "style", torch.uint8, (h, w, 3)),
+                                           _dev(nnf, "nnf", torch.int32, (h, w, 2)), h, w, patch_radius,
+                                           _dev(out, "out"), _stream(style)), "fb_remap")
+        else:
+            _check(load_library().fb_remap_strided(self.handle, ctypes.c_void_p(fr[0].rgb), fr[0].row_stride_bytes,
+                                                   _dev(nnf, "nnf", torch.int32, (h, w, 2)), h, w, patch_radius,
+                                                   _dev(out, "out"), _stream(style)), "fb_remap_strided")
         return out
 
     def fb_blend_window(self, guides: torch.Tensor, styles: torch.Tensor, radius_M: int,

@@ -84,3 +84,32 @@ def test_frames_with_different_row_strides(ctx):
     assert L.fb_blend_window_frames(ctx.handle, bad, frames(s), N, h, w, M, ctypes.byref(prm),
                                     ctypes.c_void_p(out.data_ptr()), None) == -1
     assert b"row_stride_bytes" in L.fb_last_error()
+
+
+def test_remap_of_a_strided_style(ctx):
+    """fb_remap of a cropped style view (fb_remap_strided) equals fb_remap of
+    its contiguous copy bit for bit, through the binding and the C ABI with a
+    padded row stride; an undersized stride is refused."""
+    h, w = 37, 53
+    S = _canvas(1, h + 6, w + 11, 21)[0]
+    s = S[3:3 + h, 5:5 + w]
+    assert not s.is_contiguous()
+    rng = np.random.default_rng(22)
+    nnf = torch.from_numpy(np.stack([rng.integers(0, h, (h, w)), rng.integers(0, w, (h, w))], -1)
+                           .astype(np.int32)).cuda()
+    for p in (1, 2, 3):
+        assert torch.equal(ctx.fb_remap(s, nnf, p), ctx.fb_remap(s.contiguous(), nnf, p))
+    stride = 3 * w + 20
+    buf = torch.zeros((h, stride), dtype=torch.uint8, device="cuda")
+    buf[:, :3 * w] = s.reshape(h, 3 * w)
+    out = torch.empty((h, w, 3), dtype=torch.float32, device="cuda")
+    L = fbm.load_library()
+    torch.cuda.synchronize()
+    st = L.fb_remap_strided(ctx.handle, ctypes.c_void_p(buf.data_ptr()), stride, ctypes.c_void_p(nnf.data_ptr()),
+                            h, w, 2, ctypes.c_void_p(out.data_ptr()), None)
+    assert st == 0, L.fb_last_error()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ctx.fb_remap(s.contiguous(), nnf, 2))
+    assert L.fb_remap_strided(ctx.handle, ctypes.c_void_p(buf.data_ptr()), 3 * w - 1, ctypes.c_void_p(nnf.data_ptr()),
+                              h, w, 2, ctypes.c_void_p(out.data_ptr()), None) == -1
+    assert b"row_stride_bytes" in L.fb_last_error()
