@@ -139,6 +139,51 @@ def test_bad_network_falls_back_to_plain(ctx):
         assert torch.equal(fl, fp) and torch.equal(el, ep)
 
 
+def test_interpolation_with_learned_seeds(ctx):
+    """fb_interpolate under FB_LEARNED_SEED, on a still video (one frame plus
+    independent noise of +-4 per frame, so zero is the true motion).  Every
+    pair's two race sums equal the oracle's for the same seed field.  A
+    network that predicts a constant, wrong offset loses every race: the
+    frames equal plain interpolation with plain_iters iterations exactly.  A
+    network that predicts zero offsets keeps every seed: the guarded frames
+    equal the unguarded ones (FB_NO_GUARD) and differ from plain's."""
+    N, h, w, levels = 9, 48, 64, 2
+    keys = [0, 4, 8]
+    base = _video(1, h, w, 41)[0].astype(np.int32)
+    noise = np.random.default_rng(5).integers(-4, 5, (N, h, w, 3))
+    frames = np.clip(base[None] + noise, 0, 255).astype(np.uint8)
+    guides = torch.from_numpy(frames).cuda()
+    kst = torch.from_numpy(synth.sprite_video(len(keys), h, w, 43, n_sprites=2, side=(8, 20))).cuda()
+    # the pairs in the order the call plans them: frame, then left before right key
+    pairs = [(k, i) for i in range(N) if i not in keys
+             for k in (max(k for k in keys if k < i), min(k for k in keys if k > i))]
+    hc, wc = fbm.level_size(h, w, levels - 1)
+    seed = 0xFB5EED78
+
+    def oracle_sums(shift, plain_iters):
+        off = np.zeros((hc, wc, 2), np.int32)
+        off[..., 0], off[..., 1] = shift
+        return torch.tensor([list(oracle.patchmatch_raced(frames[k], frames[i], 2, levels, 2, plain_iters, seed,
+                                                          k * N + i, off)[3]) for k, i in pairs], dtype=torch.int64)
+
+    ctx.fb_unet_load(_bad_network((37, -29)).cuda())
+    out_l = ctx.fb_interpolate(guides, keys, kst, fbm.make_params(2, levels, 2, seed, fbm.FB_LEARNED_SEED,
+                                                                  plain_iters=5))
+    sums = ctx.fb_guard_read()
+    assert torch.equal(sums, oracle_sums((37, -29), 5))
+    assert bool((sums[:, 0] > sums[:, 1]).all()), sums
+    assert torch.equal(out_l, ctx.fb_interpolate(guides, keys, kst, fbm.make_params(2, levels, 5, seed)))
+    ctx.fb_unet_load(_bad_network((0, 0)).cuda())
+    out_g = ctx.fb_interpolate(guides, keys, kst, fbm.make_params(2, levels, 2, seed, fbm.FB_LEARNED_SEED))
+    sums = ctx.fb_guard_read()
+    assert torch.equal(sums, oracle_sums((0, 0), 6))
+    assert bool((sums[:, 0] <= sums[:, 1]).all()), sums
+    out_u = ctx.fb_interpolate(guides, keys, kst, fbm.make_params(2, levels, 2, seed,
+                                                                  fbm.FB_LEARNED_SEED | fbm.FB_NO_GUARD))
+    assert torch.equal(out_g, out_u)
+    assert not torch.equal(out_g, ctx.fb_interpolate(guides, keys, kst, fbm.make_params(2, levels, 2, seed)))
+
+
 def test_guarded_graph_replay_matches_eager(ctx):
     """The guarded launch sequence is fixed: a captured graph replays it with
     the same fields, whichever seeds lose."""
