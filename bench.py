@@ -572,6 +572,13 @@ def main():
 
     n_iter, iter_ms = prof["pm_iter"]
     iter_ms_step = iter_ms / args.steps
+    # the remap and window sum (Alg. 2, Eq. 2) against HBM: its compulsory
+    # bytes are every pair's field (4 bytes per pixel, packed) and every padded
+    # 4-byte style frame read once, and the fp32 RGB outputs written once
+    pitch = (w + 2 * p + 15) // 16 * 16
+    remap_bytes = len(pairs) * h * w * 4 + N * (h + 2 * p) * pitch * 4 + N * h * w * 12
+    remap_ms_step = prof["remap"][1] / args.steps
+    remap_gbs = remap_bytes / (remap_ms_step / 1e3) / 1e9 if remap_ms_step > 0 else 0.0
     traffic, traffic_info = iter_kernel_traffic()
     achieved = terms / (iter_ms_step / 1e3) / 1e12
     kernel_ms = {k: round(v[1] / args.steps, 3) for k, v in prof.items() if v[0]}
@@ -619,6 +626,11 @@ def main():
                                       if traffic is not None else traffic_info),
                      "work": "byte-terms of Eq. 1 (one per squared channel difference) per step: %d" % terms,
                      "avg_launch_ms": round(iter_ms / max(n_iter, 1), 4), "launches": n_iter},
+        "remap_roofline": {"bound": "hbm", "kernel": "k_remap_sum", "achieved": round(remap_gbs, 1),
+                           "peak": 8000.0, "unit": "GB/s", "frac": round(remap_gbs / 8000.0, 4),
+                           "work": "compulsory bytes per step: %d (fields, padded styles, fp32 outputs); the "
+                                   "kernel is bound by L1 gathers of (2p+1)^2 source pixels per remapped pixel"
+                                   % remap_bytes},
         "cpu_baseline": cpu,
         "learned": learned,
         "style_loss": style,
