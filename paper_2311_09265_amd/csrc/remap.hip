@@ -37,6 +37,12 @@ __device__ __forceinline__ T gload(const void *base, uint32_t byte_off) {
                                                           byte_off);
 }
 
+// a 16-byte float pixel of an h x w image: its byte offset needs 64 bits
+// once h * w reaches 2^28 (the 4-byte images stay below 2^31 bytes)
+__device__ __forceinline__ f32x4 gload_f4(const void *base, int pixel) {
+    return *((const __attribute__((address_space(1))) f32x4 *)base + (size_t)(uint32_t)pixel);
+}
+
 template <int P>
 __global__ void __launch_bounds__(kRTW *kRTH)
 k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__ terms, int h,
@@ -62,7 +68,7 @@ k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__
         if (T.f == nullptr) {
             if (active) {
                 if (flt) {
-                    const f32x4 x = gload<f32x4>(sp, 16u * (uint32_t)(r * w + c));
+                    const f32x4 x = gload_f4(sp, r * w + c);
                     a0 += T.weight * x.x;
                     a1 += T.weight * x.y;
                     a2 += T.weight * x.z;
@@ -97,7 +103,7 @@ k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__
                     const uint32_t q = srow[dc];
                     const int sr = min(max((int)(q >> 16) - dr, 0), h - 1);
                     const int sc = min(max((int)(q & 0xFFFFu) - dc, 0), w - 1);
-                    const f32x4 x = gload<f32x4>(sp, 16u * (uint32_t)(sr * w + sc));
+                    const f32x4 x = gload_f4(sp, sr * w + sc);
                     x0 += x.x;
                     x1 += x.y;
                     x2 += x.z;

@@ -64,3 +64,15 @@ def test_fast_mode_approximates_the_balanced_blend():
     bal = oracle.blend_window(g, s, 2, 2, 2, 3, 11)
     raw = s / 255.0
     assert np.abs(fast - bal).mean() < 0.5 * np.abs(raw - bal).mean()
+
+
+@pytest.mark.parametrize("M", [1, 2])
+def test_two_frames_equal_the_balanced_blend(M):
+    """With two frames every window is the whole video, and the tables and
+    queries of Eq. 6 reduce to each frame plus the other one remapped through
+    the NNF Eq. 2 uses: fast mode equals the balanced blend up to rounding."""
+    g = synth.sprite_video(2, 40, 56, 3, n_sprites=2, side=(8, 20))
+    s = synth.sprite_video(2, 40, 56, 4, n_sprites=2, side=(8, 20))
+    a = oracle.blend_window_fast(g, s, M, 2, 2, 3, 9)
+    b = oracle.blend_window(g, s, M, 2, 2, 3, 9)
+    assert np.abs(a - b).max() < 1e-12
