@@ -557,6 +557,14 @@ def main():
     if not args.no_pair64:
         pair64 = bench_pair64(ctx, fbm, args)
 
+    # the row-gather rate that bounds the iteration kernel, measured on level 0
+    # of frame 0's pyramid (1 MB, L2-resident like a pair's source level)
+    probe_pyr = ctx.fb_build_pyramid(g[0], 1, p)
+    torch.cuda.synchronize()
+    gather = {"divergent_rows_per_s": ctx.fb_gather_probe(probe_pyr, h, w, True),
+              "coherent_rows_per_s": ctx.fb_gather_probe(probe_pyr, h, w, False)}
+    del probe_pyr
+
     accurate = None
     if not args.no_accurate:
         accurate = bench_accurate(ctx, fbm, g, s, out, M, p, levels, iters, seed, args, N)
@@ -631,6 +639,14 @@ def main():
                            "work": "compulsory bytes per step: %d (fields, padded styles, fp32 outputs); the "
                                    "kernel is bound by L1 gathers of (2p+1)^2 source pixels per remapped pixel"
                                    % remap_bytes},
+        "gather_roof": {
+            "kernel": "k_gather_probe",
+            "divergent_rows_per_s": round(gather["divergent_rows_per_s"], 0),
+            "coherent_rows_per_s": round(gather["coherent_rows_per_s"], 0),
+            "note": "lane-rows per second: 5-pixel rows (a 16-byte and a 4-byte load each, folded with v_dot4) "
+                    "gathered from a 512x512 padded level by 2048 x 256 lanes, every lane at its own random "
+                    "position (random-search candidates) or each wave at 64 consecutive pixels (propagation "
+                    "candidates): the two ends of the gather rate that bounds k_pm_iter"},
         "cpu_baseline": cpu,
         "learned": learned,
         "style_loss": style,

@@ -337,6 +337,17 @@ typedef struct {
 } fb_profile;
 
 int64_t fb_graph_fallbacks(fb_ctx *ctx);
+/* Measurement (no part of the method): the gather rate of patch rows that
+ * bounds the PatchMatch iteration.  2048 x 256 lanes each fetch rows_per_lane
+ * 5-pixel rows (one 16-byte and one 4-byte load, p = 2 only) from level 0 of
+ * the pyramid pyr (from fb_build_pyramid with this h, w, p), with every lane
+ * at its own random position (divergent != 0, like random-search candidates)
+ * or the 64 lanes of a wave at consecutive pixels (like propagation
+ * candidates), and fold each row into a v_dot4 sum.  Times one launch after
+ * a warm-up with HIP events on `stream` and waits for it; *rows_per_s
+ * (host) receives lane-rows per second. */
+fb_status fb_gather_probe(fb_ctx *ctx, const void *pyr, int32_t h, int32_t w, int32_t patch_radius, int32_t divergent,
+                          int32_t rows_per_lane, double *rows_per_s, void *stream);
 fb_status fb_profile_enable(fb_ctx *ctx, int32_t on);
 fb_status fb_profile_read(fb_ctx *ctx, fb_profile *out, int32_t reset);
 

@@ -190,6 +190,10 @@ hipError_t launch_remap_sum(const RemapFrame *frames, int n_frames, const RemapT
                             int h, int w, int pitch, int p, hipStream_t s);
 
 hipError_t launch_field_to_packed(const int32_t *abi, uint32_t *packed, int h, int w, hipStream_t s);
+// measurement: blocks x 256 lanes each gather `rows` 5-pixel rows of the
+// padded image img (h x w positions, row pitch in pixels >= w + 4)
+hipError_t launch_gather_probe(const uint32_t *img, int h, int w, int pitch, bool divergent, int blocks, int rows,
+                               uint32_t *out, hipStream_t s);
 
 // ---- learned proposal network (unet.hip, unet_net.hip) ----
 // one pair's coarsest pyramid level as network input

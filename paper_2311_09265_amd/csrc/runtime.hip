@@ -582,7 +582,7 @@ struct fb_ctx {
     int tab_last = 0;           // slot of the last plan
     hipStream_t last_stream = nullptr;  // stream of the last plan
     uint64_t table_gen = 0;
-    Buf pyr, style, fe, tune_table, shat, tables, race, gsum;
+    Buf pyr, style, fe, tune_table, shat, tables, race, gsum, probe;
     std::vector<int> guard_map;  // last call: guard slot of each planned pair (-1: not guarded)
     int guard_n = 0;
     std::map<std::string, int> tuned;
@@ -1305,7 +1305,7 @@ void fb_destroy(fb_ctx *ctx) {
     for (Buf *b : {&ctx->seeds, &ctx->unet_tab})
         if (b->p) (void)hipFree(b->p);
     for (Buf *b : {&ctx->pyr, &ctx->style, &ctx->fe, &ctx->tune_table, &ctx->shat, &ctx->tables, &ctx->race,
-                   &ctx->gsum})
+                   &ctx->gsum, &ctx->probe})
         if (b->p) (void)hipFree(b->p);
     for (TabSlot &t : ctx->tab) {
         if (t.dev) (void)hipFree(t.dev);
@@ -1338,6 +1338,37 @@ fb_status fb_profile_read(fb_ctx *ctx, fb_profile *out, int32_t reset) {
 }
 
 int32_t fb_num_tile_configs(void) { return n_tile_cfgs(); }
+
+fb_status fb_gather_probe(fb_ctx *ctx, const void *pyr, int32_t h, int32_t w, int32_t patch_radius, int32_t divergent,
+                          int32_t rows_per_lane, double *rows_per_s, void *stream) {
+    fb_status st = begin(ctx);
+    if (st) return st;
+    if (!pyr || !rows_per_s) return fail(FB_E_INVALID, "null pointer");
+    if ((st = check_size(h, w))) return st;
+    if (patch_radius != 2) return fail(FB_E_UNSUPPORTED, "the probe gathers 5-pixel rows: patch_radius 2 only");
+    if (rows_per_lane < 1 || rows_per_lane > 4096) return fail(FB_E_INVALID, "rows_per_lane must be in [1, 4096]");
+    constexpr int kBlocks = 2048;  // 8 workgroups of 256 lanes per CU
+    if ((st = ensure(ctx, ctx->probe, (size_t)kBlocks * 256 * 4))) return st;
+    const PyrLayout L = pyr_layout(h, w, 1, patch_radius);
+    const uint32_t *img = reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(pyr) + L.lv[0].px_off);
+    uint32_t *out = static_cast<uint32_t *>(ctx->probe.p);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    FB_HIP(hipEventCreate(&e0));
+    FB_HIP(hipEventCreate(&e1));
+    hipError_t e = launch_gather_probe(img, h, w, L.lv[0].pitch, divergent != 0, kBlocks, rows_per_lane, out, s);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = launch_gather_probe(img, h, w, L.lv[0].pitch, divergent != 0, kBlocks, rows_per_lane, out, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    FB_HIP(e);
+    *rows_per_s = ms > 0.f ? (double)kBlocks * 256.0 * rows_per_lane / (ms * 1e-3) : 0.0;
+    return FB_OK;
+}
 
 int64_t fb_autotune_runs(fb_ctx *ctx) { return ctx ? ctx->autotune_runs : -1; }
 

@@ -74,6 +74,7 @@ _EXPORTS = ["fb_create", "fb_destroy", "fb_last_error", "fb_alpha16_max", "fb_nu
             "fb_unet_forward", "fb_unet_gradients", "fb_unet_train_step", "fb_unet_pair_input", "fb_guard_read", "fb_unet_save_state", "fb_unet_load_state",
             "fb_tuning_export", "fb_tuning_import", "fb_autotune_runs", "fb_graph_fallbacks",
             "fb_build_pyramid_strided", "fb_blend_window_frames", "fb_interpolate_frames", "fb_remap_strided",
+            "fb_gather_probe",
             "fb_patchmatch_level_noalloc"]
 
 
@@ -118,6 +119,7 @@ def load_library(path: str = LIB_PATH):
         "fb_tuning_export": (ctypes.c_int64, [vp, ctypes.c_char_p, ctypes.c_int64]),
         "fb_build_pyramid_strided": (i32, [vp, vp, i32, i32, ctypes.c_int64, i32, i32, vp, vp]),
         "fb_remap_strided": (i32, [vp, vp, ctypes.c_int64, vp, i32, i32, i32, vp, vp]),
+        "fb_gather_probe": (i32, [vp, vp, i32, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_double), vp]),
         "fb_blend_window_frames": (i32, [vp, ctypes.POINTER(fb_frame), ctypes.POINTER(fb_frame), i32, i32, i32, i32,
                                          P, vp, vp]),
         "fb_interpolate_frames": (i32, [vp, ctypes.POINTER(fb_frame), i32, i32, i32, vp, ctypes.POINTER(fb_frame), i32,
@@ -315,6 +317,15 @@ class Context:
         _check(load_library().fb_profile_read(self.handle, ctypes.byref(pr), 1 if reset else 0),
                "fb_profile_read")
         return {k: (int(pr.launches[i]), float(pr.milliseconds[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+    def fb_gather_probe(self, pyr: torch.Tensor, h: int, w: int, divergent: bool, rows_per_lane: int = 256) -> float:
+        """Lane-rows per second of 5-pixel row gathers from level 0 of pyr (a
+        measurement of the rate that bounds the PatchMatch iteration)."""
+        _check_pyr(pyr, "pyr", h, w, 1, 2)
+        r = ctypes.c_double(0.0)
+        _check(load_library().fb_gather_probe(self.handle, _dev(pyr, "pyr", torch.uint8), h, w, 2, int(divergent),
+                                              rows_per_lane, ctypes.byref(r), _stream(pyr)), "fb_gather_probe")
+        return r.value
 
     def fb_guard_read(self, stream_device: int = 0):
         """(seeded, plain) summed coarsest-level energies of every pair of the

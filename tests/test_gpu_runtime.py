@@ -1,6 +1,8 @@
 """GPU tests of the library's runtime: contexts release all the device memory
 they allocate, and launch tables uploaded stream-ordered (a ring of table
 slots) serve calls on several streams and many changing plans correctly."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -126,3 +128,21 @@ def test_tuning_results_persist_across_contexts(tmp_path):
             b.tuning_import("p2;48x64*6=99\n")
     finally:
         b.close()
+
+
+def test_gather_probe_reports_rates():
+    """The measurement entry point: positive row rates, random rows no faster
+    than consecutive ones, and patch radii other than 2 refused."""
+    g, _ = _small_workload(1, 128, 160, 25)
+    ctx = fbm.Context(0)
+    try:
+        pyr = ctx.fb_build_pyramid(g[0], 1, 2)
+        div = ctx.fb_gather_probe(pyr, 128, 160, True, 32)
+        coh = ctx.fb_gather_probe(pyr, 128, 160, False, 32)
+        assert 0 < div <= coh * 1.05, (div, coh)
+        L = fbm.load_library()
+        r = ctypes.c_double(0.0)
+        assert L.fb_gather_probe(ctx.handle, ctypes.c_void_p(pyr.data_ptr()), 128, 160, 3, 1, 32, ctypes.byref(r),
+                                 None) == -3
+    finally:
+        ctx.close()
