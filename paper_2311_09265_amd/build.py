@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfastblend.so")
-SOURCES = ["pyramid.hip", "patchmatch.hip", "remap.hip", "unet.hip", "unet_net.hip", "runtime.hip"]
+SOURCES = ["pyramid.hip", "patchmatch.hip", "remap.hip", "unet.hip", "unet_net.hip", "runtime.hip", "probe.hip"]
 ARCH = os.environ.get("FB_OFFLOAD_ARCH", "gfx950")
 
 # packed-fp32 instructions are kept out of the device code on purpose

@@ -672,39 +672,6 @@ k_field_to_packed(const int32_t *__restrict__ abi, uint32_t *__restrict__ packed
     packed[i] = ((uint32_t)clampi(f.x, 0, h - 1) << 16) | (uint32_t)clampi(f.y, 0, w - 1);
 }
 
-// Measurement: the rate at which patch rows (5 pixels: one 16-byte and one
-// 4-byte load, as the iteration kernel fetches them) can be gathered from one
-// padded image, each row folded into a sum with v_dot4 like a candidate row.
-// DIVERGENT: every lane at its own random pixel (random-search candidates);
-// otherwise the wave's 64 lanes at consecutive pixels of a random row
-// (propagation candidates).  Positions come from a per-lane xorshift; the
-// sums are written out so nothing is optimised away.
-template <bool DIVERGENT>
-__global__ void __launch_bounds__(256)
-k_gather_probe(const uint32_t *__restrict__ img, int h, int w, int pitch, int rows, uint32_t *__restrict__ out) {
-    const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
-    uint32_t x = gid * 0x9E3779B9u + 0x7F4A7C15u;
-    x ^= x >> 16;
-    const uint32_t t = 0x00010101u * (gid & 0xFFu);
-    uint32_t acc = 0;
-    for (int k = 0; k < rows; ++k) {
-        x ^= x << 13;
-        x ^= x >> 17;
-        x ^= x << 5;
-        const uint32_t y = DIVERGENT ? x : (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
-        const int r = (int)(((y & 0xFFFFu) * (uint32_t)h) >> 16);
-        int c = (int)(((y >> 16) * (uint32_t)w) >> 16);
-        if (!DIVERGENT) c = min(c + (int)(threadIdx.x & 63u), w - 1);
-        const PixRow<5> row = load_pixrow<5>(img, 4u * (uint32_t)(r * pitch + c));
-#pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            acc = __builtin_amdgcn_udot4(row.v[j], t, acc, false);
-            acc = __builtin_amdgcn_udot4(row.v[j], row.v[j], acc, false);
-        }
-    }
-    out[gid] = acc;
-}
-
 constexpr TileCfg kTileCfgs[] = {{64, 4}, {32, 8}, {16, 16}, {64, 2}};
 constexpr int kGuardedGrid = 2048;  // workgroups of a guarded iteration launch (8 per CU)
 
@@ -826,13 +793,6 @@ hipError_t launch_guard_select(const PMJob *jobs, int n_jobs, int total_tiles, i
 hipError_t launch_guard_decide(const PMJob *jobs, int n_jobs, hipStream_t s) {
     if (n_jobs <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_guard_decide, dim3((n_jobs + 63) / 64), dim3(64), 0, s, jobs, n_jobs);
-    return hipGetLastError();
-}
-
-hipError_t launch_gather_probe(const uint32_t *img, int h, int w, int pitch, bool divergent, int blocks, int rows,
-                               uint32_t *out, hipStream_t s) {
-    if (divergent) hipLaunchKernelGGL(k_gather_probe<true>, dim3(blocks), dim3(256), 0, s, img, h, w, pitch, rows, out);
-    else hipLaunchKernelGGL(k_gather_probe<false>, dim3(blocks), dim3(256), 0, s, img, h, w, pitch, rows, out);
     return hipGetLastError();
 }
 
