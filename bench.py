@@ -157,12 +157,33 @@ def bench_learned(ctx, fbm, g, s, out, M, p, levels, seed, wpath, args, pairs, N
     nprm = fbm.make_params(p, levels, args.learned_iters, seed, fbm.FB_LEARNED_SEED | fbm.FB_NO_GUARD)
     ctx.fb_blend_window(g, s, M, nprm, out=out)
     torch.cuda.synchronize()
+    # timed like the guarded steps (HIP events around every launch), so the
+    # difference is the guard's work alone
+    ctx.fb_profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ctx.fb_blend_window(g, s, M, nprm, out=out)
     torch.cuda.synchronize()
     ms_unguarded = (time.perf_counter() - t0) / args.steps * 1e3
+    ctx.fb_profile_read(reset=True)
+    ctx.fb_profile_enable(False)
     log("learned without the guard: %.2f ms/step" % ms_unguarded)
+    graph_ms = None
+    if not args.no_graph:
+        # the guarded learned steps replayed as one HIP graph per step
+        gprm = fbm.make_params(p, levels, args.learned_iters, seed, fbm.FB_LEARNED_SEED | fbm.FB_USE_GRAPH)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            ctx.fb_blend_window(g, s, M, gprm, out=out)
+            side.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                ctx.fb_blend_window(g, s, M, gprm, out=out)
+            side.synchronize()
+            graph_ms = round((time.perf_counter() - t0) / args.steps * 1e3, 3)
+        torch.cuda.current_stream().wait_stream(side)
+        log("learned, graph replay: %.2f ms/step" % graph_ms)
     guard = {"rule": "each seeded pair's coarsest level (seeded start, %d iterations) is raced against the "
                      "plain random start with one iteration more (%d); a seed whose summed energy is the larger "
                      "is rejected and the pair's result is plain@6 exactly" % (args.learned_iters,
@@ -191,6 +212,7 @@ def bench_learned(ctx, fbm, g, s, out, M, p, levels, seed, wpath, args, pairs, N
     margin = 0.0
     accepted = (energy is not None and plain_energy is not None and energy <= plain_energy * (1 + margin))
     return {"ms_per_step": round(ms, 3), "blended_frames_per_s": round(N / (ms / 1e3), 3),
+            "graph_ms_per_step": graph_ms,
             "iters_per_level": args.learned_iters, "pixel_iterations_per_step": pix,
             "mean_level0_patch_energy": energy, "plain_mean_level0_patch_energy": plain_energy,
             "plain_same_iters_mean_level0_patch_energy": plain_same,
