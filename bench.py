@@ -406,6 +406,46 @@ def bench_pair64(ctx, fbm, args):
     return res
 
 
+def bench_pairs_512(ctx, fbm, g, p, levels, iters, learned_iters, seed, args, pairs, N, h, w, learned):
+    """PatchMatch alone for the 290 window pairs of the 512x512 blend (pyramids
+    built beforehand), batched in one fb_patchmatch_batch call against one
+    call per pair, for plain (6 iterations per level) and, when the network
+    is loaded, learned seeds (2 per level, guarded)."""
+    import torch
+    pyrs = [ctx.fb_build_pyramid(g[f], levels, p) for f in range(N)]
+    descs = [dict(src_pyr=pyrs[j], tgt_pyr=pyrs[i], h=h, w=w, levels=levels, pair_id=j * N + i) for (j, i) in pairs]
+    res = {"workload": "%d pairs of %dx%d, %d levels, PatchMatch only" % (len(pairs), h, w, levels)}
+    modes = [("plain", iters, 0)]
+    if learned:
+        modes.append(("learned", learned_iters, fbm.FB_LEARNED_SEED))
+    steps = max(1, args.steps // 2)
+    for name, its, flags in modes:
+        pix, _ = pm_work(len(pairs), h, w, levels, its, p)
+        prm = fbm.make_params(p, levels, its, seed, flags)
+        out = {"pixel_iterations_per_call": pix}
+        for how in ("batched", "per_pair"):
+            if how == "per_pair":
+                def run():
+                    for d in descs:
+                        ctx.fb_patchmatch_batch([d], prm)
+            else:
+                def run():
+                    ctx.fb_patchmatch_batch(descs, prm)
+            run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                run()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) / steps * 1e3
+            out[how] = {"ms_per_call": round(ms, 3), "mpix_iter_per_s": round(pix / (ms / 1e3) / 1e6, 3)}
+            log("%d pairs, %s, %s: %.2f ms per call" % (len(pairs), name, how, ms))
+        out["speedup_batched_vs_per_pair"] = round(out["per_pair"]["ms_per_call"] / out["batched"]["ms_per_call"], 3)
+        res[name] = out
+    del descs, pyrs
+    return res
+
+
 def bench_mixed(ctx, fbm, args):
     """The mixed-size batch: 12 pairs (t, t + d), d in 1..5, of each of 256x256
     and 512x512 (3 levels) and 1024x576 and 1280x720 (4 levels), 6 iterations:
@@ -492,6 +532,8 @@ def main():
     ap.add_argument("--no-interp", action="store_true", help="skip the interpolation timings")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-size batch timings")
     ap.add_argument("--no-pair64", action="store_true", help="skip the 64x64 single-pair latency")
+    ap.add_argument("--no-pairs512", action="store_true",
+                    help="skip PatchMatch of the 290 blend pairs batched vs per pair")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (counter calibration)")
     args = ap.parse_args()
@@ -600,6 +642,11 @@ def main():
     if wpath and os.path.exists(wpath):
         learned = bench_learned(ctx, fbm, g, s, out, M, p, levels, seed, wpath, args, pairs, N, h, w, mean_energy)
 
+    pairs512 = None
+    if not args.no_pairs512:
+        pairs512 = bench_pairs_512(ctx, fbm, g, p, levels, iters, args.learned_iters, seed, args, pairs, N, h, w,
+                                   learned is not None)
+
     n_iter, iter_ms = prof["pm_iter"]
     iter_ms_step = iter_ms / args.steps
     # the remap and window sum (Alg. 2, Eq. 2) against HBM: its compulsory
@@ -676,6 +723,7 @@ def main():
         "accurate_mode": accurate,
         "interpolation": interp,
         "mixed_batch": mixed,
+        "pairs_512": pairs512,
         "pair_64x64": pair64,
     }
     if learned:
