@@ -107,7 +107,10 @@ struct PMJob {
     const uint32_t *f_alt;
     const uint32_t *e_alt;
     int32_t guard_when;
-    int32_t guard_pad;
+    // style-loss iterations: e_in already holds the incumbent's loss under
+    // this iteration's target (Eq. 8, whose target T^- is fixed, after the
+    // level's first iteration), so the incumbent is not scored again
+    int32_t e_valid;
 };
 static_assert(sizeof(PMJob) % 8 == 0, "PMJob is copied as an array");
 

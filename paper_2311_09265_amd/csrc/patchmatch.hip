@@ -386,7 +386,7 @@ __device__ __forceinline__ void pm_iter_tile(const PMJob *__restrict__ jobs, int
     const uint32_t f0 = s_f[fc0];
     int br = (int)(f0 >> 16), bc = (int)(f0 & 0xFFFFu);
     uint32_t be;
-    if constexpr (STYLE) {
+    if (STYLE && !J.e_valid) {
         const uint32_t off = 4u * (uint32_t)(br * pitch + bc);
         be = a16 * patch_loss<P>(src_px, off, pitch_b, t) + 16u * patch_loss<P>(src_sty, off, pitch_b, ts);
     } else {

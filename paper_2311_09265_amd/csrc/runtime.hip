@@ -459,6 +459,10 @@ void plan_patchmatch(Plan &P, std::vector<PairSpec> &pairs, int iters, int p, ui
                 j.e_in = ps.e[cur[k]];
                 j.f_out = ps.f[cur[k] ^ 1];
                 j.e_out = ps.e[cur[k] ^ 1];
+                // Eq. 8: after the level's first iteration the stored energy is
+                // already the loss under the fixed target (the level start
+                // scores Eq. 1)
+                j.e_valid = style && fixed_target && it > 0;
                 if (track) {
                     j.trk_prev = ps.trk_prev >= 0 ? fin[ps.trk_prev] : nullptr;
                     j.trk_next = ps.trk_next >= 0 ? fin[ps.trk_next] : nullptr;
