@@ -126,7 +126,38 @@ struct TargetPatch {
     static constexpr int K = 2 * P + 1;
     uint32_t px[K][K];
     uint32_t cum_tt[K];  // sum t^2 of rows 0..i; cum_tt[K - 1] is the patch's
+    __device__ __forceinline__ uint32_t pix(int i, int j) const { return px[i][j]; }
 };
+
+// A target patch that stays in its LDS-staged tile (row stride SW): only the
+// row sums are held in registers, and every use reads the pixel from LDS again
+// (the volatile access keeps the compiler from caching the 25 pixels in
+// registers), which leaves room for a second patch at a higher occupancy.
+template <int P, int SW>
+struct LdsPatch {
+    static constexpr int K = 2 * P + 1;
+    const volatile __attribute__((address_space(3))) uint32_t *s;  // the patch's top-left padded pixel
+    uint32_t cum_tt[K];
+    __device__ __forceinline__ uint32_t pix(int i, int j) const { return s[i * SW + j]; }
+};
+
+template <int P, int SW>
+__device__ __forceinline__ void load_target_patch_lds(const uint32_t *s, int base, LdsPatch<P, SW> &t) {
+    constexpr int K = 2 * P + 1;
+    t.s = (const volatile __attribute__((address_space(3))) uint32_t *)(s + base);
+    uint32_t tt = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint32_t x = t.pix(i, j);
+            acc = __builtin_amdgcn_udot4(x, x, acc, false);
+        }
+        tt += acc;
+        t.cum_tt[i] = tt;
+    }
+}
 
 // the patch whose top-left padded pixel is element base of a tile staged in
 // LDS with row stride SW
@@ -167,27 +198,25 @@ __device__ __forceinline__ void load_target_patch(const uint32_t *tp, uint32_t o
 }
 
 // sum s^2 - 2 sum s t over pixels [J0, J0 + N) of patch row i
-template <int P, int J0, int N>
-__device__ __forceinline__ uint32_t seg_loss(const uint32_t *sp, uint32_t off, const TargetPatch<P> &t,
-                                             int i) {
+template <int J0, int N, class TP>
+__device__ __forceinline__ uint32_t seg_loss(const uint32_t *sp, uint32_t off, const TP &t, int i) {
     const PixRow<N> row = load_pixrow<N>(sp, off);
     uint32_t st = 0, ss = 0;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-        st = __builtin_amdgcn_udot4(row.v[j], t.px[i][J0 + j], st, false);
+        st = __builtin_amdgcn_udot4(row.v[j], t.pix(i, J0 + j), st, false);
         ss = __builtin_amdgcn_udot4(row.v[j], row.v[j], ss, false);
     }
     return ss - 2u * st;
 }
 
 // Eq. 1 for the source patch whose top-left padded pixel is at byte offset off
-template <int P>
-__device__ __forceinline__ uint32_t patch_loss(const uint32_t *sp, uint32_t off, uint32_t pitch_b,
-                                               const TargetPatch<P> &t) {
-    constexpr int K = 2 * P + 1;
+template <class TP>
+__device__ __forceinline__ uint32_t patch_loss(const uint32_t *sp, uint32_t off, uint32_t pitch_b, const TP &t) {
+    constexpr int K = TP::K;
     uint32_t e = t.cum_tt[K - 1];
 #pragma unroll
-    for (int i = 0; i < K; ++i) e += seg_loss<P, 0, K>(sp, off + (uint32_t)i * pitch_b, t, i);
+    for (int i = 0; i < K; ++i) e += seg_loss<0, K>(sp, off + (uint32_t)i * pitch_b, t, i);
     return e;
 }
 
@@ -286,7 +315,7 @@ k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unif
     TargetPatch<P> t;
     load_target_patch_lds<P, SW>(s_tgt, (int)threadIdx.y * SW + (int)threadIdx.x, t);
     gstore<uint32_t>(J.f_out, 4u * v, ((uint32_t)fr << 16) | (uint32_t)fc);
-    gstore<uint32_t>(J.e_out, 4u * v, patch_loss<P>(J.src_px, 4u * (uint32_t)(fr * J.pitch + fc), pitch_b, t));
+    gstore<uint32_t>(J.e_out, 4u * v, patch_loss(J.src_px, 4u * (uint32_t)(fr * J.pitch + fc), pitch_b, t));
 }
 
 // MODE & kIterStyle: a guide + style loss scaled by 16 to stay an integer,
@@ -305,8 +334,10 @@ k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unif
 // built with the pyramid), by which a candidate whose Cauchy-Schwarz bound
 // already reaches the running best is ruled out before any of its pixels is
 // fetched.
-// With the style loss and p <= 2 the kernel is held to 5 waves per SIMD
-// (at most 96 VGPRs, no spills); larger patches keep the compiler's choice.
+// With the style loss the guide patch is read from the LDS tile at every use
+// (only the target patch of the style term stays in registers), and for
+// p <= 2 the kernel is held to 7 waves per SIMD (at most 72 VGPRs, no
+// spills); larger patches keep the compiler's choice.
 // One tile (flat index `tile`) of an iteration launch, staged in the workgroup's
 // LDS arrays; every thread of the workgroup calls it with the same t.
 template <int P, int TW, int TH, int MODE>
@@ -349,7 +380,9 @@ __device__ __forceinline__ void pm_iter_tile(const PMJob *__restrict__ jobs, int
     const uint32_t *src_px = J.src_px;
     const int fc0 = ((int)threadIdx.y + 1) * FW + (int)threadIdx.x + 1;  // this pixel in s_f
 
-    TargetPatch<P> t, ts;  // ts: the patch of S^ (Eq. 3 loss only)
+    // the guide patch; with the style loss it is read from LDS at every use
+    std::conditional_t<STYLE, LdsPatch<P, SW>, TargetPatch<P>> t;
+    TargetPatch<P> ts;  // the patch of S^ or of the partner (style losses only)
     load_target_patch_lds<P, SW>(s_tgt, (int)threadIdx.y * SW + (int)threadIdx.x, t);
     const uint32_t *src_sty = J.src_sty;
     const uint32_t a16 = STYLE ? (uint32_t)J.alpha16 : 1u;
@@ -370,9 +403,10 @@ __device__ __forceinline__ void pm_iter_tile(const PMJob *__restrict__ jobs, int
         for (int i = 0; i < K; ++i)
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                a0 = __builtin_amdgcn_udot4(t.px[i][j], 0x00000001u, a0, false);
-                a1 = __builtin_amdgcn_udot4(t.px[i][j], 0x00000100u, a1, false);
-                a2 = __builtin_amdgcn_udot4(t.px[i][j], 0x00010000u, a2, false);
+                const uint32_t x = t.pix(i, j);
+                a0 = __builtin_amdgcn_udot4(x, 0x00000001u, a0, false);
+                a1 = __builtin_amdgcn_udot4(x, 0x00000100u, a1, false);
+                a2 = __builtin_amdgcn_udot4(x, 0x00010000u, a2, false);
             }
         ts0 = (int)a0;
         ts1 = (int)a1;
@@ -388,7 +422,7 @@ __device__ __forceinline__ void pm_iter_tile(const PMJob *__restrict__ jobs, int
     uint32_t be;
     if (STYLE && !J.e_valid) {
         const uint32_t off = 4u * (uint32_t)(br * pitch + bc);
-        be = a16 * patch_loss<P>(src_px, off, pitch_b, t) + 16u * patch_loss<P>(src_sty, off, pitch_b, ts);
+        be = a16 * patch_loss(src_px, off, pitch_b, t) + 16u * patch_loss(src_sty, off, pitch_b, ts);
     } else {
         be = gload<uint32_t>(J.e_in, 4u * v);
     }
@@ -433,8 +467,8 @@ __device__ __forceinline__ void pm_iter_tile(const PMJob *__restrict__ jobs, int
         uint32_t acc = 0, accs = 0;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            acc += seg_loss<P, 0, K>(src_px, off + (uint32_t)i * pitch_b, t, i);
-            if constexpr (STYLE) accs += seg_loss<P, 0, K>(src_sty, off + (uint32_t)i * pitch_b, ts, i);
+            acc += seg_loss<0, K>(src_px, off + (uint32_t)i * pitch_b, t, i);
+            if constexpr (STYLE) accs += seg_loss<0, K>(src_sty, off + (uint32_t)i * pitch_b, ts, i);
             if (i < K - 1) {
                 if constexpr (STYLE) {
                     if (a16 * (t.cum_tt[i] + acc) + 16u * (ts.cum_tt[i] + accs) >= be) return;
@@ -505,7 +539,7 @@ __device__ __forceinline__ void pm_iter_tile(const PMJob *__restrict__ jobs, int
 }
 
 template <int P, int TW, int TH, int MODE>
-__global__ void __launch_bounds__(TW *TH, ((MODE & kIterStyle) && P <= 2) ? 5 : 1)
+__global__ void __launch_bounds__(TW *TH, ((MODE & kIterStyle) && P <= 2) ? 7 : 1)
 k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles, int iter,
           uint32_t k0, uint32_t k1) {
     __shared__ uint32_t s_tgt[(TH + 2 * P) * (TW + 2 * P)];  // target tile with its patch border
