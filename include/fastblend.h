@@ -174,7 +174,9 @@ int64_t fb_autotune_runs(fb_ctx *ctx);
 /* bytes allocated by the caller; it holds every level as 4-byte pixels   */
 /* with a border of p replicated pixels (p = patch radius), each followed  */
 /* by a table of per-block ranges of the (2p+1)^2 patch sums (at most     */
-/* 16 KiB) that lets PatchMatch rule candidates out before reading them.  */
+/* 16 KiB) and a plane of every position's quantised patch sums (4 bytes  */
+/* per pixel), which let PatchMatch rule candidates out before reading    */
+/* them.                                                                  */
 /* ---------------------------------------------------------------------- */
 size_t fb_pyramid_bytes(int32_t h, int32_t w, int32_t levels, int32_t patch_radius);
 fb_status fb_build_pyramid(fb_ctx *ctx, const uint8_t *rgb, int32_t h, int32_t w,

@@ -14,6 +14,11 @@
 //   (-mx_G, -mx_B), each tab_w * tab_h words.  The block size is the
 //   smallest from 8 x 8 up whose table fits kBoundTabBytes, so one table
 //   always fits a workgroup's LDS.
+//   The table is followed by the level's patch-sum plane: for every patch
+//   position (r, c), at word r * pitch + c of h rows, each channel's
+//   (2p+1)^2 patch sum shifted right by psum_shift(p) (10 bits each: R in
+//   bits 0-9, G in 10-19, B in 20-29), so a candidate's own sums are known
+//   to within 2^psum_shift - 1.
 // * Style frames: the same format at full resolution (one aligned 4-byte
 //   gather per remapped pixel).
 // * NNFs inside the library are one uint32 per pixel: (row << 16) | col.
@@ -31,6 +36,13 @@ constexpr int kMaxP = 4;
 constexpr int kPitchAlign = 16;  // pixels
 constexpr int kBoundTabBytes = 16384;  // largest bound table of one level
 constexpr int kBoundTabMinShift = 3;   // smallest bound-table block: 8 x 8 positions
+// Patch-sum plane: each channel's (2p+1)^2 patch sum (at most (2p+1)^2 * 255)
+// shifted right until it fits 10 bits
+inline int psum_shift(int p) {
+    int s = 0;
+    while ((((2 * p + 1) * (2 * p + 1) * 255) >> s) >= 1024) ++s;
+    return s;
+}
 
 struct LevelGeom {
     int32_t h, w;        // level size
@@ -40,6 +52,7 @@ struct LevelGeom {
     size_t tab_off;      // byte offset of the level's bound table
     int32_t tab_shift;   // bound-table block side = 1 << tab_shift positions
     int32_t tab_w, tab_h;  // bound-table size in blocks
+    size_t sum_off;      // byte offset of the level's patch-sum plane
 };
 
 struct PyrLayout {
@@ -92,6 +105,7 @@ struct PMJob {
     int32_t tab_shift;         // bound table of the source level (see the layout above):
     int32_t tab_w, tab_n;      //   block shift, width in blocks, entries (0: no table)
     const uint32_t *btab;
+    const uint32_t *psum;      // the source level's patch-sum plane (with btab)
     const uint32_t *f_prev;    // Eq. 3 refresh: the field the level's previous refresh used
                                //   (nullptr: refresh every pixel)
     // Guard of a seeded pair (its coarsest level raced against the plain
@@ -111,6 +125,7 @@ struct PMJob {
     // this iteration's target (Eq. 8, whose target T^- is fixed, after the
     // level's first iteration), so the incumbent is not scored again
     int32_t e_valid;
+    int32_t psum_shift;        // quantisation shift of the patch-sum plane
 };
 static_assert(sizeof(PMJob) % 8 == 0, "PMJob is copied as an array");
 

@@ -334,9 +334,11 @@ k_pm_start(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int unif
 // built with the pyramid), by which a candidate whose Cauchy-Schwarz bound
 // already reaches the running best is ruled out before any of its pixels is
 // fetched.
-// With the style loss the guide patch is read from the LDS tile at every use
-// (only the target patch of the style term stays in registers), and for
-// p <= 2 the kernel is held to 7 waves per SIMD (at most 72 VGPRs, no
+// With a style loss, a random-search candidate that passes the table is also
+// tested against its own quantised patch sums (the source level's patch-sum
+// plane) before any row is fetched; the guide patch is read from the LDS tile
+// at every use (only the target patch of the style term stays in registers),
+// and for p <= 2 the kernel is held to 6 waves per SIMD (at most 80 VGPRs, no
 // spills); larger patches keep the compiler's choice.
 // One tile (flat index `tile`) of an iteration launch, staged in the workgroup's
 // LDS arrays; every thread of the workgroup calls it with the same t.
@@ -413,9 +415,21 @@ __device__ __forceinline__ void pm_iter_tile(const PMJob *__restrict__ jobs, int
         ts2 = (int)a2;
     }
     const int tab_shift = J.tab_shift, tab_w = J.tab_w;
+    const int qs = J.psum_shift;
+    const short nqw = (short)(1 - (1 << qs));  // minus the width of a quantisation step
     // added to the table's pairs (mn_R, mn_G), (mn_B, -mx_R), (-mx_G, -mx_B):
     // the six differences whose positive parts are the distances to the ranges
     const s16x2 u0 = {(short)-ts0, (short)-ts1}, u1 = {(short)-ts2, (short)ts0}, u2 = {(short)ts1, (short)ts2};
+    // sum_c dist(T_c, [lo_c, hi_c])^2 for ranges given as those three pairs
+    auto range_lb = [&](s16x2 p0, s16x2 p1, s16x2 p2) {
+        const s16x2 z = {0, 0};
+        const s16x2 d0 = __builtin_elementwise_max(p0 + u0, z);
+        const s16x2 d1 = __builtin_elementwise_max(p1 + u1, z);
+        const s16x2 d2 = __builtin_elementwise_max(p2 + u2, z);
+        uint32_t lb = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, d0), __builtin_bit_cast(u16x2, d0), 0u, false);
+        lb = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, d1), __builtin_bit_cast(u16x2, d1), lb, false);
+        return __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, d2), __builtin_bit_cast(u16x2, d2), lb, false);
+    };
 
     const uint32_t f0 = s_f[fc0];
     int br = (int)(f0 >> 16), bc = (int)(f0 & 0xFFFFu);
@@ -450,13 +464,8 @@ __device__ __forceinline__ void pm_iter_tile(const PMJob *__restrict__ jobs, int
             // sum_c dist(T_c, [mn_c, mx_c])^2 <= (2p+1)^2 * SSD(G); at most one
             // of each channel's two differences is positive
             const int e = (cr >> tab_shift) * tab_w + (cc >> tab_shift);
-            const s16x2 z = {0, 0};
-            const s16x2 d0 = __builtin_elementwise_max(__builtin_bit_cast(s16x2, s_btab[e]) + u0, z);
-            const s16x2 d1 = __builtin_elementwise_max(__builtin_bit_cast(s16x2, s_btab[tab_n + e]) + u1, z);
-            const s16x2 d2 = __builtin_elementwise_max(__builtin_bit_cast(s16x2, s_btab[2 * tab_n + e]) + u2, z);
-            uint32_t lb = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, d0), __builtin_bit_cast(u16x2, d0), 0u, false);
-            lb = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, d1), __builtin_bit_cast(u16x2, d1), lb, false);
-            lb = __builtin_amdgcn_udot2(__builtin_bit_cast(u16x2, d2), __builtin_bit_cast(u16x2, d2), lb, false);
+            const uint32_t lb = range_lb(__builtin_bit_cast(s16x2, s_btab[e]), __builtin_bit_cast(s16x2, s_btab[tab_n + e]),
+                                         __builtin_bit_cast(s16x2, s_btab[2 * tab_n + e]));
             if constexpr (STYLE) {
                 if ((uint64_t)a16 * lb >= (uint64_t)(K * K) * be) return;
             } else {
@@ -464,6 +473,24 @@ __device__ __forceinline__ void pm_iter_tile(const PMJob *__restrict__ jobs, int
             }
         }
         const uint32_t off = 4u * (uint32_t)(cr * pitch + cc);
+        if (STYLE && decltype(use_bound)::value && tab_n > 0) {
+            // the same bound from the candidate's own patch sums, known to
+            // within 2^qs - 1 from the plane (only with a style loss, where a
+            // candidate that gets this far costs two patches per row; in the
+            // guide-only kernel the extra load per candidate costs more than
+            // the rows it saves)
+            const uint32_t q = gload<uint32_t>(J.psum, off);
+            const s16x2 lo01 = __builtin_bit_cast(s16x2, ((q & 0x3FFu) | ((q << 6) & 0x3FF0000u)) << qs);
+            const short lo2 = (short)((q >> 20) << qs);
+            // the pairs (lo_R, lo_G), (lo_B, -hi_R), (-hi_G, -hi_B), as in the table
+            const s16x2 p1 = {lo2, (short)(nqw - lo01.x)}, p2 = {(short)(nqw - lo01.y), (short)(nqw - lo2)};
+            const uint32_t lb = range_lb(lo01, p1, p2);
+            if constexpr (STYLE) {
+                if ((uint64_t)a16 * lb >= (uint64_t)(K * K) * be) return;
+            } else {
+                if (lb >= thr) return;
+            }
+        }
         uint32_t acc = 0, accs = 0;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
@@ -539,7 +566,7 @@ __device__ __forceinline__ void pm_iter_tile(const PMJob *__restrict__ jobs, int
 }
 
 template <int P, int TW, int TH, int MODE>
-__global__ void __launch_bounds__(TW *TH, ((MODE & kIterStyle) && P <= 2) ? 7 : 1)
+__global__ void __launch_bounds__(TW *TH, ((MODE & kIterStyle) && P <= 2) ? 6 : 1)
 k_pm_iter(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int uniform_tiles, int iter,
           uint32_t k0, uint32_t k1) {
     __shared__ uint32_t s_tgt[(TH + 2 * P) * (TW + 2 * P)];  // target tile with its patch border

@@ -47,6 +47,9 @@ PyrLayout pyr_layout(int h, int w, int levels, int p) {
         g.tab_off = off;
         off += (size_t)g.tab_h * g.tab_w * 12;
         off = (off + 255) & ~(size_t)255;
+        g.sum_off = off;
+        off += (size_t)g.h * g.pitch * 4;
+        off = (off + 255) & ~(size_t)255;
     }
     L.bytes = off;
     return L;
@@ -109,10 +112,12 @@ k_downsample(uint8_t *__restrict__ base, size_t stride, int hi_, int wi, int pit
 // (sum_k d_k)^2 <= (2p+1)^2 sum_k d_k^2 for the channel differences d_k of
 // two patches, so the distance from a target patch's channel sums to these
 // ranges bounds Eq. 1 from below for every candidate in the block.  Sums are
-// at most 81 * 255, so each value and its negation fit 16 bits.
+// at most 81 * 255, so each value and its negation fit 16 bits.  Every
+// position's sums also go, quantised to 10 bits each, into the level's
+// patch-sum plane, which gives the same bound per candidate.
 __global__ void __launch_bounds__(64)
 k_bound_table(uint8_t *__restrict__ base, size_t stride, int h, int w, int pitch, size_t px_off,
-              int sh, int tab_w, int tab_n, size_t tab_off, int p) {
+              int sh, int tab_w, int tab_n, size_t tab_off, size_t sum_off, int qs, int p) {
     const int f = blockIdx.y;
     const int by = (int)blockIdx.x / tab_w, bx = (int)blockIdx.x - by * tab_w;
     const uint8_t *fb = base + (size_t)f * stride;
@@ -130,6 +135,8 @@ k_bound_table(uint8_t *__restrict__ base, size_t stride, int h, int w, int pitch
                 g += (px >> 8) & 0xFFu;
             }
         const int s0 = (int)(rb & 0xFFFFu), s1 = (int)g, s2 = (int)(rb >> 16);
+        reinterpret_cast<uint32_t *>(base + (size_t)f * stride + sum_off)[(size_t)r * pitch + c] =
+            (uint32_t)(s0 >> qs) | ((uint32_t)(s1 >> qs) << 10) | ((uint32_t)(s2 >> qs) << 20);
         mn0 = min(mn0, s0); mx0 = max(mx0, s0);
         mn1 = min(mn1, s1); mx1 = max(mx1, s1);
         mn2 = min(mn2, s2); mx2 = max(mx2, s2);
@@ -155,7 +162,8 @@ hipError_t launch_bound_tables(uint8_t *base, size_t stride, int n, const PyrLay
     for (int l = 0; l < L.levels; ++l) {
         const LevelGeom &g = L.lv[l];
         hipLaunchKernelGGL(k_bound_table, dim3(g.tab_w * g.tab_h, n), dim3(64), 0, s, base, stride,
-                           g.h, g.w, g.pitch, g.px_off, g.tab_shift, g.tab_w, g.tab_w * g.tab_h, g.tab_off, L.p);
+                           g.h, g.w, g.pitch, g.px_off, g.tab_shift, g.tab_w, g.tab_w * g.tab_h, g.tab_off,
+                           g.sum_off, psum_shift(L.p), L.p);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -254,6 +254,8 @@ PMJob job_geom(const PairSpec &ps, int l) {
     j.tab_shift = g.tab_shift;
     j.tab_w = g.tab_w;
     j.tab_n = g.tab_w * g.tab_h;
+    j.psum = reinterpret_cast<const uint32_t *>(ps.src_pyr + g.sum_off);
+    j.psum_shift = psum_shift(ps.L.p);
     if (ps.src_sty_pyr) {
         j.src_sty = reinterpret_cast<const uint32_t *>(ps.src_sty_pyr + g.px_off);
         // the iteration only reads sty_hat; T^- is never written

@@ -42,7 +42,8 @@ def test_pyramid_bytes_layout(lib):
     # level l: (h_l + 2p) rows x pitch 4-byte pixels, pitch = w_l + 2p rounded
     # up to 16, then its bound table of 12-byte entries, one per block of
     # b x b positions with b the smallest power of two >= 8 that keeps the
-    # table within 16 KiB; every part 256-byte aligned
+    # table within 16 KiB, then its patch-sum plane (h_l rows x pitch 4-byte
+    # words); every part 256-byte aligned
     def expect(h, w, levels, p):
         off = 0
         for l in range(levels):
@@ -54,6 +55,8 @@ def test_pyramid_bytes_layout(lib):
             while -(-hl // b) * -(-wl // b) * 12 > 16384:
                 b *= 2
             off += -(-hl // b) * -(-wl // b) * 12
+            off = -(-off // 256) * 256
+            off += hl * pitch * 4
             off = -(-off // 256) * 256
         return off
     for args in [(64, 64, 1, 2), (512, 512, 3, 2), (576, 1024, 4, 2), (720, 1280, 4, 2), (37, 53, 3, 1),

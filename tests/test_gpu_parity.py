@@ -54,7 +54,8 @@ def _pyramid_layout(h, w, levels, p):
     """Byte layout of a pyramid buffer: per level its padded 4-byte pixels,
     (h_l + 2p) rows of pitch = w_l + 2p rounded up to 16, then its bound table
     (12 bytes per block of b x b positions, b the smallest power of two >= 8
-    keeping the table within 16 KiB), every part 256-byte aligned."""
+    keeping the table within 16 KiB), then its patch-sum plane (h_l rows of
+    pitch 4-byte words), every part 256-byte aligned."""
     out, off = [], 0
     for l in range(levels):
         hl, wl = -(-h // (1 << l)), -(-w // (1 << l))
@@ -64,9 +65,35 @@ def _pyramid_layout(h, w, levels, p):
         b = 8
         while -(-hl // b) * -(-wl // b) * 12 > 16384:
             b *= 2
-        out.append((hl, wl, pitch, px_off, b, off))
+        tab_off = off
         off = -(-(off + -(-hl // b) * -(-wl // b) * 12) // 256) * 256
+        out.append((hl, wl, pitch, px_off, b, tab_off, off))
+        off = -(-(off + hl * pitch * 4) // 256) * 256
     return out, off
+
+
+def _patch_sums(level_img, p):
+    """Each channel's sum over the (2p+1)^2 patch around every pixel, with
+    the patch clamped into the image (an edge-padded box filter)."""
+    k = 2 * p + 1
+    hl, wl = level_img.shape[:2]
+    x = np.pad(level_img.astype(np.int64), ((p, p), (p, p), (0, 0)), mode="edge")
+    sums = np.zeros((hl, wl, 3), np.int64)
+    for dr in range(k):
+        for dc in range(k):
+            sums += x[dr:dr + hl, dc:dc + wl]
+    return sums
+
+
+def _sum_plane(level_img, p):
+    """The patch-sum plane as stored: per pixel one word holding each
+    channel's patch sum shifted right by the smallest q that fits it in 10
+    bits, R in bits 0-9, G in 10-19, B in 20-29."""
+    q = 0
+    while ((2 * p + 1) ** 2 * 255) >> q >= 1024:
+        q += 1
+    s = _patch_sums(level_img, p) >> q
+    return (s[..., 0] | (s[..., 1] << 10) | (s[..., 2] << 20)).astype(np.uint32)
 
 
 def _bound_table(level_img, p, b):
@@ -75,13 +102,8 @@ def _bound_table(level_img, p, b):
     int16 pairs (mn_R, mn_G), (mn_B, -mx_R), (-mx_G, -mx_B), one entry per
     block in row-major block order.  Written from the definition (an
     edge-padded box filter), not from the kernel."""
-    k = 2 * p + 1
     hl, wl = level_img.shape[:2]
-    x = np.pad(level_img.astype(np.int64), ((p, p), (p, p), (0, 0)), mode="edge")
-    sums = np.zeros((hl, wl, 3), np.int64)
-    for dr in range(k):
-        for dc in range(k):
-            sums += x[dr:dr + hl, dc:dc + wl]
+    sums = _patch_sums(level_img, p)
     th, tw = -(-hl // b), -(-wl // b)
     out = np.zeros((3, th, tw, 2), np.int16)
     for by in range(th):
@@ -104,7 +126,7 @@ def test_pyramid_buffer_matches_oracle(ctx, h, w, levels, p):
     ref = oracle.pyramid(img, levels)
     lay, total = _pyramid_layout(h, w, levels, p)
     assert buf.size == total
-    for l, (hl, wl, pitch, px_off, b, tab_off) in enumerate(lay):
+    for l, (hl, wl, pitch, px_off, b, tab_off, sum_off) in enumerate(lay):
         padded = np.pad(ref[l], ((p, p), (p, p), (0, 0)), mode="edge")
         px = buf[px_off:px_off + (hl + 2 * p) * pitch * 4].reshape(hl + 2 * p, pitch, 4)
         assert np.array_equal(px[:, :wl + 2 * p, :3], padded), l
@@ -112,6 +134,8 @@ def test_pyramid_buffer_matches_oracle(ctx, h, w, levels, p):
         want = _bound_table(ref[l], p, b)
         got = buf[tab_off:tab_off + want.size * 2].view(np.int16).reshape(want.shape)
         assert np.array_equal(got, want), l
+        plane = buf[sum_off:sum_off + hl * pitch * 4].view(np.uint32).reshape(hl, pitch)
+        assert np.array_equal(plane[:, :wl], _sum_plane(ref[l], p)), l
 
 
 def test_config1_translation_pair(ctx):
