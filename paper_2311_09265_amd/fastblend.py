@@ -84,7 +84,7 @@ def load_library(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError("libfastblend.so is not built (%s); run __graft_entry__.build()" % path)
+        raise RuntimeError("libfastblend.so is not built (%s); run python -m paper_2311_09265_amd.build" % path)
     L = ctypes.CDLL(path)
     vp, i32, u32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
     P = ctypes.POINTER(fb_params)
