@@ -48,6 +48,17 @@ def test_accurate_blend_matches_oracle(ctx, N, h, w, M, K, iters, alpha16):
     assert np.abs(out - ref).max() <= TOL
 
 
+@pytest.mark.parametrize("p", [1, 3])
+def test_accurate_blend_other_patch_radii(ctx, p):
+    """3x3 and 7x7 patches: their own bound tables, patch-sum quantisation
+    and unrolled row loops in both passes."""
+    g, s = _video(4, 30, 37, 70 + p)
+    prm = fbm.make_params(p, 2, 2, 31, fbm.FB_ACCURATE_BLEND, 16)
+    out = host(ctx.fb_blend_window(dev(g), dev(s), 1, prm))
+    ref = oracle.blend_window_accurate(g, s, 1, p, 2, 2, 31, 16)
+    assert np.abs(out - ref).max() <= TOL
+
+
 def test_accurate_blend_full_size_frames(ctx):
     """The first 4 frames of the 512x512 blend workload, 3 levels x 6
     iterations, window radius 5 (truncated), alpha = 1."""

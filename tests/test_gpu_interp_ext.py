@@ -49,6 +49,17 @@ def test_interp_ext_matches_oracle(ctx, track, align, alpha16, N, h, w, keys, K,
     assert np.abs(out - ref).max() <= TOL
 
 
+@pytest.mark.parametrize("p", [1, 3])
+def test_interp_ext_other_patch_radii(ctx, p):
+    """Tracking and alignment with 3x3 and 7x7 patches (their own bound
+    tables, patch-sum quantisation and unrolled row loops)."""
+    g, k, ks = _case(7, 26, 31, [0, 3, 6], 40 + p)
+    prm = fbm.make_params(p, 2, 2, 23, fbm.FB_TRACKING | fbm.FB_ALIGN, 16)
+    out = host(ctx.fb_interpolate(dev(g), list(k), dev(ks), prm))
+    ref = oracle.interpolate_ext(g, k, ks, p, 2, 2, 23, 16, track=True, align=True)
+    assert np.abs(out - ref).max() <= TOL
+
+
 def test_interp_ext_full_size(ctx):
     """1024x576 frames, 4 levels x 6 iterations, keys {0, 3}: the two middle
     frames' four coupled fields with tracking and alignment."""

@@ -71,6 +71,24 @@ def test_style_batch_matches_oracle(ctx, p, alpha16):
         assert bad.size == 0, ((h, w, K), len(bad), bad[:3])
 
 
+@pytest.mark.parametrize("p", [2, 4])
+def test_style_batch_degenerate_shapes(ctx, p):
+    """One-row, one-column and tiny frames (every patch clamped, tiles mostly
+    empty) in one batch, with the style loss."""
+    seed, iters = 5, 3
+    cases = []
+    for k, (h, w) in enumerate(((1, 17), (13, 1), (2, 3), (1, 1))):
+        rng = np.random.default_rng(100 + k)
+        g = rng.integers(0, 256, (2, h, w, 3), dtype=np.uint8)
+        s = rng.integers(0, 256, (h, w, 3), dtype=np.uint8)
+        cases.append((g, s, h, w, 1, 11 + k))
+    outs = _run_pairs(ctx, cases, _style_params(p, 1, iters, seed, 16))
+    for (g, s, h, w, K, pid), (nnf, en) in zip(cases, outs):
+        F, E, _ = oracle.patchmatch_style(g[0], g[1], s, p, K, iters, seed, pid, 16)
+        n, e = host(nnf), host(en).astype(np.uint32)
+        assert np.array_equal(n, F) and np.array_equal(e, E), (h, w, p)
+
+
 def test_style_tile_shapes_and_graph_replay_agree(ctx):
     g = _video(2, 48, 72, 5)
     s = _styles(g, 6)
