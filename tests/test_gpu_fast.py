@@ -46,6 +46,15 @@ def test_fast_blend_matches_oracle(ctx, N, h, w, M, K, iters):
     assert np.abs(out - ref).max() <= TOL
 
 
+@pytest.mark.parametrize("p", [1, 3, 4])
+def test_fast_blend_other_patch_radii(ctx, p):
+    """Tables and queries over remaps with 3x3, 7x7 and 9x9 patches."""
+    g, s = _video(6, 28, 35, 50 + p)
+    out = host(ctx.fb_blend_window(dev(g), dev(s), 2, fbm.make_params(p, 2, 2, 17, fbm.FB_FAST_BLEND)))
+    ref = oracle.blend_window_fast(g, s, 2, p, 2, 2, 17)
+    assert np.abs(out - ref).max() <= TOL
+
+
 def test_fast_blend_graph_replay_matches_eager(ctx):
     g, s = _video(12, 32, 48, 3)
     prm = fbm.make_params(2, 2, 2, 5, fbm.FB_FAST_BLEND)

@@ -297,6 +297,17 @@ def test_blend_window_matches_oracle(ctx, N, h, w, M, levels, iters):
     assert np.abs(out.astype(np.float64) - ref).max() <= TOL
 
 
+@pytest.mark.parametrize("p", [1, 3, 4])
+def test_blend_window_other_patch_radii(ctx, p):
+    """The whole balanced blend (pyramids, PatchMatch, remap, window mean)
+    with 3x3, 7x7 and 9x9 patches."""
+    guides, styles = synth.blend_workload(5, 30, 37, seed=0xC0 + p)
+    prm = fbm.make_params(p, 2, 2, 0xFB5EED02)
+    out = host(ctx.fb_blend_window(dev(guides), dev(styles), 2, prm))
+    ref = oracle.blend_window(guides, styles, 2, p, 2, 2, 0xFB5EED02)
+    assert np.abs(out.astype(np.float64) - ref).max() <= TOL
+
+
 @pytest.mark.parametrize("keys", [[0, 4, 8], [3], [2, 5], [0, 1, 2, 3, 4, 5, 6, 7, 8]])
 def test_interpolate_matches_oracle(ctx, keys):
     N, h, w = 9, 36, 52
