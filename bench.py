@@ -496,18 +496,29 @@ def n_pix_iters(h, w, levels, iters):
     return sum(hl * wl for hl, wl in level_sizes(h, w, levels)) * iters
 
 
+# the sources that decide what the iteration kernel does (its code, the
+# shared constants and the pyramid layout it reads)
+ITER_KERNEL_SOURCES = ("patchmatch.hip", "fb_common.h", "pyramid.hip")
+
+
+def iter_kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ITER_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2311_09265_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def iter_kernel_traffic():
     """HBM bytes per launch of the PatchMatch iteration kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
-    import hashlib
+    rocprofv3 counter summary, if it was taken on the current kernel sources."""
     summ = os.path.join(ROOT, "profiles", "pm_iter_counters_blend512.json")
-    src = os.path.join(ROOT, "paper_2311_09265_amd", "csrc", "patchmatch.hip")
     if not os.path.exists(summ):
         return None, "no counter summary"
     with open(summ) as f:
         d = json.load(f)
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if d.get("kernel_source_sha256") != sha:
+    if d.get("kernel_source_sha256") != iter_kernel_sha():
         return None, "counters were taken on another version of the kernel"
     return d["hbm_bytes_per_launch"], d
 

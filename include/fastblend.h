@@ -174,7 +174,7 @@ int64_t fb_autotune_runs(fb_ctx *ctx);
 /* bytes allocated by the caller; it holds every level as 4-byte pixels   */
 /* with a border of p replicated pixels (p = patch radius), each followed  */
 /* by a table of per-block ranges of the (2p+1)^2 patch sums (at most     */
-/* 16 KiB) and a plane of every position's quantised patch sums (4 bytes  */
+/* 4 KiB) and a plane of every position's quantised patch sums (4 bytes  */
 /* per pixel), which let PatchMatch rule candidates out before reading    */
 /* them.                                                                  */
 /* ---------------------------------------------------------------------- */

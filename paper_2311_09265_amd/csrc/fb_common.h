@@ -34,7 +34,7 @@ namespace fb {
 constexpr int kMaxLevels = 16;
 constexpr int kMaxP = 4;
 constexpr int kPitchAlign = 16;  // pixels
-constexpr int kBoundTabBytes = 16384;  // largest bound table of one level
+constexpr int kBoundTabBytes = 4096;   // largest bound table of one level
 constexpr int kBoundTabMinShift = 3;   // smallest bound-table block: 8 x 8 positions
 // Patch-sum plane: each channel's (2p+1)^2 patch sum (at most (2p+1)^2 * 255)
 // shifted right until it fits 10 bits

@@ -42,7 +42,7 @@ def test_pyramid_bytes_layout(lib):
     # level l: (h_l + 2p) rows x pitch 4-byte pixels, pitch = w_l + 2p rounded
     # up to 16, then its bound table of 12-byte entries, one per block of
     # b x b positions with b the smallest power of two >= 8 that keeps the
-    # table within 16 KiB, then its patch-sum plane (h_l rows x pitch 4-byte
+    # table within 4 KiB, then its patch-sum plane (h_l rows x pitch 4-byte
     # words); every part 256-byte aligned
     def expect(h, w, levels, p):
         off = 0
@@ -52,7 +52,7 @@ def test_pyramid_bytes_layout(lib):
             off += (hl + 2 * p) * pitch * 4
             off = -(-off // 256) * 256
             b = 8
-            while -(-hl // b) * -(-wl // b) * 12 > 16384:
+            while -(-hl // b) * -(-wl // b) * 12 > 4096:
                 b *= 2
             off += -(-hl // b) * -(-wl // b) * 12
             off = -(-off // 256) * 256

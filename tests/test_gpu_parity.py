@@ -54,7 +54,7 @@ def _pyramid_layout(h, w, levels, p):
     """Byte layout of a pyramid buffer: per level its padded 4-byte pixels,
     (h_l + 2p) rows of pitch = w_l + 2p rounded up to 16, then its bound table
     (12 bytes per block of b x b positions, b the smallest power of two >= 8
-    keeping the table within 16 KiB), then its patch-sum plane (h_l rows of
+    keeping the table within 4 KiB), then its patch-sum plane (h_l rows of
     pitch 4-byte words), every part 256-byte aligned."""
     out, off = [], 0
     for l in range(levels):
@@ -63,7 +63,7 @@ def _pyramid_layout(h, w, levels, p):
         px_off = off
         off = -(-(off + (hl + 2 * p) * pitch * 4) // 256) * 256
         b = 8
-        while -(-hl // b) * -(-wl // b) * 12 > 16384:
+        while -(-hl // b) * -(-wl // b) * 12 > 4096:
             b *= 2
         tab_off = off
         off = -(-(off + -(-hl // b) * -(-wl // b) * 12) // 256) * 256
