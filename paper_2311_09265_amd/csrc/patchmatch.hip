@@ -642,6 +642,34 @@ k_style_refresh(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int
         if (!changed) return;
     }
     uint32_t rb = 0, g = 0, cnt = 0;  // R and B sums in 16-bit halves; G alone
+    // A wave whose whole staged neighbourhood (its rows with the P-row border)
+    // holds one translation F(u) - u at every in-image entry has
+    // F(v + d) - d = F(v) for every pixel and in-image d: every term is
+    // S(F(v)), gathered once (packed (row << 16) + col differences are equal
+    // exactly when the translations are, sides being below 2^15).  Waves with
+    // pixels outside the image take the general sum.
+    const uint32_t q0 = sf[((int)threadIdx.y + P) * SW + (int)threadIdx.x + P];
+    bool coherent = __ballot(1) == ~0ull;
+    if (coherent) {
+        constexpr int RN = (WROWS + 2 * P) * SW;
+        const int wy0 = (tid >> 6) * WROWS;
+        const uint32_t ref = (uint32_t)__shfl((int)(q0 - (((uint32_t)r << 16) + (uint32_t)c)), 0);
+        bool ok = true;
+#pragma unroll
+        for (int e = tid & 63; e < RN; e += 64) {
+            const int ry = wy0 + e / SW, rx = e - (e / SW) * SW;
+            const int yy = rt - P + ry, xx = ct - P + rx;
+            if (yy >= 0 && yy < h && xx >= 0 && xx < w)
+                ok &= sf[ry * SW + rx] - (((uint32_t)yy << 16) + (uint32_t)xx) == ref;
+        }
+        coherent = __all(ok);
+    }
+    if (coherent) {
+        const uint32_t px = gload<uint32_t>(J.src_sty, 4u * (uint32_t)(((int)(q0 >> 16) + P) * pitch + (int)(q0 & 0xFFFFu) + P));
+        cnt = (uint32_t)((min(P, h - 1 - r) + min(P, r) + 1) * (min(P, w - 1 - c) + min(P, c) + 1));
+        rb = cnt * (px & 0x00FF00FFu);
+        g = cnt * ((px >> 8) & 0xFFu);
+    } else {
 #pragma unroll
     for (int dr = -P; dr <= P; ++dr) {
         if (r + dr < 0 || r + dr >= h) continue;
@@ -656,6 +684,7 @@ k_style_refresh(const PMJob *__restrict__ jobs, int n_jobs, int total_tiles, int
             g += (px >> 8) & 0xFFu;
             ++cnt;
         }
+    }
     }
     const uint32_t vr = (2u * (rb & 0xFFFFu) + cnt) / (2u * cnt);
     const uint32_t vg = (2u * g + cnt) / (2u * cnt);

@@ -90,8 +90,8 @@ k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__
             sf[i] = (yy >= 0 && yy < h && xx >= 0 && xx < w) ? gload<uint32_t>(T.f, 4u * (uint32_t)(yy * w + xx)) : 0u;
         }
         __syncthreads();
-        if (!active) continue;
         if (flt) {
+            if (!active) continue;
             float x0 = 0.f, x1 = 0.f, x2 = 0.f;
 #pragma unroll
             for (int dr = -P; dr <= P; ++dr) {
@@ -117,23 +117,33 @@ k_remap_sum(const RemapFrame *__restrict__ frames, const RemapTerm *__restrict__
         }
         uint32_t rb = 0, g = 0;
         // Where the field is one translation around v (F(v+d) - d = F(v) for
-        // every in-image d; packed, F(v+d) = F(v) + (d_r << 16) + d_c, and a
-        // borrow can never match a field entry since sides are below 2^15),
-        // every term of the sum is S(F(v)): a wave whose pixels all qualify
-        // gathers once per pixel instead of (2p+1)^2 times.
+        // every in-image d), every term of the sum is S(F(v)), so a wave whose
+        // pixels all qualify gathers once per pixel instead of (2p+1)^2 times.
+        // The wave tests its whole staged neighbourhood at once (its rows with
+        // the P-row border): when every in-image entry u there holds the same
+        // translation F(u) - u, every pixel of the wave qualifies.  Packed as
+        // (row << 16) + col, equal translations give equal differences and,
+        // sides being below 2^15, different ones never do.
         const uint32_t q0 = sf[((int)threadIdx.y + P) * SW + (int)threadIdx.x + P];
         bool coherent = true;
+        {
+            constexpr int WR = 64 / kRTW;          // tile rows of one wave
+            constexpr int RN = (WR + 2 * P) * SW;  // its staged neighbourhood
+            const int wy0 = (tid >> 6) * WR;
+            const uint64_t act = __ballot(active);
+            const uint32_t own = q0 - (((uint32_t)r << 16) + (uint32_t)c);
+            const uint32_t ref = (uint32_t)__shfl((int)own, act ? __ffsll((unsigned long long)act) - 1 : 0);
 #pragma unroll
-        for (int dr = -P; dr <= P; ++dr) {
-            if (dr < r0 || dr > r1) continue;
-            const uint32_t *srow = sf + ((int)threadIdx.y + P + dr) * SW + (int)threadIdx.x + P;
-#pragma unroll
-            for (int dc = -P; dc <= P; ++dc) {
-                if (dc < c0 || dc > c1) continue;
-                coherent &= srow[dc] == q0 + ((uint32_t)dr << 16) + (uint32_t)dc;
+            for (int e = tid & 63; e < RN; e += 64) {
+                const int ry = wy0 + e / SW, rx = e - (e / SW) * SW;
+                const int yy = rt - P + ry, xx = ct - P + rx;
+                if (yy >= 0 && yy < h && xx >= 0 && xx < w)
+                    coherent &= sf[ry * SW + rx] - (((uint32_t)yy << 16) + (uint32_t)xx) == ref;
             }
         }
-        if (__all(coherent)) {
+        const bool wave_coherent = __all(coherent);
+        if (!active) continue;
+        if (wave_coherent) {
             const int sr = (int)(q0 >> 16) + P, sc = (int)(q0 & 0xFFFFu) + P;
             const uint32_t px = gload<uint32_t>(sp, 4u * (uint32_t)(sr * pitch + sc));
             rb = (uint32_t)cnt_v * (px & 0x00FF00FFu);
